@@ -1,0 +1,243 @@
+"""CPU oracle for the Pauli-string operator algebra (test infrastructure).
+
+Only the tests, `__graft_entry__.smoke()` and the CPU-baseline leg of
+`bench.py` may import this package.  It wraps `liboracle.so`, a plain C
+implementation (see pauli_oracle.c) that shares no code with the HIP path,
+plus `mlp`, a float64 NumPy reference of the b_n surrogate network.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from workloads import HostOp, n_words
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "pauli_oracle.c")
+
+OR_OK, OR_EINVAL, OR_ENOMEM, OR_BREAKDOWN = 0, 1, 2, 4
+F64, F32K = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-fno-fast-math", "-Wall",
+                               "-o", tmp, _SRC, "-lm"], cwd=_HERE)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _OrOp(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("x", ctypes.POINTER(ctypes.c_uint64)), ("z", ctypes.POINTER(ctypes.c_uint64)),
+                ("re", ctypes.POINTER(ctypes.c_double)), ("im", ctypes.POINTER(ctypes.c_double))]
+
+
+class _OrTrunc(ctypes.Structure):
+    _fields_ = [("max_len", ctypes.c_int32), ("coef_eps", ctypes.c_double),
+                ("max_strings", ctypes.c_int64), ("keep", ctypes.POINTER(_OrOp))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or \
+                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER
+        L.or_free.argtypes = [P(_OrOp)]
+        L.or_string_product.argtypes = [ctypes.c_int] + [P(ctypes.c_uint64)] * 6 + [P(ctypes.c_int)]
+        L.or_canonicalize.argtypes = [P(_OrOp), P(_OrOp)]
+        L.or_commutator.argtypes = [P(_OrOp), P(_OrOp), ctypes.c_int, P(_OrOp)]
+        L.or_product.argtypes = [P(_OrOp), P(_OrOp), P(_OrOp)]
+        L.or_add.argtypes = [P(_OrOp), ctypes.c_double, ctypes.c_double, P(_OrOp),
+                             ctypes.c_double, ctypes.c_double, P(_OrOp)]
+        L.or_truncate.argtypes = [P(_OrOp), P(_OrTrunc), P(_OrOp)]
+        L.or_divide.argtypes = [P(_OrOp), ctypes.c_double, P(_OrOp)]
+        L.or_norm2.argtypes = [P(_OrOp)]
+        L.or_norm2.restype = ctypes.c_double
+        L.or_inner.argtypes = [P(_OrOp), P(_OrOp), P(ctypes.c_double), P(ctypes.c_double)]
+        L.or_exact_sum.argtypes = [P(ctypes.c_double), ctypes.c_int64]
+        L.or_exact_sum.restype = ctypes.c_double
+        L.or_lanczos_step.argtypes = [P(_OrOp), P(_OrOp), P(_OrOp), ctypes.c_double,
+                                      P(_OrTrunc), ctypes.c_int, P(_OrOp), P(ctypes.c_double)]
+        L.or_rk4_step.argtypes = [P(_OrOp), P(_OrOp), ctypes.c_double, P(_OrTrunc), P(_OrOp)]
+        _lib = L
+    return _lib
+
+
+class _Marshalled:
+    """Keeps the numpy buffers of an or_op alive while C reads them."""
+
+    def __init__(self, op: HostOp):
+        n = op.n
+        x = np.zeros((max(n, 1), 2), np.uint64)
+        z = np.zeros((max(n, 1), 2), np.uint64)
+        W = op.W
+        x[:n, :W] = op.x
+        z[:n, :W] = op.z
+        re = np.ascontiguousarray(op.coef.real if n else np.zeros(1))
+        im = np.ascontiguousarray(op.coef.imag if n else np.zeros(1))
+        self._keep = (x, z, re, im)
+        P = ctypes.POINTER
+        self.s = _OrOp(op.n_qubits, n, x.ctypes.data_as(P(ctypes.c_uint64)),
+                       z.ctypes.data_as(P(ctypes.c_uint64)),
+                       re.ctypes.data_as(P(ctypes.c_double)),
+                       im.ctypes.data_as(P(ctypes.c_double)))
+
+
+def _take(out: _OrOp, n_qubits: int) -> HostOp:
+    n = out.n
+    W = n_words(n_qubits)
+    if n > 0:
+        x = np.ctypeslib.as_array(out.x, shape=(n, 2))[:, :W].copy()
+        z = np.ctypeslib.as_array(out.z, shape=(n, 2))[:, :W].copy()
+        re = np.ctypeslib.as_array(out.re, shape=(n,)).copy()
+        im = np.ctypeslib.as_array(out.im, shape=(n,)).copy()
+    else:
+        x = np.zeros((0, W), np.uint64)
+        z = np.zeros((0, W), np.uint64)
+        re = im = np.zeros(0)
+    lib().or_free(ctypes.byref(out))
+    return HostOp(n_qubits, x, z, re + 1j * im)
+
+
+def _check(rc):
+    if rc not in (OR_OK, OR_BREAKDOWN):
+        raise RuntimeError(f"oracle error {rc}")
+    return rc
+
+
+class Trunc:
+    def __init__(self, max_len=0, coef_eps=0.0, max_strings=0, keep: HostOp | None = None):
+        self.max_len, self.coef_eps, self.max_strings, self.keep = \
+            int(max_len), float(coef_eps), int(max_strings), keep
+
+    def marshal(self):
+        km = _Marshalled(self.keep) if self.keep is not None else None
+        kp = ctypes.pointer(km.s) if km is not None else ctypes.POINTER(_OrOp)()
+        return km, _OrTrunc(self.max_len, self.coef_eps, self.max_strings, kp)
+
+
+NO_TRUNC = Trunc()
+
+
+def string_product(n_qubits, a_key, b_key):
+    """(c_key, k) with P_a P_b = i^k P_c; keys are (x words..., z words...)."""
+    W = n_words(n_qubits)
+    arr = lambda v: (ctypes.c_uint64 * 2)(*(list(v) + [0] * (2 - len(v))))
+    ax, az = arr(a_key[:W]), arr(a_key[W:])
+    bx, bz = arr(b_key[:W]), arr(b_key[W:])
+    cx, cz = (ctypes.c_uint64 * 2)(), (ctypes.c_uint64 * 2)()
+    k = ctypes.c_int()
+    lib().or_string_product(n_qubits, ax, az, bx, bz, cx, cz, ctypes.byref(k))
+    return tuple(cx[:W]) + tuple(cz[:W]), k.value
+
+
+def canonicalize(op: HostOp) -> HostOp:
+    a, out = _Marshalled(op), _OrOp()
+    _check(lib().or_canonicalize(ctypes.byref(a.s), ctypes.byref(out)))
+    return _take(out, op.n_qubits)
+
+
+def commutator(H: HostOp, O: HostOp, prec: int = F64) -> HostOp:
+    h, o, out = _Marshalled(H), _Marshalled(O), _OrOp()
+    _check(lib().or_commutator(ctypes.byref(h.s), ctypes.byref(o.s), prec, ctypes.byref(out)))
+    return _take(out, O.n_qubits)
+
+
+def product(A: HostOp, B: HostOp) -> HostOp:
+    a, b, out = _Marshalled(A), _Marshalled(B), _OrOp()
+    _check(lib().or_product(ctypes.byref(a.s), ctypes.byref(b.s), ctypes.byref(out)))
+    return _take(out, A.n_qubits)
+
+
+def add(A: HostOp, alpha: complex, B: HostOp, beta: complex) -> HostOp:
+    a, b, out = _Marshalled(A), _Marshalled(B), _OrOp()
+    alpha, beta = complex(alpha), complex(beta)
+    _check(lib().or_add(ctypes.byref(a.s), alpha.real, alpha.imag, ctypes.byref(b.s),
+                        beta.real, beta.imag, ctypes.byref(out)))
+    return _take(out, A.n_qubits)
+
+
+def truncate(O: HostOp, t: Trunc) -> HostOp:
+    o, out = _Marshalled(O), _OrOp()
+    km, ts = t.marshal()
+    _check(lib().or_truncate(ctypes.byref(o.s), ctypes.byref(ts), ctypes.byref(out)))
+    del km
+    return _take(out, O.n_qubits)
+
+
+def divide(O: HostOp, b: float) -> HostOp:
+    o, out = _Marshalled(O), _OrOp()
+    _check(lib().or_divide(ctypes.byref(o.s), float(b), ctypes.byref(out)))
+    return _take(out, O.n_qubits)
+
+
+def norm2(O: HostOp) -> float:
+    o = _Marshalled(O)
+    return lib().or_norm2(ctypes.byref(o.s))
+
+
+def inner(A: HostOp, B: HostOp) -> complex:
+    a, b = _Marshalled(A), _Marshalled(B)
+    re, im = ctypes.c_double(), ctypes.c_double()
+    lib().or_inner(ctypes.byref(a.s), ctypes.byref(b.s), ctypes.byref(re), ctypes.byref(im))
+    return complex(re.value, im.value)
+
+
+def exact_sum(values) -> float:
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    return lib().or_exact_sum(v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), v.size)
+
+
+def lanczos_step(H: HostOp, O_prev: HostOp | None, O_cur: HostOp, b_prev: float,
+                 t: Trunc = NO_TRUNC, prec: int = F64):
+    """Returns (O_next, b_n, breakdown)."""
+    h, c = _Marshalled(H), _Marshalled(O_cur)
+    p = _Marshalled(O_prev) if O_prev is not None else None
+    pp = ctypes.byref(p.s) if p is not None else ctypes.POINTER(_OrOp)()
+    km, ts = t.marshal()
+    out, b = _OrOp(), ctypes.c_double()
+    rc = _check(lib().or_lanczos_step(ctypes.byref(h.s), pp, ctypes.byref(c.s), float(b_prev),
+                                      ctypes.byref(ts), prec, ctypes.byref(out), ctypes.byref(b)))
+    del km
+    return _take(out, O_cur.n_qubits), b.value, rc == OR_BREAKDOWN
+
+
+def lanczos(H: HostOp, O0: HostOp, steps: int, t: Trunc = NO_TRUNC, prec: int = F64,
+            keep_basis: bool = False):
+    """b_1..b_steps (stops early at breakdown) and, optionally, the basis."""
+    bs, basis = [], [O0]
+    prev, cur, b_prev = None, O0, 0.0
+    for _ in range(steps):
+        nxt, b, broke = lanczos_step(H, prev, cur, b_prev, t, prec)
+        bs.append(b)
+        if broke:
+            break
+        prev, cur, b_prev = cur, nxt, b
+        if keep_basis:
+            basis.append(cur)
+    return (bs, basis) if keep_basis else bs
+
+
+def rk4_step(H: HostOp, O: HostOp, dt: float, t: Trunc = NO_TRUNC) -> HostOp:
+    h, o = _Marshalled(H), _Marshalled(O)
+    km, ts = t.marshal()
+    out = _OrOp()
+    _check(lib().or_rk4_step(ctypes.byref(h.s), ctypes.byref(o.s), float(dt), ctypes.byref(ts),
+                             ctypes.byref(out)))
+    del km
+    return _take(out, O.n_qubits)

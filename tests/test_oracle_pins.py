@@ -1,0 +1,391 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle:
+textbook Pauli matrices, dense 2^N matrices, exactly rounded sums, the paper's
+printed worked example, closed forms of Lanczos coefficients and of one
+Runge-Kutta step.  CPU only.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads as wl
+
+SIGMA = {
+    (0, 0): np.eye(2, dtype=complex),
+    (1, 0): np.array([[0, 1], [1, 0]], dtype=complex),
+    (0, 1): np.array([[1, 0], [0, -1]], dtype=complex),
+    (1, 1): np.array([[0, -1j], [1j, 0]], dtype=complex),
+}
+
+
+def site_bits(key, W, j):
+    w, b = divmod(int(j), 64)
+    return ((key[w] >> b) & 1, (key[W + w] >> b) & 1)
+
+
+def dense_string(n, key):
+    W = wl.n_words(n)
+    m = np.array([[1.0 + 0j]])
+    for j in range(n):  # site 1 is the leftmost Kronecker factor
+        m = np.kron(m, SIGMA[site_bits(key, W, j)])
+    return m
+
+
+def dense(op: wl.HostOp):
+    d = 2 ** op.n_qubits
+    m = np.zeros((d, d), complex)
+    for k, c in zip(op.keys(), op.coef):
+        m += c * dense_string(op.n_qubits, k)
+    return m
+
+
+def sparse_string(n, key):
+    W = wl.n_words(n)
+    m = sp.identity(1, dtype=complex, format="csr")
+    for j in range(n):
+        m = sp.kron(m, sp.csr_matrix(SIGMA[site_bits(key, W, j)]), format="csr")
+    return m
+
+
+def sparse_op(op):
+    d = 2 ** op.n_qubits
+    m = sp.csr_matrix((d, d), dtype=complex)
+    for k, c in zip(op.keys(), op.coef):
+        m = m + c * sparse_string(op.n_qubits, k)
+    return m
+
+
+# ---------------------------------------------------------------------------
+# String algebra
+# ---------------------------------------------------------------------------
+
+def test_single_site_table_matches_pauli_matrices():
+    for a in SIGMA:
+        for b in SIGMA:
+            ka, kb = (a[0], a[1]), (b[0], b[1])
+            c, k = oracle.string_product(1, ka, kb)
+            lhs = SIGMA[a] @ SIGMA[b]
+            rhs = (1j ** k) * SIGMA[(c[0], c[1])]
+            assert np.allclose(lhs, rhs, atol=0), (a, b, c, k)
+
+
+def test_named_products():
+    X, Y, Z = (1, 0), (1, 1), (0, 1)
+    for a, b, c, k in [(X, Y, Z, 1), (Y, Z, X, 1), (Z, X, Y, 1),
+                       (Y, X, Z, 3), (Z, Y, X, 3), (X, Z, Y, 3)]:
+        assert oracle.string_product(1, a, b) == (c, k)
+
+
+@pytest.mark.parametrize("n", [3, 5, 70])
+def test_string_products_vs_kron(n):
+    rng = np.random.default_rng(n)
+    A = wl.random_operator(n, 12, seed=n, density=0.6)
+    B = wl.random_operator(n, 12, seed=n + 100, density=0.6)
+    for ka in A.keys():
+        for kb in B.keys():
+            kc, k = oracle.string_product(n, ka, kb)
+            if n <= 5:
+                assert np.allclose(dense_string(n, ka) @ dense_string(n, kb),
+                                   (1j ** k) * dense_string(n, kc), atol=0)
+            else:  # site-wise check on wide strings: the phase multiplies over sites
+                W = wl.n_words(n)
+                ph = 0
+                for j in rng.permutation(n):
+                    a, b = site_bits(ka, W, j), site_bits(kb, W, j)
+                    c1, k1 = oracle.string_product(1, a, b)
+                    assert site_bits(kc, W, j) == c1
+                    ph += k1
+                assert ph % 4 == k
+
+
+# ---------------------------------------------------------------------------
+# Operator algebra vs dense matrices
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,seed", [(2, 1), (4, 2), (5, 3), (6, 4)])
+def test_commutator_vs_dense(n, seed):
+    H = wl.random_operator(n, 7, seed=seed, density=0.5)
+    O = wl.random_operator(n, 9, seed=seed + 50, density=0.7)
+    C = oracle.commutator(H, O)
+    dH, dO = dense(H), dense(O)
+    assert np.abs(dense(C) - (dH @ dO - dO @ dH)).max() < 1e-12
+    assert all(abs(c) > 0 for c in C.coef)
+    assert len(set(C.keys())) == C.n
+
+
+@pytest.mark.parametrize("n,seed", [(3, 5), (5, 6)])
+def test_product_vs_dense(n, seed):
+    A = wl.random_operator(n, 6, seed=seed)
+    B = wl.random_operator(n, 5, seed=seed + 1)
+    assert np.abs(dense(oracle.product(A, B)) - dense(A) @ dense(B)).max() < 1e-12
+
+
+def test_add_norm_inner_vs_dense():
+    n = 5
+    A = wl.random_operator(n, 20, seed=11)
+    B = wl.random_operator(n, 25, seed=12)
+    B.coef[:5] = A.coef[:5]
+    B.x[:5], B.z[:5] = A.x[:5], A.z[:5]  # force common keys
+    B = oracle.canonicalize(B)
+    al, be = 0.7 - 0.2j, -1.3 + 0.5j
+    S = oracle.add(A, al, B, be)
+    assert np.abs(dense(S) - (al * dense(A) + be * dense(B))).max() < 1e-12
+    d = 2 ** n
+    dA, dB = dense(A), dense(B)
+    assert abs(oracle.norm2(A) - np.trace(dA.conj().T @ dA).real / d) < 1e-12
+    assert abs(oracle.inner(A, B) - np.trace(dA.conj().T @ dB) / d) < 1e-12
+
+
+def test_add_exact_cancellation_drops_string():
+    n = 4
+    A = wl.random_operator(n, 10, seed=3)
+    S = oracle.add(A, 1.0, A, -1.0)
+    assert S.n == 0
+
+
+def test_canonicalize_sums_duplicates():
+    n = 4
+    A = wl.random_operator(n, 10, seed=21)
+    dup = wl.HostOp(n, np.concatenate([A.x, A.x[:4]]), np.concatenate([A.z, A.z[:4]]),
+                    np.concatenate([A.coef, A.coef[:4] * 2]))
+    C = oracle.canonicalize(dup)
+    assert C.n == A.n
+    assert np.abs(dense(C) - dense(dup)).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Exact summation (pinned to Python's correctly rounded math.fsum)
+# ---------------------------------------------------------------------------
+
+def test_exact_sum_matches_fsum():
+    rng = np.random.default_rng(0)
+    for trial in range(60):
+        n = int(rng.integers(1, 400))
+        scale = 10.0 ** rng.integers(-300, 300, size=n)
+        v = rng.standard_normal(n) * scale
+        if trial % 3 == 0:  # heavy cancellation
+            v = np.concatenate([v, -v[: n // 2], rng.standard_normal(3) * 1e-200])
+        if trial % 5 == 0:
+            v = np.concatenate([v, [5e-324, -5e-324, 2.2250738585072014e-308]])
+        assert oracle.exact_sum(v) == math.fsum(v.tolist())
+    assert oracle.exact_sum([1.0, 2.0 ** -53, 2.0 ** -53]) == math.fsum([1.0, 2.0 ** -53, 2.0 ** -53])
+    assert oracle.exact_sum([]) == 0.0
+
+
+def test_norm2_is_exactly_rounded_sum_of_weights():
+    A = wl.random_operator(6, 300, seed=8)
+    m2 = [c.real * c.real + c.imag * c.imag for c in A.coef]
+    assert oracle.norm2(A) == math.fsum(m2)
+
+
+# ---------------------------------------------------------------------------
+# Lanczos: the paper's worked example, closed forms, dense recursion
+# ---------------------------------------------------------------------------
+
+def load_worked_example():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "worked_example_lanczos.txt")
+    steps = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        s, re, im, text = line.split()
+        steps.setdefault(int(s), []).append((complex(float(re), float(im)), text))
+    return steps
+
+
+def test_worked_example_verbatim():
+    golden = load_worked_example()
+    n = 10
+    H = wl.xx_plus_zz_defect(n, 4)
+    O0 = wl.from_terms(n, [(1.0, [("X", 1)])])
+    bs, basis = oracle.lanczos(H, O0, 7, oracle.Trunc(coef_eps=1e-10), keep_basis=True)
+    for step in range(1, 8):
+        got = {wl.text_of_key(n, k): c for k, c in zip(basis[step - 1].keys(),
+                                                       basis[step - 1].coef)}
+        want = dict((t, c) for c, t in golden[step])
+        assert set(got) == set(want), step
+        for t in want:
+            assert abs(got[t] - want[t]) < 1e-10, (step, t)
+    # b_n of that run: 2, 2, 2, 2 sqrt2, 2 sqrt3, 2 sqrt(25/6)
+    expect = [2, 2, 2, 2 * math.sqrt(2), 2 * math.sqrt(3), 2 * math.sqrt(25 / 6)]
+    assert np.allclose(bs[:6], expect, rtol=1e-14)
+
+
+def test_config_small_closed_form_and_dense():
+    H, O0, steps = wl.config_lanczos_small()
+    bs, basis = oracle.lanczos(H, O0, steps, keep_basis=True)
+    assert bs[0] == pytest.approx(2.1, rel=1e-15)          # [H,Z1] = 2*1.05*(-i)Y1
+    assert bs[1] == pytest.approx(math.sqrt(5), rel=1e-15)  # O'_2 = -2 X1 Z2 - X1 (up to phase)
+    # dense Liouvillian recursion at N = 12 (sparse H, dense operators)
+    n = 12
+    Hs = sparse_op(H)
+    d = 2 ** n
+    prev = None
+    cur = sparse_op(O0).toarray()
+    b_prev = 0.0
+    dense_b = []
+    for _ in range(steps):
+        A = np.asarray(Hs @ cur) - np.asarray(cur @ Hs)
+        if prev is not None:
+            A = A - b_prev * prev
+        b = math.sqrt(np.vdot(A, A).real / d)
+        dense_b.append(b)
+        prev, cur, b_prev = cur, A / b, b
+    assert np.allclose(bs, dense_b, rtol=1e-13, atol=0)
+    # Krylov basis orthonormal; coefficients alternate real / imaginary
+    for m in range(len(basis)):
+        for k in range(m, min(len(basis), m + 3)):
+            ip = oracle.inner(basis[m], basis[k])
+            assert abs(ip - (1.0 if m == k else 0.0)) < 1e-12
+    for m, B in enumerate(basis):
+        if m % 2 == 0:
+            assert np.all(B.coef.imag == 0)
+        else:
+            assert np.all(B.coef.real == 0)
+
+
+def test_dense_lanczos_random_small():
+    n = 5
+    H = wl.random_operator(n, 10, seed=31, real=True)
+    O0 = wl.from_terms(n, [(1.0, [("Z", 2)])])
+    bs = oracle.lanczos(H, O0, 8)
+    dH = dense(H)
+    d = 2 ** n
+    prev, cur, b_prev, ref = None, dense(O0), 0.0, []
+    for _ in range(len(bs)):
+        A = dH @ cur - cur @ dH
+        if prev is not None:
+            A = A - b_prev * prev
+        b = math.sqrt(np.vdot(A, A).real / d)
+        ref.append(b)
+        prev, cur, b_prev = cur, A / b, b
+    assert np.allclose(bs, ref, rtol=1e-11)
+
+
+@pytest.mark.parametrize("n", [6, 70])
+def test_majorana_chain_closed_form(n):
+    J, h = 1.0, 0.7
+    H = wl.majorana_chain(n, J, h)
+    O0 = wl.from_terms(n, [(1.0, [("X", 1)])])
+    bs, basis = oracle.lanczos(H, O0, 2 * n + 1, keep_basis=True)
+    want = [2 * h if k % 2 == 0 else 2 * J for k in range(2 * n - 1)]
+    assert len(bs) == 2 * n  # breakdown reported at step 2N
+    assert np.allclose(bs[:-1], want, rtol=1e-14)
+    assert bs[-1] < 1e-12
+    assert all(B.n == 1 for B in basis)
+    # the last basis string of the chain is Y...Y X or Y...Y Z covering all N sites
+    last = wl.text_of_key(n, basis[-1].keys()[0])
+    assert "1" not in last
+
+
+def test_conserved_operator_breaks_down():
+    H, _ = wl.xxz_random_field(8, 0.5, 0.3, 4)
+    O0 = wl.single_site_sum(8, "Z", 1 / math.sqrt(8))
+    nxt, b, broke = oracle.lanczos_step(H, None, O0, 0.0)
+    assert b == 0.0 and broke and nxt.n == 0
+    O0x = wl.single_site_sum(8, "X", 1 / math.sqrt(8))
+    _, b, broke = oracle.lanczos_step(H, None, O0x, 0.0)
+    assert b > 0.5 and not broke
+
+
+def test_krylov_dimension_single_site():
+    # D = 2: n <= D^2 - D + 1 = 3 ... H = hX, O = Z closes after one step
+    h = 0.8
+    H = wl.from_terms(1, [(h, [("X", 1)])])
+    O0 = wl.from_terms(1, [(1.0, [("Z", 1)])])
+    bs = oracle.lanczos(H, O0, 5)
+    assert bs[0] == pytest.approx(2 * h, rel=1e-15)
+    assert len(bs) == 2 and bs[1] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Runge-Kutta
+# ---------------------------------------------------------------------------
+
+def test_rk4_step_taylor_closed_form_tfim():
+    H, O0 = wl.config_rk4_tfim()
+    dt = 0.02
+    O1 = oracle.rk4_step(H, O0, dt)
+    S = oracle.inner(O0, O1)
+    b1, b2 = 4.0, 4.0  # 2 hx and 2 J sqrt(4): closed forms for an interior site
+    want = 1 - b1 ** 2 * dt ** 2 / 2 + b1 ** 2 * (b1 ** 2 + b2 ** 2) * dt ** 4 / 24
+    assert abs(S.real - want) < 1e-14 and abs(S.imag) < 1e-15
+    bs = oracle.lanczos(H, O0, 2)
+    assert np.allclose(bs, [b1, b2], rtol=1e-15)
+    assert O1.n == 50
+
+
+def dense_rk4(dH, dO, dt):
+    L = lambda M: 1j * (dH @ M - M @ dH)
+    k1 = L(dO)
+    k2 = L(dO + dt / 2 * k1)
+    k3 = L(dO + dt / 2 * k2)
+    k4 = L(dO + dt * k3)
+    return dO + dt / 6 * k1 + dt / 3 * k2 + dt / 3 * k3 + dt / 6 * k4
+
+
+def test_rk4_vs_dense_and_norm():
+    n = 4
+    H = wl.random_operator(n, 8, seed=41, real=True)
+    O = wl.random_operator(n, 6, seed=42, real=True)
+    dt = 0.05
+    dH = dense(H)
+    dO = dense(O)
+    cur = O
+    for _ in range(3):
+        cur = oracle.rk4_step(H, cur, dt)
+        dO = dense_rk4(dH, dO, dt)
+    assert np.abs(dense(cur) - dO).max() < 1e-12
+    # exact evolution conserves the Frobenius norm; RK4 only to O(dt^5) per step
+    n0 = oracle.norm2(O)
+    assert abs(oracle.norm2(cur) - n0) < 1e-4 * n0
+    d = 2 ** n
+    assert abs(oracle.norm2(cur) - np.vdot(dO, dO).real / d) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Truncation: defining properties of top-M with keep set and filters
+# ---------------------------------------------------------------------------
+
+def key_order(k, W):
+    return tuple(reversed(k[:W])) + tuple(reversed(k[W:]))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_truncate_properties(seed):
+    rng = np.random.default_rng(seed)
+    n = 20
+    O = wl.random_operator(n, 300, seed=seed + 60, density=0.3)
+    # many exact ties: quantise magnitudes
+    if seed % 2 == 0:
+        O.coef = np.round(O.coef * 2) / 2
+        O.coef[O.coef == 0] = 0.5
+    keep = wl.HostOp(n, O.x[:3], O.z[:3], O.coef[:3])
+    M = int(rng.integers(1, 250))
+    L = int(rng.integers(3, 10))
+    eps = 0.3 if seed % 3 == 0 else 0.0
+    t = oracle.Trunc(max_len=L, coef_eps=eps, max_strings=M, keep=keep)
+    out = oracle.truncate(O, t)
+    W = 1
+    length = lambda k: bin(k[0] | k[1]).count("1")
+    m2 = lambda c: c.real * c.real + c.imag * c.imag
+    surv = {k: c for k, c in zip(O.keys(), O.coef)
+            if length(k) <= L and (eps == 0 or m2(c) >= eps * eps) and c != 0}
+    kept = out.as_dict()
+    assert set(kept) <= set(surv)
+    for k in kept:
+        assert kept[k] == surv[k]
+    keep_keys = set(keep.keys()) & set(surv)
+    assert keep_keys <= set(kept)
+    assert len(kept) == len(keep_keys) + min(max(0, M - len(keep_keys)),
+                                             len(surv) - len(keep_keys))
+    dropped = [k for k in surv if k not in kept]
+    for kk in kept:
+        if kk in keep_keys:
+            continue
+        for kd in dropped:
+            a, b = m2(kept[kk]), m2(surv[kd])
+            assert a > b or (a == b and key_order(kk, W) < key_order(kd, W))
