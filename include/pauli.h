@@ -1,0 +1,172 @@
+/* pauli.h - C ABI of the MI355X (gfx950) Pauli-string operator engine.
+ *
+ * An operator is a sum of Pauli strings, O = sum_k c_k P(x_k, z_k), each
+ * string encoded in binary as two bit-masks (Methods, "Pauli strings": the
+ * encoding of strings as pairs of integers whose product is an XOR of the
+ * masks with a phase from popcounts).  Site j (1-based) is bit (j-1) % 64 of
+ * word (j-1) / 64; I=(x,z)=(0,0), X=(1,0), Z=(0,1), Y=(1,1), and P(x,z) is the
+ * Hermitian tensor product of those Paulis (so the paper's tau_11 = iY is
+ * represented as i * Y).
+ *
+ * Memory and ownership
+ *   - Every pointer inside pauli_op and pauli_ws is a DEVICE pointer owned by
+ *     the caller.  The library never allocates or frees device memory, keeps
+ *     no pointer after a call returns and keeps no state between calls
+ *     (except the optional kernel-timing log, see pauli_profile_*).
+ *   - x and z are word-major: word w of string k is x[w * capacity + k].
+ *     coef holds `capacity` interleaved (re, im) pairs: double for
+ *     PAULI_C128, float for PAULI_C64K.
+ *   - Inputs are read-only.  An output must not alias any input.
+ *   - Calls enqueue work on `stream` (a hipStream_t) and synchronise it
+ *     before returning, so sizes and scalars are valid on return.
+ *
+ * Canonical form
+ *   Every operator the library writes is canonical: unique strings, no exact
+ *   zero coefficient, sorted in the library's fixed order (ascending value of
+ *   a bijective mix of the key words).  Operators built elsewhere are brought
+ *   to this form with pauli_canonicalize.  Inputs of pauli_commutator,
+ *   pauli_add, pauli_truncate and the step functions need unique strings but
+ *   may come in any order; the keep set of a pauli_trunc and the second
+ *   argument of pauli_inner must be canonical.
+ *
+ * Summation order (determinism)
+ *   Each output coefficient of a commutator sums its contributions in
+ *   ascending index of the H string that produced it; a linear combination
+ *   alpha A + beta B is fl(fl(alpha a) + fl(beta b)); norms are sums of
+ *   fl(fl(re^2) + fl(im^2)) accumulated in double-double and rounded once.
+ *   Results are bitwise reproducible run to run.
+ *
+ * Errors
+ *   Every function returns a pauli_status.  PAULI_ECAPACITY: an output's
+ *   capacity is too small; its `size` field receives the required number of
+ *   strings and no output is valid.  PAULI_EWORKSPACE: the workspace is too
+ *   small; ws->required receives a sufficient size in bytes (retry with at
+ *   least that much; data-dependent sizes may need one more retry).
+ *   PAULI_BREAKDOWN: a Lanczos step produced b_n <= 1e-13 max(1, b_{n-1}).
+ *   PAULI_EHIP: a HIP runtime error (text from pauli_last_error()).
+ */
+#ifndef PAULI_H
+#define PAULI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PAULI_OK = 0,
+  PAULI_EINVAL = 1,
+  PAULI_ECAPACITY = 2,
+  PAULI_EWORKSPACE = 3,
+  PAULI_BREAKDOWN = 4,
+  PAULI_EHIP = 5,
+  PAULI_EINTERNAL = 6
+} pauli_status;
+
+typedef enum {
+  PAULI_C128 = 0, /* complex double coefficients */
+  PAULI_C64K = 1  /* complex float coefficients; products in FP32 with
+                     Kahan-compensated sums, recombination, norms and b_n in
+                     FP64 (precision split of the Lanczos recursion) */
+} pauli_dtype;
+
+typedef struct pauli_op {
+  int32_t n_qubits;  /* 1..128 */
+  int32_t dtype;     /* pauli_dtype */
+  int64_t size;      /* strings in use; written by the library on outputs */
+  int64_t capacity;  /* rows allocated for x, z and coef */
+  uint64_t *x;       /* device, [W][capacity], W = (n_qubits + 63) / 64 */
+  uint64_t *z;       /* device, [W][capacity] */
+  void *coef;        /* device, [capacity] (re, im) */
+} pauli_op;
+
+/* Truncation (Methods: keeping only the strings of largest weight; discarding
+ * long strings; the cutoff of the Lanczos listing), applied in this order:
+ *   1. drop strings with popcount(x | z) > max_len        (max_len <= 0: off)
+ *   2. drop strings with |c| < coef_eps, compared as
+ *      fl(fl(re^2)+fl(im^2)) < fl(coef_eps^2); exact zeros always dropped
+ *   3. keep every surviving string of `keep`, then the
+ *      max(0, max_strings - kept) largest |c| among the rest, ties broken by
+ *      the smaller key (x words from high to low, then z words from high to
+ *      low, unsigned)                                      (max_strings <= 0: off)
+ */
+typedef struct pauli_trunc {
+  int32_t max_len;
+  double coef_eps;
+  int64_t max_strings;
+  const pauli_op *keep; /* nullable; canonical; at most 65536 strings */
+} pauli_trunc;
+
+typedef struct pauli_ws {
+  void *ptr;       /* device scratch, 256-byte aligned */
+  size_t bytes;
+  size_t required; /* written on PAULI_EWORKSPACE */
+} pauli_ws;
+
+/* out = [H, O] = sum_{a,b} h_a c_b [P_a, P_b] (Alg. 1 in commutator form with
+ * the commutator phase of eq. eps_com), then truncated by t (nullable: only
+ * exact zeros are dropped).  H must be PAULI_C128; O and out share a dtype. */
+int pauli_commutator(const pauli_op *H, const pauli_op *O, const pauli_trunc *t,
+                     pauli_op *out, pauli_ws *ws, void *stream);
+
+/* out = trunc(alpha A + beta B) over the union of strings (the operator sum
+ * used by both the Lanczos recursion and the Runge-Kutta stages). */
+int pauli_add(const pauli_op *A, double alpha_re, double alpha_im, const pauli_op *B,
+              double beta_re, double beta_im, const pauli_trunc *t, pauli_op *out,
+              pauli_ws *ws, void *stream);
+
+/* out = trunc(in) (trim / cutoff of the Methods section). */
+int pauli_truncate(const pauli_op *in, const pauli_trunc *t, pauli_op *out, pauli_ws *ws,
+                   void *stream);
+
+/* out = canonical form of in: duplicate strings summed in input order, exact
+ * zeros dropped, library order.  Duplicates allowed; up to 2^28 strings. */
+int pauli_canonicalize(const pauli_op *in, pauli_op *out, pauli_ws *ws, void *stream);
+
+/* One classical Runge-Kutta step of the Heisenberg equation dO/dt = i[H, O]
+ * (Heisenberg time evolution section):
+ *   k1 = i[H,O];  S2 = trunc(O + fl(dt/2) k1);  k2 = i[H,S2];
+ *   S3 = trunc(O + fl(dt/2) k2);  k3 = i[H,S3];  S4 = trunc(O + dt k3);
+ *   k4 = i[H,S4];  out = trunc((((O + c1 k1) + c2 k2) + c2 k3) + c1 k4),
+ * c1 = fl(dt/6), c2 = fl(dt/3).  PAULI_C128 only. */
+int pauli_rk4_step(const pauli_op *H, const pauli_op *O, double dt, const pauli_trunc *t,
+                   pauli_op *out, pauli_ws *ws, void *stream);
+
+/* One step of the Liouvillian Lanczos recursion (Krylov section, L = [H, .]):
+ *   O'_n = [H, O_{n-1}] - b_{n-1} O_{n-2}    (O_prev = NULL at n = 1)
+ *   b_n  = ||O'_n|| = sqrt(sum |c|^2)         (norm of the untruncated O'_n)
+ *   O_n  = trunc(O'_n / b_n)                 (IEEE division per component)
+ * *b_out (host) receives b_n.  On PAULI_BREAKDOWN O_next->size = 0.
+ * flags: must be 0.  For PAULI_C64K operators the commutator runs in FP32 with
+ * compensated sums and everything after it in FP64 (O_n rounded to FP32). */
+int pauli_lanczos_step(const pauli_op *H, const pauli_op *O_prev, const pauli_op *O_cur,
+                       double b_prev, const pauli_trunc *t, uint32_t flags,
+                       pauli_op *O_next, double *b_out, pauli_ws *ws, void *stream);
+
+/* *out (host) = sum_k fl(fl(re_k^2) + fl(im_k^2)) (the squared Frobenius norm
+ * Tr(A^dagger A)/2^N), double-double accumulation rounded once. */
+int pauli_norm2(const pauli_op *A, double *out, pauli_ws *ws, void *stream);
+
+/* out[0] + i out[1] (host) = <A, B> = Tr(A^dagger B)/2^N = sum over common
+ * strings of conj(a) b.  B must be canonical. */
+int pauli_inner(const pauli_op *A, const pauli_op *B, double out[2], pauli_ws *ws,
+                void *stream);
+
+/* Static description of the error code. */
+const char *pauli_strerror(int status);
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char *pauli_last_error(void);
+
+/* Optional per-kernel timing with HIP events on the caller's stream.
+ * pauli_profile_enable(1) clears the log and starts recording;
+ * pauli_profile_read fills `buf` with one line per kernel name:
+ * "name count total_ms\n" and returns the number of bytes needed. */
+void pauli_profile_enable(int on);
+size_t pauli_profile_read(char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAULI_H */

@@ -1,0 +1,15 @@
+"""MI355X-native Pauli-string operator engine (HIP for gfx950).
+
+The hot path (commutator [H, O] on binary-encoded Pauli strings, duplicate
+merge, truncation, and the Lanczos / Runge-Kutta steps built on them) runs in
+libpauli.so behind the C ABI of include/pauli.h; this package is its thin
+Python binding over torch device memory.
+"""
+from ._lib import PAULI_C128, PAULI_C64K, PauliError
+from .ops import (PauliOp, Trunc, Workspace, add, canonicalize, commutator, inner,
+                  lanczos_step, norm2, profile_enable, profile_read, rk4_step, truncate)
+from .algorithms import evolve, lanczos
+
+__all__ = ["PAULI_C128", "PAULI_C64K", "PauliError", "PauliOp", "Trunc", "Workspace", "add",
+           "canonicalize", "commutator", "inner", "lanczos_step", "norm2", "rk4_step",
+           "truncate", "lanczos", "evolve", "profile_enable", "profile_read"]

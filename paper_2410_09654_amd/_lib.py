@@ -1,0 +1,87 @@
+"""ctypes declarations of the C ABI in include/pauli.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpauli.so")
+
+PAULI_OK, PAULI_EINVAL, PAULI_ECAPACITY, PAULI_EWORKSPACE, PAULI_BREAKDOWN, PAULI_EHIP, \
+    PAULI_EINTERNAL = range(7)
+PAULI_C128, PAULI_C64K = 0, 1
+
+EXPORTS = ["pauli_commutator", "pauli_add", "pauli_truncate", "pauli_canonicalize",
+           "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
+           "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_read"]
+
+
+class PauliOpC(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("size", ctypes.c_int64), ("capacity", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("z", ctypes.c_void_p), ("coef", ctypes.c_void_p)]
+
+
+class PauliTruncC(ctypes.Structure):
+    _fields_ = [("max_len", ctypes.c_int32), ("coef_eps", ctypes.c_double),
+                ("max_strings", ctypes.c_int64), ("keep", ctypes.POINTER(PauliOpC))]
+
+
+class PauliWsC(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("bytes", ctypes.c_size_t),
+                ("required", ctypes.c_size_t)]
+
+
+class PauliError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({strerror(status)}) {detail}".strip())
+
+
+_lib = None
+
+
+def load():
+    """Load libpauli.so.  Raises if it is missing: there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with "
+                          "`python -m paper_2410_09654_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    op, tr, ws = P(PauliOpC), P(PauliTruncC), P(PauliWsC)
+    vp, d = ctypes.c_void_p, ctypes.c_double
+    L.pauli_commutator.argtypes = [op, op, tr, op, ws, vp]
+    L.pauli_add.argtypes = [op, d, d, op, d, d, tr, op, ws, vp]
+    L.pauli_truncate.argtypes = [op, tr, op, ws, vp]
+    L.pauli_canonicalize.argtypes = [op, op, ws, vp]
+    L.pauli_rk4_step.argtypes = [op, op, d, tr, op, ws, vp]
+    L.pauli_lanczos_step.argtypes = [op, op, op, d, tr, ctypes.c_uint32, op, P(d), ws, vp]
+    L.pauli_norm2.argtypes = [op, P(d), ws, vp]
+    L.pauli_inner.argtypes = [op, op, P(d), ws, vp]
+    L.pauli_strerror.argtypes = [ctypes.c_int]
+    L.pauli_strerror.restype = ctypes.c_char_p
+    L.pauli_last_error.argtypes = []
+    L.pauli_last_error.restype = ctypes.c_char_p
+    L.pauli_profile_enable.argtypes = [ctypes.c_int]
+    L.pauli_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    L.pauli_profile_read.restype = ctypes.c_size_t
+    for name in EXPORTS:
+        L[name].restype = L[name].restype if name in (
+            "pauli_strerror", "pauli_last_error", "pauli_profile_read") else \
+            (None if name == "pauli_profile_enable" else ctypes.c_int)
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    try:
+        return load().pauli_strerror(status).decode()
+    except ImportError:
+        return str(status)
+
+
+def last_error() -> str:
+    return load().pauli_last_error().decode()

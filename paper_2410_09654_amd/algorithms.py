@@ -1,0 +1,46 @@
+"""Drivers of the two iterative methods on device operators.
+
+Both loops only sequence calls of the C ABI: every operator update runs in
+the HIP library.
+"""
+from __future__ import annotations
+
+from . import ops
+from .ops import PauliOp, Trunc, Workspace
+
+
+def lanczos(H: PauliOp, O0: PauliOp, steps: int, trunc: Trunc | None = None,
+            ws: Workspace | None = None, keep_basis: bool = False):
+    """Liouvillian Lanczos recursion (Krylov section): b_1..b_steps, stopping
+    at breakdown.  O0 must have unit norm."""
+    ws = ws or ops.default_workspace(O0.device)
+    bs, basis = [], [O0]
+    prev, cur, b_prev = None, O0, 0.0
+    for _ in range(steps):
+        nxt, b, broke = ops.lanczos_step(H, prev, cur, b_prev, trunc, ws=ws)
+        bs.append(b)
+        if broke:
+            break
+        prev, cur, b_prev = cur, nxt, b
+        if keep_basis:
+            basis.append(cur)
+    return (bs, basis) if keep_basis else bs
+
+
+def evolve(H: PauliOp, O0: PauliOp, dt: float, steps: int, trunc: Trunc | None = None,
+           ws: Workspace | None = None, observe=None):
+    """Heisenberg evolution dO/dt = i[H, O] by classical RK4 steps.
+
+    Returns (O(t_steps), [S(t_0), ..., S(t_steps)]) with the autocorrelation
+    S(t) = <O0, O(t)> / <O0, O0> (the correlator of the Heisenberg section).
+    """
+    ws = ws or ops.default_workspace(O0.device)
+    n0 = ops.norm2(O0, ws=ws)
+    S = [ops.inner(O0, O0, ws=ws) / n0]
+    cur = O0
+    for _ in range(steps):
+        cur = ops.rk4_step(H, cur, dt, trunc, ws=ws)
+        S.append(ops.inner(cur, O0, ws=ws).conjugate() / n0)
+        if observe is not None:
+            observe(cur)
+    return cur, S

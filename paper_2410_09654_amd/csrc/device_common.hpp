@@ -1,0 +1,259 @@
+// Device-side helpers of the Pauli-string engine (gfx950, wave64).
+//
+// Key words: a string on W 64-bit words per mask is kept as 2W words,
+// raw order (x[0..W-1], z[0..W-1]).  Inside the engine strings travel as
+// "mixed keys": a three-round Feistel network over the two halves (x, z)
+// whose round function is built from the MurmurHash3 64-bit finalizer
+// (fmix64).  The mix is a bijection, so equal mixed keys mean equal strings,
+// its leading bits are uniformly spread (they choose the hash bins), and the
+// ascending order of mixed keys is the library's canonical storage order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define DEV __device__ __forceinline__
+
+namespace pauli {
+
+constexpr int NBINS_LOG = 14;
+constexpr int NBINS = 1 << NBINS_LOG;   // hash bins of the emit passes
+constexpr int MERGE_CAP = 2048;         // max records of one merge bucket
+constexpr int MERGE_THREADS = 512;
+constexpr int DIGIT_BITS = 11;          // in-bucket counting-sort digit
+constexpr int NDIGITS = 1 << DIGIT_BITS;
+constexpr int EMIT_THREADS = 512;
+constexpr int SEL0_BINS = 2048;         // exponent bins of |c|^2
+constexpr int SEL_BINS = 4096;          // 12-bit digits of later select levels
+constexpr int FINISH_CAP = 2048;
+constexpr uint32_t GROUP_SHIFT = 28;    // record source id = group << 28 | index
+
+constexpr uint64_t MIX_C1 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t MIX_C2 = 0xC2B2AE3D27D4EB4Full;
+constexpr uint64_t MIX_C3 = 0x165667B19E3779F9ull;
+
+DEV uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+template <int W>
+struct Key {
+  uint64_t w[2 * W];
+};
+
+// Feistel round function of one half (W words) -> W words.
+template <int W>
+DEV void mix_round(const uint64_t* in, uint64_t* out, uint64_t c) {
+  if constexpr (W == 1) {
+    out[0] = fmix64(in[0] ^ c);
+  } else {
+    uint64_t s = fmix64(in[0] ^ c);
+    s = fmix64(s ^ in[1]);
+    out[0] = s;
+    out[1] = fmix64(s ^ c ^ 0x5bd1e9955bd1e995ull);
+  }
+}
+
+template <int W>
+DEV Key<W> mix_key(const Key<W>& raw) {
+  uint64_t L[W], R[W], f[W];
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    L[i] = raw.w[i];
+    R[i] = raw.w[W + i];
+  }
+  mix_round<W>(L, f, MIX_C1);
+#pragma unroll
+  for (int i = 0; i < W; i++) R[i] ^= f[i];
+  mix_round<W>(R, f, MIX_C2);
+#pragma unroll
+  for (int i = 0; i < W; i++) L[i] ^= f[i];
+  mix_round<W>(L, f, MIX_C3);
+#pragma unroll
+  for (int i = 0; i < W; i++) R[i] ^= f[i];
+  Key<W> m;
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    m.w[i] = L[i];
+    m.w[W + i] = R[i];
+  }
+  return m;
+}
+
+template <int W>
+DEV Key<W> unmix_key(const Key<W>& m) {
+  uint64_t L[W], R[W], f[W];
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    L[i] = m.w[i];
+    R[i] = m.w[W + i];
+  }
+  mix_round<W>(L, f, MIX_C3);
+#pragma unroll
+  for (int i = 0; i < W; i++) R[i] ^= f[i];
+  mix_round<W>(R, f, MIX_C2);
+#pragma unroll
+  for (int i = 0; i < W; i++) L[i] ^= f[i];
+  mix_round<W>(L, f, MIX_C1);
+#pragma unroll
+  for (int i = 0; i < W; i++) R[i] ^= f[i];
+  Key<W> raw;
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    raw.w[i] = L[i];
+    raw.w[W + i] = R[i];
+  }
+  return raw;
+}
+
+// -1 / 0 / 1 lexicographic comparison, word 0 most significant.
+template <int W>
+DEV int key_cmp(const Key<W>& a, const Key<W>& b) {
+#pragma unroll
+  for (int i = 0; i < 2 * W; i++)
+    if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
+  return 0;
+}
+
+template <int W>
+DEV bool key_eq(const Key<W>& a, const Key<W>& b) {
+  bool e = true;
+#pragma unroll
+  for (int i = 0; i < 2 * W; i++) e = e && (a.w[i] == b.w[i]);
+  return e;
+}
+
+// Number of non-identity sites of a raw key.
+template <int W>
+DEV int key_length(const Key<W>& raw) {
+  int n = 0;
+#pragma unroll
+  for (int i = 0; i < W; i++) n += __popcll(raw.w[i] | raw.w[W + i]);
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// Complex arithmetic, no contraction (the library is compiled with
+// -ffp-contract=off): (ar br - ai bi, ar bi + ai br), each product rounded.
+// ---------------------------------------------------------------------------
+DEV double2 cmul(double2 a, double2 b) {
+  double p1 = a.x * b.x, p2 = a.y * b.y, p3 = a.x * b.y, p4 = a.y * b.x;
+  return make_double2(p1 - p2, p3 + p4);
+}
+DEV float2 cmulf(float2 a, float2 b) {
+  float p1 = a.x * b.x, p2 = a.y * b.y, p3 = a.x * b.y, p4 = a.y * b.x;
+  return make_float2(p1 - p2, p3 + p4);
+}
+// 2 i^e v, exact.
+DEV double2 times_2ie(double2 v, int e) {
+  double2 r;
+  switch (e & 3) {
+    case 0: r = make_double2(2.0 * v.x, 2.0 * v.y); break;
+    case 1: r = make_double2(-2.0 * v.y, 2.0 * v.x); break;
+    case 2: r = make_double2(-2.0 * v.x, -2.0 * v.y); break;
+    default: r = make_double2(2.0 * v.y, -2.0 * v.x); break;
+  }
+  return r;
+}
+DEV float2 times_2ie(float2 v, int e) {
+  float2 r;
+  switch (e & 3) {
+    case 0: r = make_float2(2.0f * v.x, 2.0f * v.y); break;
+    case 1: r = make_float2(-2.0f * v.y, 2.0f * v.x); break;
+    case 2: r = make_float2(-2.0f * v.x, -2.0f * v.y); break;
+    default: r = make_float2(2.0f * v.y, -2.0f * v.x); break;
+  }
+  return r;
+}
+DEV double weight2(double2 v) {
+  double a = v.x * v.x;
+  double b = v.y * v.y;
+  return a + b;
+}
+DEV bool is_zero(double2 v) { return v.x == 0.0 && v.y == 0.0; }
+
+// Kahan-compensated accumulation (one component).
+DEV void kahan_add(float& s, float& comp, float t) {
+  float y = t - comp;
+  float u = s + y;
+  comp = (u - s) - y;
+  s = u;
+}
+
+// ---------------------------------------------------------------------------
+// Double-double accumulation of non-negative or signed terms.
+// ---------------------------------------------------------------------------
+struct dd {
+  double hi, lo;
+};
+DEV dd dd_zero() { return {0.0, 0.0}; }
+DEV void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+DEV dd dd_add(dd a, double b) {
+  double s, e;
+  two_sum(a.hi, b, s, e);
+  e = e + a.lo;
+  double hi = s + e;
+  double lo = e - (hi - s);
+  return {hi, lo};
+}
+DEV dd dd_add(dd a, dd b) {
+  double s, e;
+  two_sum(a.hi, b.hi, s, e);
+  e = e + (a.lo + b.lo);
+  double hi = s + e;
+  double lo = e - (hi - s);
+  return {hi, lo};
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers
+// ---------------------------------------------------------------------------
+DEV uint32_t lane_id() { return __lane_id(); }
+DEV uint32_t mbcnt64(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Block-wide exclusive scan of one uint32 per thread (blockDim <= 1024).
+// `tmp` must hold blockDim.x/64 + 1 words.  Returns the exclusive prefix and
+// writes the total into *total.
+DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) tmp[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int i = 0; i < nw; i++) {
+      uint32_t t = tmp[i];
+      tmp[i] = run;
+      run += t;
+    }
+    tmp[nw] = run;
+  }
+  __syncthreads();
+  uint32_t r = tmp[wv] + x - v;
+  *total = tmp[nw];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace pauli

@@ -1,0 +1,966 @@
+// Host orchestration and C ABI of the Pauli-string engine (see include/pauli.h).
+//
+// Every operation is one or more "engine calls": records from a commutator
+// pair loop and/or from operator terms are binned by the leading bits of
+// their mixed key, merged per bucket in LDS (summing each string's
+// contributions in canonical order), filtered, reduced to the top-M by an
+// exact radix select and compacted into the output.  The engine carves all
+// of its scratch from the caller's workspace; intermediate operators of a
+// Runge-Kutta step live at the top end of the same workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pauli.h"
+#include "kernels.hpp"
+
+using namespace pauli;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// ---------------------------------------------------------------------------
+// Optional kernel timing
+// ---------------------------------------------------------------------------
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<long, double>> acc;
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void resolve() {  // call after the stream is synchronised
+    std::lock_guard<std::mutex> g(mu);
+    for (auto& p : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        auto& e = acc[p.name];
+        e.first += 1;
+        e.second += ms;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+};
+Prof g_prof;
+
+struct ProfScope {
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(const char* n, hipStream_t st) : name(n), s(st) {
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    a = g_prof.get();
+    b = g_prof.get();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    g_prof.pending.push_back({name, a, b});
+  }
+};
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(e_);           \
+      return PAULI_EHIP;                                                           \
+    }                                                                              \
+  } while (0)
+
+#define LAUNCH(name, kern, grid, block, ...)                                       \
+  do {                                                                             \
+    ProfScope ps_(name, stream);                                                   \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, __VA_ARGS__);     \
+    HIP_TRY(hipGetLastError());                                                    \
+  } while (0)
+
+#define TRY(expr)                    \
+  do {                               \
+    int rc_ = (expr);                \
+    if (rc_ != PAULI_OK) return rc_; \
+  } while (0)
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+inline int words_of(int n_qubits) { return (n_qubits + 63) / 64; }
+
+// pinned host copy of the control block (one per thread)
+thread_local Ctl* t_hctl = nullptr;
+int host_ctl(Ctl** out) {
+  if (!t_hctl) HIP_TRY(hipHostMalloc((void**)&t_hctl, sizeof(Ctl), hipHostMallocDefault));
+  *out = t_hctl;
+  return PAULI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace arena: engine scratch grows from the bottom (reset per engine
+// call), operators that outlive an engine call are taken from the top.
+// ---------------------------------------------------------------------------
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t bottom = 0;  // next free byte from the bottom
+  size_t top = 0;     // bytes used at the top end
+  size_t need = 0;    // largest bottom + top requested so far
+  bool short_ = false;
+
+  void* take(size_t bytes) {
+    bottom = align256(bottom);
+    void* p = base + bottom;
+    bottom += align256(bytes);
+    if (bottom + top > need) need = bottom + top;
+    if (bottom + top > cap) {
+      short_ = true;
+      return nullptr;
+    }
+    return p;
+  }
+  void* take_top(size_t bytes) {
+    top += align256(bytes);
+    if (bottom + top > need) need = bottom + top;
+    if (bottom + top > cap) {
+      short_ = true;
+      return nullptr;
+    }
+    return base + (cap - top);
+  }
+};
+
+struct OpV {
+  int W = 1;
+  int f32 = 0;
+  int64_t n = 0;
+  int64_t cap = 0;
+  const uint64_t* x = nullptr;
+  const uint64_t* z = nullptr;
+  const void* c = nullptr;
+};
+
+OpV view(const pauli_op* o) {
+  OpV v;
+  v.W = words_of(o->n_qubits);
+  v.f32 = o->dtype == PAULI_C64K;
+  v.n = o->size;
+  v.cap = o->capacity;
+  v.x = o->x;
+  v.z = o->z;
+  v.c = o->coef;
+  return v;
+}
+
+int check_op(const pauli_op* o, bool output) {
+  if (!o) return PAULI_EINVAL;
+  if (o->n_qubits < 1 || o->n_qubits > 128) return PAULI_EINVAL;
+  if (o->dtype != PAULI_C128 && o->dtype != PAULI_C64K) return PAULI_EINVAL;
+  if (o->capacity < 0 || (!output && (o->size < 0 || o->size > o->capacity))) return PAULI_EINVAL;
+  if (o->capacity > 0 && (!o->x || !o->z || !o->coef)) return PAULI_EINVAL;
+  return PAULI_OK;
+}
+
+struct GroupSpec {
+  int kind = G_TERM;
+  double2 alpha = make_double2(1.0, 0.0);
+};
+
+struct OutSpec {
+  pauli_op* user = nullptr;  // write into the caller's operator
+  bool to_arena = false;     // or allocate at the top of the workspace
+  OpV arena_op;              // filled when to_arena
+  int f32 = 0;
+};
+
+struct Call {
+  int W = 1;
+  bool f32rec = false;  // FP32 record values (precision split)
+  bool has_comm = false;
+  OpV H, O;
+  int comm_group = 0;
+  int n_terms = 0;
+  OpV T[MAX_TERMS];
+  int tgroup[MAX_TERMS] = {0};
+  int tlist[MAX_TERMS] = {0};
+  int n_groups = 0;
+  GroupSpec groups[MAX_GROUPS];
+  int mode = M_PLAIN;
+  bool round32 = false;
+  const pauli_trunc* trunc = nullptr;
+  OutSpec out;
+  // Lanczos
+  double b_prev = 0.0;
+  double* b_out = nullptr;
+};
+
+int alpha_kind(double2 a) {
+  if (a.x == 1.0 && a.y == 0.0) return A_ONE;
+  if (a.x == 0.0 && a.y == 1.0) return A_I;
+  return A_GENERAL;
+}
+
+struct Engine {
+  Arena* ar;
+  hipStream_t stream;
+  Ctl* dctl = nullptr;
+  Ctl* hctl = nullptr;
+
+  int read_ctl() {
+    HIP_TRY(hipMemcpyAsync(hctl, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    g_prof.resolve();
+    return PAULI_OK;
+  }
+  int zero_u32(void* p, size_t words) {
+    if (!words) return PAULI_OK;
+    const size_t blocks = (words + 255) / 256;
+    LAUNCH("k_fill_u32", k_fill_u32, blocks, 256, (uint32_t*)p, 0u, words);
+    return PAULI_OK;
+  }
+  int set_u64(unsigned long long* dst, unsigned long long v) {
+    // small host->device update of the control block (not used under capture)
+    HIP_TRY(hipMemcpyAsync(dst, &v, sizeof(v), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return PAULI_OK;
+  }
+
+  template <int W, bool F32>
+  int run(Call& c);
+};
+
+int ws_short(Arena& ar, pauli_ws* ws) {
+  ws->required = ar.need + (1 << 20);
+  return PAULI_EWORKSPACE;
+}
+
+template <int W, bool F32>
+int Engine::run(Call& c) {
+  using V = RecV<F32>;
+  const size_t KB = sizeof(Key<W>);
+  const size_t VB = sizeof(V);
+  ar->bottom = 0;
+  // ----- inputs --------------------------------------------------------------
+  const bool comm = c.has_comm && c.H.n > 0 && c.O.n > 0;
+  int64_t tstart[MAX_TERMS + 1];
+  tstart[0] = 0;
+  for (int t = 0; t < c.n_terms; t++) tstart[t + 1] = tstart[t] + c.T[t].n;
+  const int64_t nterm_rec = tstart[c.n_terms];
+  const pauli_trunc* tr = c.trunc;
+  const pauli_op* keep = tr ? tr->keep : nullptr;
+  const int64_t n_keep = keep ? keep->size : 0;
+  if (n_keep > 65536) return PAULI_EINVAL;
+  if (keep && words_of(keep->n_qubits) != W) return PAULI_EINVAL;
+
+  int comm_rows = comm ? (int)std::min<int64_t>((c.O.n + EMIT_THREADS - 1) / EMIT_THREADS, 512) : 0;
+  int term_rows = nterm_rec > 0 ? (int)std::min<int64_t>((nterm_rec + EMIT_THREADS - 1) / EMIT_THREADS, 256) : 0;
+  const int rows = comm_rows + term_rows;
+
+  dctl = (Ctl*)ar->take(sizeof(Ctl));
+  uint64_t* Hk = comm ? (uint64_t*)ar->take((size_t)c.H.n * KB) : nullptr;
+  Key<W>* keep_mk = n_keep ? (Key<W>*)ar->take((size_t)n_keep * KB) : nullptr;
+  uint32_t* counts = (uint32_t*)ar->take((size_t)std::max(rows, 1) * NBINS * 4);
+  uint32_t* bin_total = (uint32_t*)ar->take(NBINS * 4);
+  uint32_t* bin_base = (uint32_t*)ar->take((NBINS + 1) * 4);
+  uint32_t* hist0 = (uint32_t*)ar->take(SEL0_BINS * 4);
+  uint32_t* histL[2];
+  histL[0] = (uint32_t*)ar->take(SEL_BINS * 4);
+  histL[1] = (uint32_t*)ar->take(SEL_BINS * 4);
+  if (ar->short_) return PAULI_EWORKSPACE;
+  TRY(host_ctl(&hctl));
+  TRY(zero_u32(dctl, sizeof(Ctl) / 4));
+
+  auto write_empty = [&]() -> int {
+    if (c.out.to_arena) {
+      c.out.arena_op = OpV();
+      c.out.arena_op.W = W;
+      c.out.arena_op.f32 = c.out.f32;
+    } else {
+      c.out.user->size = 0;
+    }
+    return PAULI_OK;
+  };
+  if (rows == 0) {
+    if (c.mode == M_LANCZOS) {
+      if (c.b_out) *c.b_out = 0.0;
+      write_empty();
+      return PAULI_BREAKDOWN;
+    }
+    return write_empty();
+  }
+  if (comm) {
+    LAUNCH("k_pack_keys", (k_pack_keys<W>), (c.H.n + 255) / 256, 256, c.H.x, c.H.z, c.H.cap,
+           c.H.n, Hk);
+  }
+  if (n_keep) {
+    LAUNCH("k_mix_keys", (k_mix_keys<W>), (n_keep + 255) / 256, 256, keep->x, keep->z,
+           keep->capacity, n_keep, keep_mk, &dctl->bad_keep);
+  }
+
+  EmitArgs ea;
+  memset(&ea, 0, sizeof(ea));
+  ea.Hk = Hk;
+  ea.Hc = comm ? (const double2*)c.H.c : nullptr;
+  ea.nH = comm ? (int)c.H.n : 0;
+  ea.has_comm = comm ? 1 : 0;
+  ea.comm_rows = comm_rows;
+  ea.comm_group = (uint32_t)c.comm_group;
+  if (comm) {
+    ea.Ox = c.O.x;
+    ea.Oz = c.O.z;
+    ea.Ocap = c.O.cap;
+    ea.nO = c.O.n;
+    ea.Oc = c.O.c;
+  }
+  ea.n_terms = c.n_terms;
+  ea.term_rows = term_rows;
+  for (int t = 0; t < c.n_terms; t++) {
+    ea.tx[t] = c.T[t].x;
+    ea.tz[t] = c.T[t].z;
+    ea.tcap[t] = c.T[t].cap;
+    ea.tc[t] = c.T[t].c;
+    ea.tf32[t] = c.T[t].f32;
+    ea.tgroup[t] = (uint32_t)c.tgroup[t];
+    ea.tlist[t] = c.tlist[t];
+  }
+  for (int t = 0; t <= c.n_terms; t++) ea.tstart[t] = tstart[t];
+  ea.counts = counts;
+  ea.bin_base = bin_base;
+
+  auto count_pass = [&](int pass_bits, uint32_t pass_id) -> int {
+    ea.pass_bits = pass_bits;
+    ea.pass_id = pass_id;
+    LAUNCH("k_emit_count", (k_emit<W, F32, false>), rows, EMIT_THREADS, ea);
+    LAUNCH("k_scan_cols", k_scan_cols, NBINS / 256, 256, counts, rows, bin_total, dctl);
+    LAUNCH("k_scan_bins", k_scan_bins, 1, 1024, bin_total, bin_base, dctl);
+    return read_ctl();
+  };
+  TRY(count_pass(0, 0));
+  if (hctl->bad_keep) return PAULI_EINVAL;
+  if (hctl->overflow & 2u) {
+    g_last_error = "more than 2^32 records in one pass";
+    return PAULI_EINTERNAL;
+  }
+  const unsigned long long pe_all = hctl->pe_total;
+  // passes over disjoint hash ranges keep every bucket within MERGE_CAP
+  int pass_bits = 0;
+  {
+    unsigned long long mx = hctl->maxg[0];
+    while (mx > (unsigned long long)(MERGE_CAP * 7 / 8) && pass_bits < 10) {
+      pass_bits++;
+      mx = (mx + 1) / 2;
+    }
+  }
+  const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
+  const uint32_t max_buckets = (uint32_t)NBINS << pass_bits;
+  // ----- records, U, bucket tables, candidate lists -------------------------
+  void* rkey = ar->take(ptot * KB);
+  void* rval = ar->take(ptot * VB);
+  uint32_t* rsrc = (uint32_t*)ar->take(ptot * 4);
+  void* uk = ar->take(ptot * KB);
+  double2* uc = (double2*)ar->take(ptot * sizeof(double2));
+  uint32_t* b_ubase = (uint32_t*)ar->take((size_t)max_buckets * 4);
+  uint32_t* b_slots = (uint32_t*)ar->take((size_t)max_buckets * 4);
+  uint32_t* b_surv = (uint32_t*)ar->take((size_t)max_buckets * 4);
+  uint32_t* b_keep = (uint32_t*)ar->take((size_t)max_buckets * 4);
+  uint32_t* b_abv = (uint32_t*)ar->take((size_t)max_buckets * 4);
+  uint32_t* b_bcnt = (uint32_t*)ar->take((size_t)max_buckets * 4);
+  uint32_t* b_obase = (uint32_t*)ar->take((size_t)max_buckets * 4);
+  double2* norm_part = (double2*)ar->take((size_t)max_buckets * sizeof(double2));
+  const bool want_select = tr && tr->max_strings > 0;
+  uint32_t* cand[3] = {nullptr, nullptr, nullptr};
+  if (want_select)
+    for (int k = 0; k < 3; k++) cand[k] = (uint32_t*)ar->take(ptot * 8);
+  if (ar->short_) return PAULI_EWORKSPACE;
+  TRY(zero_u32(hist0, SEL0_BINS));
+
+  MergeArgs ma;
+  memset(&ma, 0, sizeof(ma));
+  ma.bin_base = bin_base;
+  ma.rkey = rkey;
+  ma.rval = rval;
+  ma.rsrc = rsrc;
+  for (int g = 0; g < c.n_groups; g++) {
+    ma.alpha[g] = c.groups[g].alpha;
+    ma.alpha_kind[g] = alpha_kind(c.groups[g].alpha);
+    ma.gkind[g] = c.groups[g].kind;
+  }
+  ma.mode = c.mode;
+  ma.round32 = c.round32 ? 1 : 0;
+  ma.max_len = tr ? tr->max_len : 0;
+  ma.use_eps = (tr && tr->coef_eps > 0.0) ? 1 : 0;
+  ma.eps2 = tr ? tr->coef_eps * tr->coef_eps : 0.0;
+  ma.keep_mk = keep_mk;
+  ma.n_keep = (int)n_keep;
+  ma.uk = uk;
+  ma.uc = uc;
+  ma.b_ubase = b_ubase;
+  ma.b_slots = b_slots;
+  ma.b_surv = b_surv;
+  ma.b_keep = b_keep;
+  ma.hist0 = hist0;
+  ma.norm_part = norm_part;
+  ma.ctl = dctl;
+
+  ea.rkey = rkey;
+  ea.rval = rval;
+  ea.rsrc = rsrc;
+  uint32_t nbk = 0;                // buckets written so far
+  unsigned long long u_off = 0;   // U slots reserved by earlier passes
+  const int npass = 1 << pass_bits;
+  for (int p = 0; p < npass; p++) {
+    if (pass_bits) TRY(count_pass(pass_bits, (uint32_t)p));
+    const unsigned long long pe = hctl->pe_total;
+    int g_log = 4;
+    while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)MERGE_CAP) g_log--;
+    if (hctl->maxg[0] > (unsigned int)MERGE_CAP) {
+      g_last_error = "hash bucket above merge capacity";
+      return PAULI_EINTERNAL;
+    }
+    if (pe == 0) continue;
+    LAUNCH("k_emit_scatter", (k_emit<W, F32, true>), rows, EMIT_THREADS, ea);
+    ma.g_log = g_log;
+    ma.digit_shift = pass_bits + NBINS_LOG - g_log;
+    ma.u_off = u_off;
+    ma.bucket_off = nbk;
+    const uint32_t nb_pass = (uint32_t)(NBINS >> g_log);
+    LAUNCH("k_merge", (k_merge<W, F32>), nb_pass, MERGE_THREADS, ma);
+    nbk += nb_pass;
+    u_off += pe;
+  }
+  TRY(read_ctl());
+  if (hctl->overflow) {
+    g_last_error = "merge bucket overflow";
+    return PAULI_EINTERNAL;
+  }
+
+  // ----- Lanczos: b_n from the untruncated sum, then divide and filter -------
+  if (c.mode == M_LANCZOS) {
+    double* nrm = (double*)ar->take(16);
+    if (ar->short_) return PAULI_EWORKSPACE;
+    if (nbk) {
+      LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, norm_part, nbk, nrm);
+      HIP_TRY(hipMemcpyAsync(&hctl->norm_hi, nrm, 16, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+    } else {
+      hctl->norm_hi = 0.0;
+    }
+    const double b = std::sqrt(hctl->norm_hi);
+    if (c.b_out) *c.b_out = b;
+    const double floor_b = 1e-13 * (c.b_prev > 1.0 ? c.b_prev : 1.0);
+    if (!(b > floor_b)) {
+      write_empty();
+      return PAULI_BREAKDOWN;
+    }
+    // reset survivor totals: the scale pass recounts them
+    TRY(zero_u32(&dctl->surv_total, 4));
+    ScaleArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    sa.b_ubase = b_ubase;
+    sa.b_slots = b_slots;
+    sa.b_surv = b_surv;
+    sa.b_keep = b_keep;
+    sa.uk = uk;
+    sa.uc = uc;
+    sa.bnorm = b;
+    sa.round32 = c.out.f32;
+    sa.max_len = ma.max_len;
+    sa.use_eps = ma.use_eps;
+    sa.eps2 = ma.eps2;
+    sa.keep_mk = keep_mk;
+    sa.n_keep = (int)n_keep;
+    sa.hist0 = hist0;
+    sa.ctl = dctl;
+    if (nbk) LAUNCH("k_scale_filter", (k_scale_filter<W>), nbk, 256, sa);
+    TRY(read_ctl());
+  }
+
+  // ----- top-M --------------------------------------------------------------
+  const unsigned long long surv = hctl->surv_total, fk = hctl->keep_total;
+  const unsigned long long nonkeep = surv - fk;
+  int sel_mode = S_ALL;
+  if (want_select) {
+    const long long budget = (long long)tr->max_strings - (long long)fk;
+    if (budget <= 0) sel_mode = fk == surv ? S_ALL : S_KEEP_ONLY;
+    else if ((unsigned long long)budget >= nonkeep) sel_mode = S_ALL;
+    else sel_mode = S_THRESHOLD;
+    if (sel_mode == S_THRESHOLD) {
+      SelArgs sa;
+      memset(&sa, 0, sizeof(sa));
+      sa.b_ubase = b_ubase;
+      sa.b_slots = b_slots;
+      sa.b_abv = b_abv;
+      sa.b_bcnt = b_bcnt;
+      sa.uk = uk;
+      sa.uc = uc;
+      sa.keep_mk = keep_mk;
+      sa.n_keep = (int)n_keep;
+      sa.cand_cap = ptot;
+      sa.ctl = dctl;
+      TRY(set_u64(&dctl->sel_K, (unsigned long long)budget));
+      TRY(zero_u32(dctl->cand_n, 6));
+      LAUNCH("k_select", k_select, 1, 1024, hist0, SEL0_BINS, dctl);
+      // level 1: full pass over U into list 0 (kept for the boundary count)
+      TRY(zero_u32(histL[0], SEL_BINS));
+      sa.out_slot = 0;
+      sa.cand_out = cand[0];
+      sa.hist = histL[0];
+      sa.level = 0;
+      LAUNCH("k_level1", (k_level1<W>), nbk, 256, sa);
+      TRY(read_ctl());
+      int level = 0, in_slot = 0, hslot = 0;
+      unsigned long long cnt = hctl->sel_count;
+      if (cnt > FINISH_CAP) {
+        level = 1;
+        LAUNCH("k_select", k_select, 1, 1024, histL[0], SEL_BINS, dctl);
+        TRY(read_ctl());
+        cnt = hctl->sel_count;
+        int out_slot = 1;
+        while (cnt > FINISH_CAP) {
+          if (level >= (64 + 128 * W) / 12) {
+            g_last_error = "top-M select did not converge";
+            return PAULI_EINTERNAL;
+          }
+          hslot ^= 1;
+          TRY(zero_u32(histL[hslot], SEL_BINS));
+          TRY(zero_u32(&dctl->cand_n[out_slot], 2));
+          sa.in_slot = in_slot;
+          sa.out_slot = out_slot;
+          sa.cand_in = cand[in_slot];
+          sa.cand_out = cand[out_slot];
+          sa.hist = histL[hslot];
+          sa.level = level;
+          const int grid = (int)std::min<unsigned long long>((cnt + 255) / 256 + 1, 1024);
+          LAUNCH("k_cand_level", (k_cand_level<W>), grid, 256, sa);
+          LAUNCH("k_select", k_select, 1, 1024, histL[hslot], SEL_BINS, dctl);
+          TRY(read_ctl());
+          cnt = hctl->sel_count;
+          in_slot = out_slot;
+          out_slot = out_slot == 1 ? 2 : 1;
+          level++;
+        }
+      }
+      sa.in_slot = in_slot;
+      sa.cand_in = cand[in_slot];
+      sa.level = level;
+      LAUNCH("k_finish", (k_finish<W>), 1, 1024, sa);
+      TRY(zero_u32(b_bcnt, nbk));
+      sa.in_slot = 0;
+      sa.cand_in = cand[0];
+      LAUNCH("k_count_boundary", (k_count_boundary<W>), 512, 256, sa);
+    }
+  }
+  if (nbk == 0) return write_empty();
+  LAUNCH("k_scan_buckets", k_scan_buckets, 1, 1024, b_surv, b_keep, b_abv, b_bcnt, nbk, sel_mode,
+         b_obase, dctl);
+  TRY(read_ctl());
+  if (sel_mode == S_THRESHOLD && !hctl->t_found) {
+    g_last_error = "top-M threshold not found";
+    return PAULI_EINTERNAL;
+  }
+  const unsigned long long nout = hctl->out_total;
+  WriteArgs wa;
+  memset(&wa, 0, sizeof(wa));
+  wa.b_ubase = b_ubase;
+  wa.b_slots = b_slots;
+  wa.b_obase = b_obase;
+  wa.uk = uk;
+  wa.uc = uc;
+  wa.keep_mk = keep_mk;
+  wa.n_keep = (int)n_keep;
+  wa.sel_mode = sel_mode;
+  wa.ctl = dctl;
+  wa.out_f32 = c.out.f32;
+  if (c.out.to_arena) {
+    const size_t n = (size_t)std::max<unsigned long long>(nout, 1);
+    uint64_t* ox = (uint64_t*)ar->take_top(n * 8 * W);
+    uint64_t* oz = (uint64_t*)ar->take_top(n * 8 * W);
+    void* oc = ar->take_top(n * (c.out.f32 ? 8 : 16));
+    if (ar->short_) return PAULI_EWORKSPACE;
+    c.out.arena_op.W = W;
+    c.out.arena_op.f32 = c.out.f32;
+    c.out.arena_op.n = (int64_t)nout;
+    c.out.arena_op.cap = (int64_t)n;
+    c.out.arena_op.x = ox;
+    c.out.arena_op.z = oz;
+    c.out.arena_op.c = oc;
+    wa.ox = ox;
+    wa.oz = oz;
+    wa.oc = oc;
+    wa.ocap = (int64_t)n;
+  } else {
+    pauli_op* o = c.out.user;
+    if ((unsigned long long)o->capacity < nout) {
+      o->size = (int64_t)nout;
+      return PAULI_ECAPACITY;
+    }
+    wa.ox = o->x;
+    wa.oz = o->z;
+    wa.oc = o->coef;
+    wa.ocap = o->capacity;
+  }
+  if (nout) LAUNCH("k_write", (k_write<W>), nbk, 256, wa);
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  if (!c.out.to_arena) c.out.user->size = (int64_t)nout;
+  return PAULI_OK;
+}
+
+int dispatch(Engine& e, Call& c) {
+  if (c.W == 1) return c.f32rec ? e.run<1, true>(c) : e.run<1, false>(c);
+  if (c.W == 2) return c.f32rec ? e.run<2, true>(c) : e.run<2, false>(c);
+  return PAULI_EINVAL;
+}
+
+int run_call(Arena& ar, pauli_ws* ws, void* stream, Call& c) {
+  Engine e;
+  e.ar = &ar;
+  e.stream = (hipStream_t)stream;
+  int rc = dispatch(e, c);
+  if (rc == PAULI_EWORKSPACE || ar.short_) return ws_short(ar, ws);
+  return rc;
+}
+
+Arena make_arena(pauli_ws* ws) {
+  Arena a;
+  a.base = (char*)ws->ptr;
+  a.cap = ws->ptr ? ws->bytes : 0;
+  return a;
+}
+
+OpV as_input(const OpV& v) { return v; }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* pauli_strerror(int status) {
+  switch (status) {
+    case PAULI_OK: return "ok";
+    case PAULI_EINVAL: return "invalid argument";
+    case PAULI_ECAPACITY: return "output capacity too small (size holds the requirement)";
+    case PAULI_EWORKSPACE: return "workspace too small (ws->required holds the requirement)";
+    case PAULI_BREAKDOWN: return "Lanczos breakdown: b_n is zero";
+    case PAULI_EHIP: return "HIP runtime error";
+    case PAULI_EINTERNAL: return "internal limit exceeded";
+    default: return "unknown status";
+  }
+}
+
+const char* pauli_last_error(void) { return g_last_error.c_str(); }
+
+void pauli_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  g_prof.on = on != 0;
+  g_prof.acc.clear();
+}
+
+size_t pauli_profile_read(char* buf, size_t len) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  std::string s;
+  char line[256];
+  for (auto& kv : g_prof.acc) {
+    snprintf(line, sizeof(line), "%s %ld %.9f\n", kv.first.c_str(), kv.second.first,
+             kv.second.second);
+    s += line;
+  }
+  if (buf && len) {
+    size_t n = std::min(len - 1, s.size());
+    memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return s.size() + 1;
+}
+
+int pauli_commutator(const pauli_op* H, const pauli_op* O, const pauli_trunc* t, pauli_op* out,
+                     pauli_ws* ws, void* stream) {
+  if (!ws || check_op(H, false) || check_op(O, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (H->n_qubits != O->n_qubits || out->n_qubits != O->n_qubits) return PAULI_EINVAL;
+  if (H->dtype != PAULI_C128 || out->dtype != O->dtype) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  Call c;
+  c.W = words_of(O->n_qubits);
+  c.f32rec = O->dtype == PAULI_C64K;
+  c.has_comm = true;
+  c.H = view(H);
+  c.O = view(O);
+  c.comm_group = 0;
+  c.n_groups = 1;
+  c.groups[0].kind = c.f32rec ? G_SUM_KAHAN32 : G_SUM;
+  c.trunc = t;
+  c.out.user = out;
+  c.out.f32 = out->dtype == PAULI_C64K;
+  c.round32 = c.out.f32;
+  return run_call(ar, ws, stream, c);
+}
+
+int pauli_add(const pauli_op* A, double ar_, double ai, const pauli_op* B, double br, double bi,
+              const pauli_trunc* t, pauli_op* out, pauli_ws* ws, void* stream) {
+  if (!ws || check_op(A, false) || check_op(B, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (A->n_qubits != B->n_qubits || out->n_qubits != A->n_qubits) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  Call c;
+  c.W = words_of(A->n_qubits);
+  c.f32rec = A->dtype == PAULI_C64K && B->dtype == PAULI_C64K;
+  c.n_terms = 2;
+  c.T[0] = view(A);
+  c.T[1] = view(B);
+  c.tgroup[0] = 0;
+  c.tgroup[1] = 1;
+  c.n_groups = 2;
+  c.groups[0].alpha = make_double2(ar_, ai);
+  c.groups[1].alpha = make_double2(br, bi);
+  c.trunc = t;
+  c.out.user = out;
+  c.out.f32 = out->dtype == PAULI_C64K;
+  c.round32 = c.out.f32;
+  return run_call(ar, ws, stream, c);
+}
+
+int pauli_truncate(const pauli_op* in, const pauli_trunc* t, pauli_op* out, pauli_ws* ws,
+                   void* stream) {
+  if (!ws || check_op(in, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (out->n_qubits != in->n_qubits) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  Call c;
+  c.W = words_of(in->n_qubits);
+  c.f32rec = in->dtype == PAULI_C64K;
+  c.n_terms = 1;
+  c.T[0] = view(in);
+  c.n_groups = 1;
+  c.trunc = t;
+  c.out.user = out;
+  c.out.f32 = out->dtype == PAULI_C64K;
+  c.round32 = c.out.f32;
+  return run_call(ar, ws, stream, c);
+}
+
+int pauli_canonicalize(const pauli_op* in, pauli_op* out, pauli_ws* ws, void* stream) {
+  if (!ws || check_op(in, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (out->n_qubits != in->n_qubits) return PAULI_EINVAL;
+  if (in->size >= ((int64_t)1 << GROUP_SHIFT)) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  Call c;
+  c.W = words_of(in->n_qubits);
+  c.f32rec = in->dtype == PAULI_C64K;
+  c.n_terms = 1;
+  c.T[0] = view(in);
+  c.tlist[0] = 1;
+  c.n_groups = 1;
+  c.groups[0].kind = G_SUM;
+  c.out.user = out;
+  c.out.f32 = out->dtype == PAULI_C64K;
+  c.round32 = c.out.f32;
+  return run_call(ar, ws, stream, c);
+}
+
+int pauli_lanczos_step(const pauli_op* H, const pauli_op* O_prev, const pauli_op* O_cur,
+                       double b_prev, const pauli_trunc* t, uint32_t flags, pauli_op* O_next,
+                       double* b_out, pauli_ws* ws, void* stream) {
+  if (!ws || flags != 0 || check_op(H, false) || check_op(O_cur, false) ||
+      check_op(O_next, true))
+    return PAULI_EINVAL;
+  if (O_prev && check_op(O_prev, false)) return PAULI_EINVAL;
+  if (H->dtype != PAULI_C128 || O_next->dtype != O_cur->dtype) return PAULI_EINVAL;
+  if (O_prev && O_prev->dtype != O_cur->dtype) return PAULI_EINVAL;
+  if (H->n_qubits != O_cur->n_qubits || O_next->n_qubits != O_cur->n_qubits ||
+      (O_prev && O_prev->n_qubits != O_cur->n_qubits))
+    return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  Call c;
+  c.W = words_of(O_cur->n_qubits);
+  c.f32rec = O_cur->dtype == PAULI_C64K;
+  c.has_comm = true;
+  c.H = view(H);
+  c.O = view(O_cur);
+  c.comm_group = 0;
+  c.n_groups = 1;
+  c.groups[0].kind = c.f32rec ? G_SUM_KAHAN32 : G_SUM;
+  if (O_prev && O_prev->size > 0) {
+    c.n_terms = 1;
+    c.T[0] = view(O_prev);
+    c.tgroup[0] = 1;
+    c.n_groups = 2;
+    c.groups[1].kind = G_TERM;
+    c.groups[1].alpha = make_double2(-b_prev, 0.0);
+  }
+  c.mode = M_LANCZOS;
+  c.trunc = t;
+  c.out.user = O_next;
+  c.out.f32 = O_next->dtype == PAULI_C64K;
+  c.b_prev = b_prev;
+  double b = 0.0;
+  c.b_out = &b;
+  int rc = run_call(ar, ws, stream, c);
+  if (b_out) *b_out = b;
+  return rc;
+}
+
+int pauli_rk4_step(const pauli_op* H, const pauli_op* O, double dt, const pauli_trunc* t,
+                   pauli_op* out, pauli_ws* ws, void* stream) {
+  if (!ws || check_op(H, false) || check_op(O, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (H->dtype != PAULI_C128 || O->dtype != PAULI_C128 || out->dtype != PAULI_C128)
+    return PAULI_EINVAL;
+  if (H->n_qubits != O->n_qubits || out->n_qubits != O->n_qubits) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  const int W = words_of(O->n_qubits);
+  const double h2 = dt / 2.0, c1 = dt / 6.0, c2 = dt / 3.0;
+  const OpV Ov = view(O);
+  // k = i [H, S], untruncated, kept at the top of the workspace
+  auto comm_i = [&](const OpV& S, OpV* k) -> int {
+    Call c;
+    c.W = W;
+    c.has_comm = true;
+    c.H = view(H);
+    c.O = S;
+    c.n_groups = 1;
+    c.groups[0].kind = G_SUM;
+    c.groups[0].alpha = make_double2(0.0, 1.0);
+    c.out.to_arena = true;
+    int rc = run_call(ar, ws, stream, c);
+    *k = c.out.arena_op;
+    return rc;
+  };
+  // S = trunc(O + h k)
+  auto stage = [&](const OpV& k, double h, OpV* S) -> int {
+    Call c;
+    c.W = W;
+    c.n_terms = 2;
+    c.T[0] = Ov;
+    c.T[1] = k;
+    c.tgroup[0] = 0;
+    c.tgroup[1] = 1;
+    c.n_groups = 2;
+    c.groups[1].alpha = make_double2(h, 0.0);
+    c.trunc = t;
+    c.out.to_arena = true;
+    int rc = run_call(ar, ws, stream, c);
+    *S = c.out.arena_op;
+    return rc;
+  };
+  OpV k1, k2, k3, k4, S2, S3, S4;
+  TRY(comm_i(Ov, &k1));
+  TRY(stage(k1, h2, &S2));
+  TRY(comm_i(S2, &k2));
+  TRY(stage(k2, h2, &S3));
+  TRY(comm_i(S3, &k3));
+  TRY(stage(k3, dt, &S4));
+  TRY(comm_i(S4, &k4));
+  Call c;
+  c.W = W;
+  c.n_terms = 5;
+  c.T[0] = Ov;
+  c.T[1] = k1;
+  c.T[2] = k2;
+  c.T[3] = k3;
+  c.T[4] = k4;
+  const double al[5] = {1.0, c1, c2, c2, c1};
+  for (int g = 0; g < 5; g++) {
+    c.tgroup[g] = g;
+    c.groups[g].alpha = make_double2(al[g], 0.0);
+  }
+  c.n_groups = 5;
+  c.trunc = t;
+  c.out.user = out;
+  return run_call(ar, ws, stream, c);
+}
+
+int pauli_norm2(const pauli_op* A, double* out, pauli_ws* ws, void* stream_) {
+  if (!ws || !out || check_op(A, false)) return PAULI_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  Arena ar = make_arena(ws);
+  const int blocks = (int)std::min<int64_t>(std::max<int64_t>((A->size + 255) / 256, 1), 1024);
+  double2* part = (double2*)ar.take((size_t)blocks * 16);
+  double* res = (double*)ar.take(16);
+  if (ar.short_) return ws_short(ar, ws);
+  if (A->size == 0) {
+    *out = 0.0;
+    return PAULI_OK;
+  }
+  if (A->dtype == PAULI_C64K)
+    LAUNCH("k_norm_part", k_norm_part<true>, blocks, 256, A->coef, A->size, part);
+  else
+    LAUNCH("k_norm_part", k_norm_part<false>, blocks, 256, A->coef, A->size, part);
+  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, part, (uint32_t)blocks, res);
+  double h[2];
+  HIP_TRY(hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  *out = h[0];
+  return PAULI_OK;
+}
+
+int pauli_inner(const pauli_op* A, const pauli_op* B, double out[2], pauli_ws* ws,
+                void* stream_) {
+  if (!ws || !out || check_op(A, false) || check_op(B, false)) return PAULI_EINVAL;
+  if (A->n_qubits != B->n_qubits) return PAULI_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  Arena ar = make_arena(ws);
+  const int W = words_of(A->n_qubits);
+  const int blocks = (int)std::min<int64_t>(std::max<int64_t>((A->size + 255) / 256, 1), 1024);
+  Ctl* dctl = (Ctl*)ar.take(sizeof(Ctl));
+  void* bmk = ar.take((size_t)std::max<int64_t>(B->size, 1) * 16 * W);
+  double2* pr = (double2*)ar.take((size_t)blocks * 16);
+  double2* pi = (double2*)ar.take((size_t)blocks * 16);
+  double* res = (double*)ar.take(32);
+  if (ar.short_) return ws_short(ar, ws);
+  out[0] = out[1] = 0.0;
+  if (A->size == 0 || B->size == 0) return PAULI_OK;
+  {
+    const size_t words = sizeof(Ctl) / 4;
+    LAUNCH("k_fill_u32", k_fill_u32, (words + 255) / 256, 256, (uint32_t*)dctl, 0u, words);
+  }
+  if (W == 1) {
+    LAUNCH("k_mix_keys", k_mix_keys<1>, (B->size + 255) / 256, 256, B->x, B->z, B->capacity,
+           B->size, (Key<1>*)bmk, &dctl->bad_keep);
+    LAUNCH("k_inner_part", k_inner_part<1>, blocks, 256, A->x, A->z, A->capacity, A->size,
+           A->coef, A->dtype == PAULI_C64K, (const Key<1>*)bmk, B->size, B->coef,
+           B->dtype == PAULI_C64K, pr, pi);
+  } else {
+    LAUNCH("k_mix_keys", k_mix_keys<2>, (B->size + 255) / 256, 256, B->x, B->z, B->capacity,
+           B->size, (Key<2>*)bmk, &dctl->bad_keep);
+    LAUNCH("k_inner_part", k_inner_part<2>, blocks, 256, A->x, A->z, A->capacity, A->size,
+           A->coef, A->dtype == PAULI_C64K, (const Key<2>*)bmk, B->size, B->coef,
+           B->dtype == PAULI_C64K, pr, pi);
+  }
+  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, pr, (uint32_t)blocks, res);
+  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, pi, (uint32_t)blocks, res + 2);
+  double h[4];
+  unsigned int bad = 0;
+  HIP_TRY(hipMemcpyAsync(h, res, 32, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&bad, &dctl->bad_keep, 4, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  if (bad) return PAULI_EINVAL;
+  out[0] = h[0];
+  out[1] = h[2];
+  return PAULI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1242 @@
+// HIP kernels of the Pauli-string engine (gfx950, wave64).
+//
+// Data flow of one engine call (commutator, linear combination, truncation,
+// canonicalisation all use it):
+//   k_emit<COUNT>   pair loop over (H string, O string) -> for every
+//                   anticommuting pair the product string's mixed key picks a
+//                   hash bin; per-workgroup bin histograms (LDS) -> counts
+//                   matrix [rows][NBINS]; operator terms are binned the same way
+//   k_scan_cols / k_scan_bins
+//                   column prefix of the counts matrix, bin bases, bucket sizes
+//   k_emit<SCATTER> the same pair loop, writing records (mixed key, value,
+//                   source id) at their bin's cursor
+//   k_merge         one workgroup per bucket of bins: records -> LDS, counting
+//                   sort on the next 11 key bits + insertion sort per thread
+//                   range, then every run of equal keys is folded in ascending
+//                   source id (the canonical summation order), filtered, and
+//                   written compactly; exponent histogram of |c|^2 for top-M
+//   k_select / k_level1 / k_cand_level / k_finish / k_count_boundary
+//                   exact radix select of the M-th largest (|c|^2, key) pair
+//   k_scan_buckets / k_write
+//                   bucket output bases, stable compaction into the caller's
+//                   word-major output
+#pragma once
+#include <type_traits>
+
+#include "device_common.hpp"
+
+namespace pauli {
+
+enum GroupKind : int { G_TERM = 0, G_SUM = 1, G_SUM_KAHAN32 = 2 };
+enum AlphaKind : int { A_GENERAL = 0, A_ONE = 1, A_I = 2 };
+enum MergeMode : int { M_PLAIN = 0, M_LANCZOS = 1 };
+constexpr int MAX_GROUPS = 8;
+constexpr int MAX_TERMS = 6;
+
+struct Ctl {
+  unsigned long long pe_total;   // records emitted in this pass
+  unsigned int maxg[8];          // max records over aligned groups of 2^k bins
+  unsigned int overflow;         // a bucket exceeded MERGE_CAP / u32 overflow
+  unsigned int bad_keep;         // keep set not canonical
+  unsigned long long u_slots;    // U slots written by the merges
+  unsigned long long surv_total; // survivors after filters (incl. keep)
+  unsigned long long keep_total; // keep-set survivors
+  unsigned long long cand_n[3];  // candidate list sizes
+  unsigned long long sel_K;      // records still needed inside the chosen bin
+  unsigned long long sel_count;  // records in the chosen bin
+  unsigned int sel_digit;
+  unsigned int t_found;
+  unsigned long long T[8];       // threshold composite (m2 bits, ~key words)
+  unsigned long long out_total;
+  double norm_hi, norm_lo;
+  double inner[4];
+};
+
+struct EmitArgs {
+  // commutator group: H packed [nH][2W] raw words, O word-major
+  const uint64_t* Hk;
+  const double2* Hc;
+  int nH;
+  int has_comm;
+  int comm_rows;
+  uint32_t comm_group;
+  const uint64_t* Ox;
+  const uint64_t* Oz;
+  int64_t Ocap;
+  int64_t nO;
+  const void* Oc;
+  // operator terms
+  int n_terms;
+  int term_rows;
+  const uint64_t* tx[MAX_TERMS];
+  const uint64_t* tz[MAX_TERMS];
+  int64_t tcap[MAX_TERMS];
+  const void* tc[MAX_TERMS];
+  int tf32[MAX_TERMS];
+  uint32_t tgroup[MAX_TERMS];
+  int tlist[MAX_TERMS];
+  int64_t tstart[MAX_TERMS + 1];
+  // binning
+  int pass_bits;
+  uint32_t pass_id;
+  uint32_t* counts;
+  const uint32_t* bin_base;
+  void* rkey;
+  void* rval;
+  uint32_t* rsrc;
+};
+
+template <bool F32>
+using RecV = typename std::conditional<F32, float2, double2>::type;
+
+template <int W, bool F32, bool SCATTER>
+__global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
+  using V = RecV<F32>;
+  __shared__ uint32_t hist[NBINS];
+  __shared__ uint32_t queue[EMIT_THREADS / 64][128];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int row = blockIdx.x;
+  if (SCATTER) {
+    const uint32_t* crow = a.counts + (size_t)row * NBINS;
+    for (int i = tid; i < NBINS; i += EMIT_THREADS) hist[i] = a.bin_base[i] + crow[i];
+  } else {
+    for (int i = tid; i < NBINS; i += EMIT_THREADS) hist[i] = 0u;
+  }
+  __syncthreads();
+  Key<W>* rkey = reinterpret_cast<Key<W>*>(a.rkey);
+  V* rval = reinterpret_cast<V*>(a.rval);
+
+  auto deposit = [&](const Key<W>& raw, V val, uint32_t src) {
+    const Key<W> mk = mix_key<W>(raw);
+    uint64_t top = mk.w[0];
+    if (a.pass_bits) {
+      if ((uint32_t)(top >> (64 - a.pass_bits)) != a.pass_id) return;
+      top <<= a.pass_bits;
+    }
+    const uint32_t bin = (uint32_t)(top >> (64 - NBINS_LOG));
+    const uint32_t pos = atomicAdd(&hist[bin], 1u);
+    if (SCATTER) {
+      rkey[pos] = mk;
+      rval[pos] = val;
+      a.rsrc[pos] = src;
+    }
+  };
+
+  if (a.has_comm && row < a.comm_rows) {
+    const V* Oc = reinterpret_cast<const V*>(a.Oc);
+    const int64_t ntiles = (a.nO + EMIT_THREADS - 1) / EMIT_THREADS;
+    for (int64_t tile = row; tile < ntiles; tile += a.comm_rows) {
+      const int64_t i = tile * EMIT_THREADS + tid;
+      const bool valid = i < a.nO;
+      uint64_t xb[W], zb[W];
+      V cb;
+#pragma unroll
+      for (int w = 0; w < W; w++) {
+        xb[w] = valid ? a.Ox[(size_t)w * a.Ocap + i] : 0ull;
+        zb[w] = valid ? a.Oz[(size_t)w * a.Ocap + i] : 0ull;
+      }
+      if (valid) cb = Oc[i];
+      else { cb.x = 0; cb.y = 0; }
+
+      // Handle one queued (lane, H index) pair per lane.
+      auto process = [&](uint32_t entry, bool active) {
+        const int src_lane = (int)(entry & 63u);
+        const int h = (int)(entry >> 6);
+        uint64_t bx[W], bz[W];
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+          bx[w] = __shfl(xb[w], src_lane, 64);
+          bz[w] = __shfl(zb[w], src_lane, 64);
+        }
+        V bc;
+        bc.x = __shfl(cb.x, src_lane, 64);
+        bc.y = __shfl(cb.y, src_lane, 64);
+        if (!active) return;
+        const uint64_t* hk = a.Hk + (size_t)h * (2 * W);
+        Key<W> c;
+        int pa = 0, pb = 0, pz = 0, pc = 0;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+          const uint64_t ax = hk[w], az = hk[W + w];
+          c.w[w] = ax ^ bx[w];
+          c.w[W + w] = az ^ bz[w];
+          pa += __popcll(ax & az);
+          pb += __popcll(bx[w] & bz[w]);
+          pz += __popcll(az & bx[w]);
+          pc += __popcll(c.w[w] & c.w[W + w]);
+        }
+        // P_a P_b = i^(pa + pb + 2 pop(z_a & x_b) - pc) P_c; anticommuting
+        // pairs contribute 2 i^e h_a c_b to [P_a, P_b] h_a c_b.
+        const int e = (pa + pb + 2 * pz - pc) & 3;
+        const double2 hd = a.Hc[h];
+        V hc;
+        hc.x = hd.x;
+        hc.y = hd.y;
+        V prod;
+        if constexpr (F32) prod = cmulf(hc, bc);
+        else prod = cmul(hc, bc);
+        deposit(c, times_2ie(prod, e), (a.comm_group << GROUP_SHIFT) | (uint32_t)h);
+      };
+
+      uint32_t qn = 0;  // wave-uniform queue fill
+      for (int h = 0; h < a.nH; ++h) {
+        const uint64_t* hk = a.Hk + (size_t)h * (2 * W);
+        uint32_t par = 0;
+#pragma unroll
+        for (int w = 0; w < W; w++) par += __popcll((hk[w] & zb[w]) ^ (hk[W + w] & xb[w]));
+        const bool emit = valid && (par & 1u);
+        const uint64_t m = __ballot(emit);
+        if (m) {
+          const uint32_t pos = qn + mbcnt64(m);
+          if (emit) queue[wv][pos] = (uint32_t)lane | ((uint32_t)h << 6);
+          qn += (uint32_t)__popcll(m);
+          if (qn >= 64) {
+            wave_sync();
+            process(queue[wv][lane], true);
+            const uint32_t rem = qn - 64;
+            const uint32_t mv = (uint32_t)lane < rem ? queue[wv][64 + lane] : 0u;
+            wave_sync();
+            if ((uint32_t)lane < rem) queue[wv][lane] = mv;
+            wave_sync();
+            qn = rem;
+          }
+        }
+      }
+      if (qn) {
+        wave_sync();
+        process(queue[wv][lane], (uint32_t)lane < qn);
+        wave_sync();
+      }
+    }
+  } else if (a.n_terms > 0) {
+    const int trow = row - (a.has_comm ? a.comm_rows : 0);
+    const int64_t total = a.tstart[a.n_terms];
+    const int64_t ntiles = (total + EMIT_THREADS - 1) / EMIT_THREADS;
+    for (int64_t tile = trow; tile < ntiles; tile += a.term_rows) {
+      const int64_t v = tile * EMIT_THREADS + tid;
+      if (v < total) {
+        int t = 0;
+        while (t + 1 < a.n_terms && v >= a.tstart[t + 1]) t++;
+        const int64_t k = v - a.tstart[t];
+        Key<W> raw;
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+          raw.w[w] = a.tx[t][(size_t)w * a.tcap[t] + k];
+          raw.w[W + w] = a.tz[t][(size_t)w * a.tcap[t] + k];
+        }
+        V val;
+        if (a.tf32[t]) {
+          const float2 f = reinterpret_cast<const float2*>(a.tc[t])[k];
+          val.x = f.x;
+          val.y = f.y;
+        } else {
+          const double2 d = reinterpret_cast<const double2*>(a.tc[t])[k];
+          val.x = d.x;
+          val.y = d.y;
+        }
+        const uint32_t src = (a.tgroup[t] << GROUP_SHIFT) | (a.tlist[t] ? (uint32_t)k : 0u);
+        deposit(raw, val, src);
+      }
+    }
+  }
+  __syncthreads();
+  if (!SCATTER) {
+    uint32_t* crow = a.counts + (size_t)row * NBINS;
+    for (int i = tid; i < NBINS; i += EMIT_THREADS) crow[i] = hist[i];
+  }
+}
+
+// Column-wise exclusive prefix of the counts matrix; bin totals.
+__global__ void k_scan_cols(uint32_t* counts, int rows, uint32_t* bin_total, Ctl* ctl) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= NBINS) return;
+  unsigned long long run = 0;
+  for (int r = 0; r < rows; ++r) {
+    const size_t idx = (size_t)r * NBINS + b;
+    const uint32_t c = counts[idx];
+    counts[idx] = (uint32_t)run;
+    run += c;
+  }
+  if (run > 0xFFFFFFFFull) atomicOr(&ctl->overflow, 2u);
+  bin_total[b] = (uint32_t)run;
+}
+
+// Exclusive scan of the bin totals (one block of 1024 threads, 16 bins each)
+// and the largest total over aligned groups of 1, 2, 4, 8, 16 bins.
+__global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, uint32_t* bin_base,
+                                                    Ctl* ctl) {
+  __shared__ unsigned long long tmp[1024 / 64 + 1];
+  __shared__ unsigned int gmax[5];
+  const int t = threadIdx.x;
+  if (t < 5) gmax[t] = 0;
+  uint32_t v[16];
+  unsigned long long s = 0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    v[k] = bin_total[t * 16 + k];
+    s += v[k];
+  }
+  unsigned int lm[5];
+#pragma unroll
+  for (int lg = 0; lg < 5; lg++) {
+    const int g = 1 << lg;
+    unsigned int best = 0;
+    for (int k = 0; k < 16; k += g) {
+      unsigned long long acc = 0;
+      for (int q = 0; q < g; q++) acc += v[k + q];
+      if (acc > best) best = acc > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned int)acc;
+    }
+    lm[lg] = best;
+  }
+  // block exclusive scan (u64)
+  const int lane = t & 63, wv = t >> 6;
+  unsigned long long x = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    unsigned long long y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) tmp[wv] = x;
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long run = 0;
+    for (int i = 0; i < 16; i++) {
+      unsigned long long q = tmp[i];
+      tmp[i] = run;
+      run += q;
+    }
+    tmp[16] = run;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int lg = 0; lg < 5; lg++) atomicMax(&gmax[lg], lm[lg]);
+  unsigned long long pre = tmp[wv] + x - s;
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    bin_base[t * 16 + k] = (uint32_t)pre;
+    pre += v[k];
+  }
+  __syncthreads();
+  if (t == 0) {
+    bin_base[NBINS] = (uint32_t)tmp[16];
+    ctl->pe_total = tmp[16];
+    if (tmp[16] > 0xFFFFFFFFull) ctl->overflow |= 2u;
+    for (int lg = 0; lg < 5; lg++) ctl->maxg[lg] = gmax[lg];
+  }
+}
+
+struct MergeArgs {
+  const uint32_t* bin_base;
+  int g_log;
+  int digit_shift;
+  const void* rkey;
+  const void* rval;
+  const uint32_t* rsrc;
+  double2 alpha[MAX_GROUPS];
+  int alpha_kind[MAX_GROUPS];
+  int gkind[MAX_GROUPS];
+  int mode;
+  int round32;
+  int max_len;
+  int use_eps;
+  double eps2;
+  const void* keep_mk;
+  int n_keep;
+  unsigned long long u_off;
+  void* uk;
+  double2* uc;
+  uint32_t bucket_off;
+  uint32_t* b_ubase;
+  uint32_t* b_slots;
+  uint32_t* b_surv;
+  uint32_t* b_keep;
+  uint32_t* hist0;
+  double2* norm_part;
+  Ctl* ctl;
+};
+
+template <int W>
+DEV bool keep_lookup(const Key<W>* keep, int n, const Key<W>& mk) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const int c = key_cmp<W>(keep[mid], mk);
+    if (c == 0) return true;
+    if (c < 0) lo = mid + 1;
+    else hi = mid;
+  }
+  return false;
+}
+
+DEV double2 apply_alpha(const MergeArgs& a, int g, double2 v) {
+  const int k = a.alpha_kind[g];
+  if (k == A_ONE) return v;
+  if (k == A_I) return make_double2(-v.y, v.x);
+  return cmul(a.alpha[g], v);
+}
+
+DEV double round_to_f32(double v) { return (double)(float)v; }
+
+template <int W, bool F32>
+__global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
+  using V = RecV<F32>;
+  constexpr int PER = MERGE_CAP / MERGE_THREADS;
+  constexpr int DPT = NDIGITS / MERGE_THREADS;
+  __shared__ Key<W> mk[MERGE_CAP];
+  __shared__ uint32_t sx[MERGE_CAP];
+  __shared__ uint16_t perm[MERGE_CAP];
+  __shared__ uint32_t dh[NDIGITS];
+  __shared__ uint32_t h0[SEL0_BINS];
+  __shared__ uint32_t scan_tmp[MERGE_THREADS / 64 + 1];
+  __shared__ double red_hi[MERGE_THREADS / 64], red_lo[MERGE_THREADS / 64];
+
+  const int tid = threadIdx.x;
+  const uint32_t j = blockIdx.x;
+  const uint32_t gb = a.bucket_off + j;
+  const uint32_t b0 = a.bin_base[j << a.g_log];
+  const uint32_t b1 = a.bin_base[(j + 1) << a.g_log];
+  const uint32_t n = b1 - b0;
+  const unsigned long long ub = a.u_off + b0;
+  if (n > (uint32_t)MERGE_CAP) {
+    if (tid == 0) {
+      atomicOr(&a.ctl->overflow, 1u);
+      a.b_ubase[gb] = (uint32_t)ub;
+      a.b_slots[gb] = 0;
+      a.b_surv[gb] = 0;
+      a.b_keep[gb] = 0;
+      if (a.mode == M_LANCZOS) a.norm_part[gb] = make_double2(0.0, 0.0);
+    }
+    return;
+  }
+  for (int i = tid; i < NDIGITS; i += MERGE_THREADS) dh[i] = 0u;
+  if (a.mode == M_PLAIN)
+    for (int i = tid; i < SEL0_BINS; i += MERGE_THREADS) h0[i] = 0u;
+  __syncthreads();
+
+  const Key<W>* rk = reinterpret_cast<const Key<W>*>(a.rkey) + b0;
+  const V* rv = reinterpret_cast<const V*>(a.rval) + b0;
+  const uint32_t* rs = a.rsrc + b0;
+  uint32_t dig[PER], rnk[PER];
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const uint32_t i = tid + k * MERGE_THREADS;
+    dig[k] = 0;
+    rnk[k] = 0;
+    if (i < n) {
+      const Key<W> m = rk[i];
+      mk[i] = m;
+      sx[i] = rs[i];
+      dig[k] = (uint32_t)((m.w[0] << a.digit_shift) >> (64 - DIGIT_BITS));
+      rnk[k] = atomicAdd(&dh[dig[k]], 1u);
+    }
+  }
+  __syncthreads();
+  {
+    uint32_t loc[DPT], s = 0;
+#pragma unroll
+    for (int q = 0; q < DPT; q++) {
+      loc[q] = dh[tid * DPT + q];
+      s += loc[q];
+    }
+    uint32_t tot;
+    uint32_t pre = block_exclusive_scan(s, scan_tmp, &tot);
+#pragma unroll
+    for (int q = 0; q < DPT; q++) {
+      dh[tid * DPT + q] = pre;
+      pre += loc[q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const uint32_t i = tid + k * MERGE_THREADS;
+    if (i < n) perm[dh[dig[k]] + rnk[k]] = (uint16_t)i;
+  }
+  __syncthreads();
+  // This thread owns digits [tid*DPT, tid*DPT + DPT): sorted positions [s0, s1).
+  const uint32_t s0 = dh[tid * DPT];
+  const uint32_t s1 = (tid + 1) * DPT < NDIGITS ? dh[(tid + 1) * DPT] : n;
+  // insertion sort of the range by (mixed key, source id)
+  for (uint32_t p = s0 + 1; p < s1; ++p) {
+    const uint16_t v = perm[p];
+    const Key<W> kv = mk[v];
+    const uint32_t sv = sx[v];
+    int q = (int)p - 1;
+    while (q >= (int)s0) {
+      const uint16_t u = perm[q];
+      const int c = key_cmp<W>(mk[u], kv);
+      if (c < 0 || (c == 0 && sx[u] < sv)) break;
+      perm[q + 1] = u;
+      --q;
+    }
+    perm[q + 1] = v;
+  }
+
+  const Key<W>* keep = reinterpret_cast<const Key<W>*>(a.keep_mk);
+  // Fold the run [p, q) of equal keys: groups in ascending id, a SUM group
+  // adds its contributions in ascending source index, then
+  // acc = g0, acc = fl(acc + g1), ... after scaling each group by its alpha.
+  auto fold = [&](uint32_t p, uint32_t q, double2& out) -> bool {
+    bool present = false;
+    double2 acc = make_double2(0.0, 0.0);
+    int cur = -1;
+    double2 gs = make_double2(0.0, 0.0);
+    float kr = 0.f, kcr = 0.f, ki = 0.f, kci = 0.f;
+    auto finish = [&]() {
+      double2 gv;
+      if (a.gkind[cur] == G_SUM_KAHAN32) gv = make_double2((double)kr - (double)kcr,
+                                                           (double)ki - (double)kci);
+      else gv = gs;
+      gv = apply_alpha(a, cur, gv);
+      if (!present) acc = gv;
+      else acc = make_double2(acc.x + gv.x, acc.y + gv.y);
+      present = true;
+    };
+    for (uint32_t r = p; r < q; ++r) {
+      const uint16_t idx = perm[r];
+      const int g = (int)(sx[idx] >> GROUP_SHIFT);
+      const V v = rv[idx];
+      if (g != cur) {
+        if (cur >= 0) finish();
+        cur = g;
+        if (a.gkind[g] == G_SUM_KAHAN32) {
+          kr = 0.f; kcr = 0.f; ki = 0.f; kci = 0.f;
+          kahan_add(kr, kcr, (float)v.x);
+          kahan_add(ki, kci, (float)v.y);
+        } else {
+          gs = make_double2((double)v.x, (double)v.y);
+        }
+      } else {
+        if (a.gkind[g] == G_SUM_KAHAN32) {
+          kahan_add(kr, kcr, (float)v.x);
+          kahan_add(ki, kci, (float)v.y);
+        } else {
+          gs = make_double2(gs.x + (double)v.x, gs.y + (double)v.y);
+        }
+      }
+    }
+    if (cur >= 0) finish();
+    if (a.round32) acc = make_double2(round_to_f32(acc.x), round_to_f32(acc.y));
+    out = acc;
+    return !is_zero(acc);
+  };
+  // Filters of the plain mode; returns survival, sets keep membership.
+  auto filters = [&](const Key<W>& m, double2 v, bool& is_keep) -> bool {
+    is_keep = false;
+    if (a.max_len > 0) {
+      const Key<W> raw = unmix_key<W>(m);
+      if (key_length<W>(raw) > a.max_len) return false;
+    }
+    if (a.use_eps && !(weight2(v) >= a.eps2)) return false;
+    if (a.n_keep) is_keep = keep_lookup<W>(keep, a.n_keep, m);
+    return true;
+  };
+
+  // sweep 1: count survivors
+  uint32_t cnt = 0, kc = 0;
+  dd nrm = dd_zero();
+  for (uint32_t p = s0; p < s1;) {
+    uint32_t q = p + 1;
+    const Key<W> kp = mk[perm[p]];
+    while (q < s1 && key_eq<W>(mk[perm[q]], kp)) ++q;
+    double2 v;
+    if (fold(p, q, v)) {
+      if (a.mode == M_LANCZOS) {
+        cnt++;
+        nrm = dd_add(nrm, weight2(v));
+      } else {
+        bool isk;
+        if (filters(kp, v, isk)) {
+          cnt++;
+          if (isk) kc++;
+          else {
+            const double m2 = weight2(v);
+            atomicAdd(&h0[(uint32_t)(__double_as_longlong(m2) >> 52)], 1u);
+          }
+        }
+      }
+    }
+    p = q;
+  }
+  uint32_t tot_cnt, tot_kc;
+  const uint32_t off = block_exclusive_scan(cnt, scan_tmp, &tot_cnt);
+  (void)block_exclusive_scan(kc, scan_tmp, &tot_kc);
+
+  // sweep 2: write survivors (raw keys) to U
+  if (cnt) {
+    Key<W>* uk = reinterpret_cast<Key<W>*>(a.uk) + ub;
+    double2* uc = a.uc + ub;
+    uint32_t o = off;
+    for (uint32_t p = s0; p < s1;) {
+      uint32_t q = p + 1;
+      const Key<W> kp = mk[perm[p]];
+      while (q < s1 && key_eq<W>(mk[perm[q]], kp)) ++q;
+      double2 v;
+      if (fold(p, q, v)) {
+        bool isk = false;
+        if (a.mode == M_LANCZOS || filters(kp, v, isk)) {
+          uk[o] = unmix_key<W>(kp);
+          uc[o] = v;
+          ++o;
+        }
+      }
+      p = q;
+    }
+  }
+  if (a.mode == M_LANCZOS) {
+    // block reduction of the double-double norm partial, fixed order
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int d = 32; d >= 1; d >>= 1) {
+      dd o2;
+      o2.hi = __shfl_down(nrm.hi, d, 64);
+      o2.lo = __shfl_down(nrm.lo, d, 64);
+      if (lane < d) nrm = dd_add(nrm, o2);
+    }
+    if (lane == 0) {
+      red_hi[wv] = nrm.hi;
+      red_lo[wv] = nrm.lo;
+    }
+  }
+  __syncthreads();
+  if (a.mode == M_PLAIN) {
+    for (int i = tid; i < SEL0_BINS; i += MERGE_THREADS)
+      if (h0[i]) atomicAdd(&a.hist0[i], h0[i]);
+  }
+  if (tid == 0) {
+    a.b_ubase[gb] = (uint32_t)ub;
+    a.b_slots[gb] = tot_cnt;
+    a.b_surv[gb] = tot_cnt;
+    a.b_keep[gb] = tot_kc;
+    atomicAdd(&a.ctl->u_slots, (unsigned long long)tot_cnt);
+    atomicAdd(&a.ctl->surv_total, (unsigned long long)tot_cnt);
+    atomicAdd(&a.ctl->keep_total, (unsigned long long)tot_kc);
+    if (a.mode == M_LANCZOS) {
+      dd s = {red_hi[0], red_lo[0]};
+      for (int w = 1; w < MERGE_THREADS / 64; w++) s = dd_add(s, dd{red_hi[w], red_lo[w]});
+      a.norm_part[gb] = make_double2(s.hi, s.lo);
+    }
+  }
+}
+
+// Deterministic double-double sum of n partials (one block).
+__global__ __launch_bounds__(256) void k_reduce_dd(const double2* part, uint32_t n, double* out) {
+  __shared__ double rh[4], rl[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  dd s = dd_zero();
+  for (uint32_t i = tid; i < n; i += 256) s = dd_add(s, dd{part[i].x, part[i].y});
+  for (int d = 32; d >= 1; d >>= 1) {
+    dd o;
+    o.hi = __shfl_down(s.hi, d, 64);
+    o.lo = __shfl_down(s.lo, d, 64);
+    if (lane < d) s = dd_add(s, o);
+  }
+  if (lane == 0) {
+    rh[wv] = s.hi;
+    rl[wv] = s.lo;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    dd t = {rh[0], rl[0]};
+    for (int w = 1; w < 4; w++) t = dd_add(t, dd{rh[w], rl[w]});
+    out[0] = t.hi;
+    out[1] = t.lo;
+  }
+}
+
+// Lanczos: divide the merged O'_n by b_n (IEEE division), round to FP32 when
+// the result is stored in FP32, then apply the plain-mode filters; dropped
+// strings become exact zeros in place.
+struct ScaleArgs {
+  const uint32_t* b_ubase;
+  const uint32_t* b_slots;
+  uint32_t* b_surv;
+  uint32_t* b_keep;
+  void* uk;
+  double2* uc;
+  double bnorm;
+  int round32;
+  int max_len;
+  int use_eps;
+  double eps2;
+  const void* keep_mk;
+  int n_keep;
+  uint32_t* hist0;
+  Ctl* ctl;
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void k_scale_filter(ScaleArgs a) {
+  __shared__ uint32_t h0[SEL0_BINS];
+  __shared__ uint32_t rs[4], rk[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t b = blockIdx.x;
+  for (int i = tid; i < SEL0_BINS; i += 256) h0[i] = 0u;
+  __syncthreads();
+  const uint32_t ub = a.b_ubase[b], ns = a.b_slots[b];
+  const Key<W>* uk = reinterpret_cast<const Key<W>*>(a.uk) + ub;
+  double2* uc = a.uc + ub;
+  const Key<W>* keep = reinterpret_cast<const Key<W>*>(a.keep_mk);
+  uint32_t surv = 0, kc = 0;
+  for (uint32_t i = tid; i < ns; i += 256) {
+    double2 v = uc[i];
+    v = make_double2(v.x / a.bnorm, v.y / a.bnorm);
+    if (a.round32) v = make_double2(round_to_f32(v.x), round_to_f32(v.y));
+    bool ok = !is_zero(v);
+    const Key<W> raw = uk[i];
+    if (ok && a.max_len > 0 && key_length<W>(raw) > a.max_len) ok = false;
+    if (ok && a.use_eps && !(weight2(v) >= a.eps2)) ok = false;
+    if (ok) {
+      surv++;
+      bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mix_key<W>(raw)) : false;
+      if (isk) kc++;
+      else atomicAdd(&h0[(uint32_t)(__double_as_longlong(weight2(v)) >> 52)], 1u);
+    } else {
+      v = make_double2(0.0, 0.0);
+    }
+    uc[i] = v;
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    surv += __shfl_down(surv, d, 64);
+    kc += __shfl_down(kc, d, 64);
+  }
+  if (lane == 0) {
+    rs[wv] = surv;
+    rk[wv] = kc;
+  }
+  __syncthreads();
+  for (int i = tid; i < SEL0_BINS; i += 256)
+    if (h0[i]) atomicAdd(&a.hist0[i], h0[i]);
+  if (tid == 0) {
+    const uint32_t s = rs[0] + rs[1] + rs[2] + rs[3];
+    const uint32_t k = rk[0] + rk[1] + rk[2] + rk[3];
+    a.b_surv[b] = s;
+    a.b_keep[b] = k;
+    atomicAdd(&a.ctl->surv_total, (unsigned long long)s);
+    atomicAdd(&a.ctl->keep_total, (unsigned long long)k);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Top-M selection: exact radix select over the composite ordering key
+// (|c|^2 bits, then the complemented key words x[W-1]..x[0], z[W-1]..z[0]):
+// larger composite = kept first.  Digit 0 = the 11 exponent bits of |c|^2,
+// digit L >= 1 = the 12 bits at position 12L of the composite bit string.
+// ---------------------------------------------------------------------------
+template <int W>
+DEV void composite(double2 v, const Key<W>& raw, uint64_t* c) {
+  c[0] = (uint64_t)__double_as_longlong(weight2(v));
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    c[1 + i] = ~raw.w[W - 1 - i];
+    c[1 + W + i] = ~raw.w[2 * W - 1 - i];
+  }
+}
+
+template <int W>
+DEV uint32_t comp_digit(const uint64_t* c, int level) {
+  if (level == 0) return (uint32_t)(c[0] >> 52);
+  const int p = 12 * level;
+  const int wi = p >> 6, off = p & 63;
+  constexpr int NW = 1 + 2 * W;
+  const uint64_t hi = wi < NW ? c[wi] : 0ull;
+  const uint64_t lo = wi + 1 < NW ? c[wi + 1] : 0ull;
+  const uint64_t v = off ? ((hi << off) | (lo >> (64 - off))) : hi;
+  return (uint32_t)(v >> 52);
+}
+
+template <int W>
+DEV int comp_cmp(const uint64_t* a, const uint64_t* b) {
+#pragma unroll
+  for (int i = 0; i < 1 + 2 * W; i++)
+    if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+  return 0;
+}
+
+// Pick the bin holding the K-th largest: K from ctl->sel_K (1-based).
+__global__ __launch_bounds__(1024) void k_select(const uint32_t* hist, int nbins, Ctl* ctl) {
+  __shared__ unsigned long long tmp[17];
+  __shared__ unsigned long long Ks;
+  const int t = threadIdx.x;
+  if (t == 0) Ks = ctl->sel_K;
+  const int per = nbins / 1024;  // nbins is 2048 or 4096
+  // thread t owns bins [nbins - (t+1)*per, nbins - t*per), scanned high to low
+  const int hiB = nbins - t * per;
+  unsigned long long s = 0;
+  for (int q = 1; q <= per; q++) s += hist[hiB - q];
+  const int lane = t & 63, wv = t >> 6;
+  unsigned long long x = s;
+  for (int d = 1; d < 64; d <<= 1) {
+    unsigned long long y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) tmp[wv] = x;
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long run = 0;
+    for (int i = 0; i < 16; i++) {
+      unsigned long long q = tmp[i];
+      tmp[i] = run;
+      run += q;
+    }
+  }
+  __syncthreads();
+  const unsigned long long K = Ks;
+  unsigned long long cum = tmp[wv] + x - s;  // records in bins above this thread's
+  for (int q = 1; q <= per; q++) {
+    const int b = hiB - q;
+    const unsigned long long h = hist[b];
+    if (cum < K && K <= cum + h) {
+      ctl->sel_digit = (unsigned int)b;
+      ctl->sel_K = K - cum;
+      ctl->sel_count = h;
+    }
+    cum += h;
+  }
+}
+
+struct SelArgs {
+  const uint32_t* b_ubase;
+  const uint32_t* b_slots;
+  uint32_t* b_abv;
+  uint32_t* b_bcnt;
+  const void* uk;
+  const double2* uc;
+  const void* keep_mk;
+  int n_keep;
+  uint32_t* cand_in;   // pairs (U index, bucket)
+  uint32_t* cand_out;
+  unsigned long long cand_cap;
+  int level;
+  uint32_t* hist;      // next-level histogram (SEL_BINS)
+  Ctl* ctl;
+  int in_slot, out_slot;
+};
+
+DEV uint32_t wave_append(unsigned long long* counter, bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (!m) return 0;
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0;
+  if ((int)__lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader, 64);
+  return (uint32_t)(base + mbcnt64(m));
+}
+
+// Level 1: full pass over U.  Counts per bucket the non-keep survivors whose
+// digit 0 is above the chosen bin, collects the chosen bin's records and
+// histograms their digit 1.
+template <int W>
+__global__ __launch_bounds__(256) void k_level1(SelArgs a) {
+  __shared__ uint32_t h[SEL_BINS];
+  __shared__ uint32_t ra[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t b = blockIdx.x;
+  for (int i = tid; i < SEL_BINS; i += 256) h[i] = 0u;
+  __syncthreads();
+  const uint32_t D = a.ctl->sel_digit;
+  const uint32_t ub = a.b_ubase[b], ns = a.b_slots[b];
+  const Key<W>* uk = reinterpret_cast<const Key<W>*>(a.uk) + ub;
+  const double2* uc = a.uc + ub;
+  const Key<W>* keep = reinterpret_cast<const Key<W>*>(a.keep_mk);
+  uint32_t abv = 0;
+  const uint32_t nround = (ns + 255) / 256;
+  for (uint32_t r = 0; r < nround; r++) {
+    const uint32_t i = r * 256 + tid;
+    bool cand = false;
+    uint64_t c[1 + 2 * W];
+    if (i < ns) {
+      const double2 v = uc[i];
+      if (!is_zero(v)) {
+        const Key<W> raw = uk[i];
+        const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mix_key<W>(raw)) : false;
+        if (!isk) {
+          composite<W>(v, raw, c);
+          const uint32_t d0 = comp_digit<W>(c, 0);
+          if (d0 > D) abv++;
+          else if (d0 == D) cand = true;
+        }
+      }
+    }
+    const uint32_t pos = wave_append(&a.ctl->cand_n[a.out_slot], cand);
+    if (cand && pos < a.cand_cap) {
+      a.cand_out[2 * (size_t)pos] = ub + i;
+      a.cand_out[2 * (size_t)pos + 1] = b;
+      atomicAdd(&h[comp_digit<W>(c, 1)], 1u);
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) abv += __shfl_down(abv, d, 64);
+  if (lane == 0) ra[wv] = abv;
+  __syncthreads();
+  for (int i = tid; i < SEL_BINS; i += 256)
+    if (h[i]) atomicAdd(&a.hist[i], h[i]);
+  if (tid == 0) a.b_abv[b] = ra[0] + ra[1] + ra[2] + ra[3];
+}
+
+// Level L >= 1 over a candidate list: keep the records whose digit L equals
+// the chosen bin, histogram their digit L+1.
+template <int W>
+__global__ __launch_bounds__(256) void k_cand_level(SelArgs a) {
+  __shared__ uint32_t h[SEL_BINS];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < SEL_BINS; i += 256) h[i] = 0u;
+  __syncthreads();
+  const uint32_t D = a.ctl->sel_digit;
+  const unsigned long long n = a.ctl->cand_n[a.in_slot];
+  const Key<W>* ukb = reinterpret_cast<const Key<W>*>(a.uk);
+  const unsigned long long stride = (unsigned long long)gridDim.x * 256;
+  const unsigned long long nround = (n + stride - 1) / stride;
+  for (unsigned long long r = 0; r < nround; r++) {
+    const unsigned long long i = r * stride + (unsigned long long)blockIdx.x * 256 + tid;
+    bool keepit = false;
+    uint64_t c[1 + 2 * W];
+    uint32_t ui = 0, bk = 0;
+    if (i < n) {
+      ui = a.cand_in[2 * i];
+      bk = a.cand_in[2 * i + 1];
+      composite<W>(a.uc[ui], ukb[ui], c);
+      keepit = comp_digit<W>(c, a.level) == D;
+    }
+    const uint32_t pos = wave_append(&a.ctl->cand_n[a.out_slot], keepit);
+    if (keepit && pos < a.cand_cap) {
+      a.cand_out[2 * (size_t)pos] = ui;
+      a.cand_out[2 * (size_t)pos + 1] = bk;
+      atomicAdd(&h[comp_digit<W>(c, a.level + 1)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < SEL_BINS; i += 256)
+    if (h[i]) atomicAdd(&a.hist[i], h[i]);
+}
+
+// Final level: at most FINISH_CAP candidates of the chosen bin; the one of
+// rank K-1 (descending composite) is the threshold T.
+template <int W>
+__global__ __launch_bounds__(1024) void k_finish(SelArgs a) {
+  constexpr int NW = 1 + 2 * W;
+  __shared__ uint64_t cs[FINISH_CAP][NW];
+  __shared__ unsigned int m;
+  const int tid = threadIdx.x;
+  if (tid == 0) m = 0;
+  __syncthreads();
+  const uint32_t D = a.ctl->sel_digit;
+  const unsigned long long n = a.ctl->cand_n[a.in_slot];
+  const Key<W>* ukb = reinterpret_cast<const Key<W>*>(a.uk);
+  for (unsigned long long i = tid; i < n; i += 1024) {
+    uint64_t c[NW];
+    const uint32_t ui = a.cand_in[2 * i];
+    composite<W>(a.uc[ui], ukb[ui], c);
+    if (comp_digit<W>(c, a.level) == D) {
+      const unsigned int p = atomicAdd(&m, 1u);
+      if (p < FINISH_CAP)
+        for (int q = 0; q < NW; q++) cs[p][q] = c[q];
+    }
+  }
+  __syncthreads();
+  const unsigned int mm = m < FINISH_CAP ? m : FINISH_CAP;
+  const unsigned long long K = a.ctl->sel_K;
+  for (unsigned int i = tid; i < mm; i += 1024) {
+    unsigned int rank = 0;
+    for (unsigned int k = 0; k < mm; k++) rank += comp_cmp<W>(cs[k], cs[i]) > 0 ? 1u : 0u;
+    if ((unsigned long long)rank + 1 == K) {
+      for (int q = 0; q < NW; q++) a.ctl->T[q] = cs[i][q];
+      a.ctl->t_found = 1;
+    }
+  }
+}
+
+// Per bucket: level-1 candidates at or above the threshold.
+template <int W>
+__global__ __launch_bounds__(256) void k_count_boundary(SelArgs a) {
+  constexpr int NW = 1 + 2 * W;
+  const unsigned long long n = a.ctl->cand_n[a.in_slot];
+  uint64_t T[NW];
+  for (int q = 0; q < NW; q++) T[q] = a.ctl->T[q];
+  const Key<W>* ukb = reinterpret_cast<const Key<W>*>(a.uk);
+  for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * 256) {
+    const uint32_t ui = a.cand_in[2 * i], bk = a.cand_in[2 * i + 1];
+    uint64_t c[NW];
+    composite<W>(a.uc[ui], ukb[ui], c);
+    if (comp_cmp<W>(c, T) >= 0) atomicAdd(&a.b_bcnt[bk], 1u);
+  }
+}
+
+// Output bases: survivors per bucket are counted according to the select
+// mode; exclusive scan over the buckets (one block).
+enum SelMode : int { S_ALL = 0, S_KEEP_ONLY = 1, S_THRESHOLD = 2 };
+
+__global__ __launch_bounds__(1024) void k_scan_buckets(const uint32_t* b_surv,
+                                                       const uint32_t* b_keep,
+                                                       const uint32_t* b_abv,
+                                                       const uint32_t* b_bcnt, uint32_t nb,
+                                                       int sel_mode, uint32_t* b_obase, Ctl* ctl) {
+  __shared__ unsigned long long tmp[17];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const uint32_t per = (nb + 1023) / 1024;
+  const uint32_t lo = t * per;
+  unsigned long long s = 0;
+  for (uint32_t k = 0; k < per; k++) {
+    const uint32_t b = lo + k;
+    if (b < nb) {
+      uint32_t c = sel_mode == S_ALL ? b_surv[b]
+                   : sel_mode == S_KEEP_ONLY ? b_keep[b]
+                                             : b_keep[b] + b_abv[b] + b_bcnt[b];
+      s += c;
+    }
+  }
+  unsigned long long x = s;
+  for (int d = 1; d < 64; d <<= 1) {
+    unsigned long long y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) tmp[wv] = x;
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long run = 0;
+    for (int i = 0; i < 16; i++) {
+      unsigned long long q = tmp[i];
+      tmp[i] = run;
+      run += q;
+    }
+    tmp[16] = run;
+  }
+  __syncthreads();
+  unsigned long long pre = tmp[wv] + x - s;
+  for (uint32_t k = 0; k < per; k++) {
+    const uint32_t b = lo + k;
+    if (b < nb) {
+      b_obase[b] = (uint32_t)pre;
+      uint32_t c = sel_mode == S_ALL ? b_surv[b]
+                   : sel_mode == S_KEEP_ONLY ? b_keep[b]
+                                             : b_keep[b] + b_abv[b] + b_bcnt[b];
+      pre += c;
+    }
+  }
+  if (t == 0) ctl->out_total = tmp[16];
+}
+
+struct WriteArgs {
+  const uint32_t* b_ubase;
+  const uint32_t* b_slots;
+  const uint32_t* b_obase;
+  const void* uk;
+  const double2* uc;
+  const void* keep_mk;
+  int n_keep;
+  int sel_mode;
+  const Ctl* ctl;
+  uint64_t* ox;
+  uint64_t* oz;
+  void* oc;
+  int64_t ocap;
+  int out_f32;
+};
+
+template <int W>
+__global__ __launch_bounds__(256) void k_write(WriteArgs a) {
+  constexpr int NW = 1 + 2 * W;
+  __shared__ uint32_t scan_tmp[256 / 64 + 1];
+  const int tid = threadIdx.x;
+  const uint32_t b = blockIdx.x;
+  const uint32_t ub = a.b_ubase[b], ns = a.b_slots[b];
+  uint32_t obase = a.b_obase[b];
+  const Key<W>* uk = reinterpret_cast<const Key<W>*>(a.uk) + ub;
+  const double2* uc = a.uc + ub;
+  const Key<W>* keep = reinterpret_cast<const Key<W>*>(a.keep_mk);
+  uint64_t T[NW];
+  if (a.sel_mode == S_THRESHOLD)
+    for (int q = 0; q < NW; q++) T[q] = a.ctl->T[q];
+  const uint32_t nround = (ns + 255) / 256;
+  for (uint32_t r = 0; r < nround; r++) {
+    const uint32_t i = r * 256 + tid;
+    bool s = false;
+    Key<W> raw;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < ns) {
+      v = uc[i];
+      if (!is_zero(v)) {
+        raw = uk[i];
+        if (a.sel_mode == S_ALL) {
+          s = true;
+        } else {
+          const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mix_key<W>(raw)) : false;
+          if (isk) s = true;
+          else if (a.sel_mode == S_THRESHOLD) {
+            uint64_t c[NW];
+            composite<W>(v, raw, c);
+            s = comp_cmp<W>(c, T) >= 0;
+          }
+        }
+      }
+    }
+    uint32_t tot;
+    const uint32_t pos = block_exclusive_scan(s ? 1u : 0u, scan_tmp, &tot);
+    if (s) {
+      const size_t o = (size_t)obase + pos;
+#pragma unroll
+      for (int w = 0; w < W; w++) {
+        a.ox[(size_t)w * a.ocap + o] = raw.w[w];
+        a.oz[(size_t)w * a.ocap + o] = raw.w[W + w];
+      }
+      if (a.out_f32) reinterpret_cast<float2*>(a.oc)[o] = make_float2((float)v.x, (float)v.y);
+      else reinterpret_cast<double2*>(a.oc)[o] = v;
+    }
+    obase += tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void k_pack_keys(const uint64_t* x, const uint64_t* z, int64_t cap, int64_t n,
+                            uint64_t* packed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    packed[i * 2 * W + w] = x[(size_t)w * cap + i];
+    packed[i * 2 * W + W + w] = z[(size_t)w * cap + i];
+  }
+}
+
+// Mixed keys of a canonical operator; flags a violation of ascending order.
+template <int W>
+__global__ void k_mix_keys(const uint64_t* x, const uint64_t* z, int64_t cap, int64_t n,
+                           Key<W>* out, unsigned int* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Key<W> raw;
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    raw.w[w] = x[(size_t)w * cap + i];
+    raw.w[W + w] = z[(size_t)w * cap + i];
+  }
+  const Key<W> m = mix_key<W>(raw);
+  out[i] = m;
+  if (i > 0) {
+    Key<W> rp;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+      rp.w[w] = x[(size_t)w * cap + i - 1];
+      rp.w[W + w] = z[(size_t)w * cap + i - 1];
+    }
+    if (key_cmp<W>(mix_key<W>(rp), m) >= 0) atomicOr(bad, 1u);
+  }
+}
+
+// Partial double-double sums of |c|^2 per block.
+template <bool F32>
+__global__ __launch_bounds__(256) void k_norm_part(const void* coef, int64_t n, double2* part) {
+  __shared__ double rh[4], rl[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  dd s = dd_zero();
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
+    double2 v;
+    if (F32) {
+      const float2 f = reinterpret_cast<const float2*>(coef)[i];
+      v = make_double2(f.x, f.y);
+    } else {
+      v = reinterpret_cast<const double2*>(coef)[i];
+    }
+    s = dd_add(s, weight2(v));
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    dd o;
+    o.hi = __shfl_down(s.hi, d, 64);
+    o.lo = __shfl_down(s.lo, d, 64);
+    if (lane < d) s = dd_add(s, o);
+  }
+  if (lane == 0) {
+    rh[wv] = s.hi;
+    rl[wv] = s.lo;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    dd t = {rh[0], rl[0]};
+    for (int w = 1; w < 4; w++) t = dd_add(t, dd{rh[w], rl[w]});
+    part[blockIdx.x] = make_double2(t.hi, t.lo);
+  }
+}
+
+// Inner product partials: every string of A is looked up in B's mixed keys.
+template <int W>
+__global__ __launch_bounds__(256) void k_inner_part(const uint64_t* ax, const uint64_t* az,
+                                                    int64_t acap, int64_t na, const void* acoef,
+                                                    int af32, const Key<W>* bmk, int64_t nb,
+                                                    const void* bcoef, int bf32, double2* part_re,
+                                                    double2* part_im) {
+  __shared__ double rh[2][4], rl[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  dd sr = dd_zero(), si = dd_zero();
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < na; i += (int64_t)gridDim.x * 256) {
+    Key<W> raw;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+      raw.w[w] = ax[(size_t)w * acap + i];
+      raw.w[W + w] = az[(size_t)w * acap + i];
+    }
+    const Key<W> m = mix_key<W>(raw);
+    int64_t lo = 0, hi = nb;
+    int64_t found = -1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      const int c = key_cmp<W>(bmk[mid], m);
+      if (c == 0) {
+        found = mid;
+        break;
+      }
+      if (c < 0) lo = mid + 1;
+      else hi = mid;
+    }
+    if (found >= 0) {
+      double2 av, bv;
+      if (af32) {
+        const float2 f = reinterpret_cast<const float2*>(acoef)[i];
+        av = make_double2(f.x, f.y);
+      } else av = reinterpret_cast<const double2*>(acoef)[i];
+      if (bf32) {
+        const float2 f = reinterpret_cast<const float2*>(bcoef)[found];
+        bv = make_double2(f.x, f.y);
+      } else bv = reinterpret_cast<const double2*>(bcoef)[found];
+      const double p1 = av.x * bv.x, p2 = av.y * bv.y, p3 = av.x * bv.y, p4 = av.y * bv.x;
+      sr = dd_add(sr, p1);
+      sr = dd_add(sr, p2);
+      si = dd_add(si, p3);
+      si = dd_add(si, -p4);
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    dd o;
+    o.hi = __shfl_down(sr.hi, d, 64);
+    o.lo = __shfl_down(sr.lo, d, 64);
+    if (lane < d) sr = dd_add(sr, o);
+    o.hi = __shfl_down(si.hi, d, 64);
+    o.lo = __shfl_down(si.lo, d, 64);
+    if (lane < d) si = dd_add(si, o);
+  }
+  if (lane == 0) {
+    rh[0][wv] = sr.hi;
+    rl[0][wv] = sr.lo;
+    rh[1][wv] = si.hi;
+    rl[1][wv] = si.lo;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    dd t0 = {rh[0][0], rl[0][0]}, t1 = {rh[1][0], rl[1][0]};
+    for (int w = 1; w < 4; w++) {
+      t0 = dd_add(t0, dd{rh[0][w], rl[0][w]});
+      t1 = dd_add(t1, dd{rh[1][w], rl[1][w]});
+    }
+    part_re[blockIdx.x] = make_double2(t0.hi, t0.lo);
+    part_im[blockIdx.x] = make_double2(t1.hi, t1.lo);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace pauli

@@ -1,0 +1,66 @@
+"""CPU checks of the boundary: the HIP library loads and exports every entry
+point that include/pauli.h declares; host-side marshalling is consistent."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pauli.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(pauli_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["pauli_commutator", "pauli_add", "pauli_truncate", "pauli_rk4_step",
+                 "pauli_lanczos_step", "pauli_norm2", "pauli_inner", "pauli_canonicalize"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2410_09654_amd import _lib
+    L = _lib.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(_lib.EXPORTS) == set(declared_functions())
+
+
+def test_strerror_and_profile_calls_run_on_host():
+    from paper_2410_09654_amd import _lib
+    L = _lib.load()
+    assert L.pauli_strerror(0) == b"ok"
+    assert b"workspace" in L.pauli_strerror(3)
+    L.pauli_profile_enable(0)
+    assert L.pauli_profile_read(None, 0) >= 1
+
+
+def test_struct_layout_matches_header():
+    from paper_2410_09654_amd._lib import PauliOpC, PauliTruncC, PauliWsC
+    assert ctypes.sizeof(PauliOpC) == 4 + 4 + 8 + 8 + 8 * 3
+    assert PauliOpC.x.offset == 24
+    assert ctypes.sizeof(PauliTruncC) == 32
+    assert ctypes.sizeof(PauliWsC) == 24
+
+
+def test_invalid_arguments_rejected_without_gpu_work():
+    """Argument validation happens on the host before any HIP call."""
+    from paper_2410_09654_amd import _lib
+    L = _lib.load()
+    op = _lib.PauliOpC(200, 0, 0, 0, None, None, None)  # 200 qubits: unsupported
+    ws = _lib.PauliWsC(None, 0, 0)
+    rc = L.pauli_commutator(ctypes.byref(op), ctypes.byref(op), None, ctypes.byref(op),
+                            ctypes.byref(ws), None)
+    assert rc == _lib.PAULI_EINVAL
+    bad_dtype = _lib.PauliOpC(10, 7, 0, 0, None, None, None)
+    rc = L.pauli_truncate(ctypes.byref(bad_dtype), None, ctypes.byref(bad_dtype),
+                          ctypes.byref(ws), None)
+    assert rc == _lib.PAULI_EINVAL
+    rc = L.pauli_lanczos_step(ctypes.byref(op), None, ctypes.byref(op), 0.0, None, 1,
+                              ctypes.byref(op), None, ctypes.byref(ws), None)
+    assert rc == _lib.PAULI_EINVAL

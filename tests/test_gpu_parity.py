@@ -1,0 +1,286 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Keys must match bit for bit; FP64 coefficients within 1e-12 relative (the
+tolerance the method's FP64 path is held to).  Inputs are seeded synthetic
+operators from `workloads`.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from helpers import assert_canonical_unique, assert_same_operator, exact_fraction, gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2410_09654_amd as pk
+    pk._lib.load()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ws(pk):
+    return pk.Workspace(256 << 20)
+
+
+def up(pk, host, ws, dtype=0):
+    return pk.PauliOp.from_host(host, dtype=dtype, ws=ws)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ---------------------------------------------------------------------------
+# commutator
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,nh,no,seed", [(10, 20, 3000, 1), (64, 191, 2500, 2),
+                                          (100, 40, 1500, 3), (128, 30, 700, 4),
+                                          (1, 1, 1, 5)])
+def test_commutator_random(pk, ws, n, nh, no, seed):
+    say(f"commutator n={n} nh={nh} no={no} seed={seed}")
+    H = wl.random_operator(n, nh, seed=seed, density=min(1.0, 3.0 / n + 0.05))
+    O = wl.random_operator(n, no, seed=seed + 100, density=min(1.0, 6.0 / n + 0.05))
+    want = oracle.commutator(H, O)
+    got = pk.commutator(up(pk, H, ws), up(pk, O, ws), ws=ws).to_host()
+    assert_canonical_unique(got)
+    assert_same_operator(got, want, what="commutator")
+    assert exact_fraction(got, want) == 1.0
+
+
+def test_commutator_chain_local_strings_truncated(pk, ws):
+    say("commutator chain N=64, 6000 strings, L=12, M=5000")
+    H = wl.ising_chain(64)
+    O = wl.random_local_strings(64, 6000, 10, seed=7)
+    t = oracle.Trunc(max_len=8, max_strings=5000)
+    want = oracle.truncate(oracle.commutator(H, O), t)
+    got = pk.commutator(up(pk, H, ws), up(pk, O, ws), pk.Trunc(max_len=8, max_strings=5000),
+                        ws=ws).to_host()
+    assert got.n == want.n == 5000
+    assert_same_operator(got, want, what="truncated commutator")
+
+
+def test_commutator_order_is_canonical_and_deterministic(pk, ws):
+    say("determinism")
+    H = wl.ising_chain(64)
+    O = wl.random_local_strings(64, 20000, 10, seed=8)
+    Hd, Od = up(pk, H, ws), up(pk, O, ws)
+    a = pk.commutator(Hd, Od, pk.Trunc(max_strings=30000), ws=ws)
+    b = pk.commutator(Hd, Od, pk.Trunc(max_strings=30000), ws=ws)
+    n = a.size
+    assert n == b.size
+    assert (a.x[:, :n] == b.x[:, :n]).all() and (a.z[:, :n] == b.z[:, :n]).all()
+    assert (a.coef[:n] == b.coef[:n]).all()
+    # a canonical operator passed back through canonicalize is unchanged
+    c = pk.canonicalize(a, ws=ws)
+    assert c.size == n and (c.x[:, :n] == a.x[:, :n]).all() and (c.coef[:n] == a.coef[:n]).all()
+
+
+def test_empty_and_commuting_inputs(pk, ws):
+    say("empty inputs")
+    H = wl.ising_chain(12)
+    empty = wl.empty(12)
+    got = pk.commutator(up(pk, H, ws), pk.PauliOp.from_raw(12, empty.x, empty.z, empty.coef),
+                        ws=ws)
+    assert got.size == 0
+    # Z strings commute with a pure-Z Hamiltonian
+    Hz = wl.from_terms(12, [(1.0, [("Z", 1), ("Z", 2)]), (0.5, [("Z", 3)])])
+    Oz = wl.from_terms(12, [(1.0, [("Z", 5)]), (2.0, [("Z", 1), ("Z", 7)])])
+    got = pk.commutator(up(pk, Hz, ws), up(pk, Oz, ws), ws=ws)
+    assert got.size == 0
+
+
+# ---------------------------------------------------------------------------
+# add / truncate / canonicalize / norms
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [20, 64, 128])
+def test_add(pk, ws, n):
+    say(f"add n={n}")
+    A = wl.random_operator(n, 3000, seed=n, density=0.2)
+    B = wl.random_operator(n, 2000, seed=n + 1, density=0.2)
+    # shared strings, one of them cancelling exactly
+    B = wl.HostOp(n, np.concatenate([A.x[:500], B.x]), np.concatenate([A.z[:500], B.z]),
+                  np.concatenate([A.coef[:500], B.coef]))
+    B = oracle.canonicalize(B)
+    al, be = 0.7 - 0.25j, -1.5 + 0.5j
+    want = oracle.add(A, al, B, be)
+    got = pk.add(up(pk, A, ws), al, up(pk, B, ws), be, ws=ws).to_host()
+    assert_same_operator(got, want, what="add")
+    assert exact_fraction(got, want) == 1.0
+    z = pk.add(up(pk, A, ws), 1.0, up(pk, A, ws), -1.0, ws=ws)
+    assert z.size == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_truncate_ties_keep_filters(pk, ws, seed):
+    say(f"truncate seed={seed}")
+    n = 64
+    O = wl.random_operator(n, 12000, seed=seed + 40, density=0.08)
+    if seed % 2 == 0:  # many exact ties in |c|
+        O.coef = np.round(O.coef * 4) / 4
+        O.coef[O.coef == 0] = 0.25
+    keep = wl.HostOp(n, O.x[5:9], O.z[5:9], O.coef[5:9])
+    keepc = oracle.canonicalize(keep)
+    M = [1, 777, 5000, 11990][seed]
+    t = oracle.Trunc(max_len=[0, 9, 7, 0][seed], coef_eps=[0.0, 0.3, 0.0, 0.5][seed],
+                     max_strings=M, keep=keepc)
+    want = oracle.truncate(O, t)
+    kd = up(pk, keepc, ws)
+    got = pk.truncate(up(pk, O, ws), pk.Trunc(t.max_len, t.coef_eps, M, kd), ws=ws).to_host()
+    assert_same_operator(got, want, rtol=0.0, what="truncate")
+
+
+def test_truncate_large_tie_group(pk, ws):
+    """All magnitudes equal: the cut is decided by key order alone."""
+    say("truncate all ties")
+    n = 64
+    O = wl.random_operator(n, 9000, seed=77, density=0.1)
+    O.coef = np.where(np.arange(O.n) % 2 == 0, 1.0 + 0j, 1j)
+    for M in (1, 2500, 4099, 8999):
+        t = oracle.Trunc(max_strings=M)
+        want = oracle.truncate(O, t)
+        got = pk.truncate(up(pk, O, ws), pk.Trunc(max_strings=M), ws=ws).to_host()
+        assert_same_operator(got, want, rtol=0.0, what=f"ties M={M}")
+
+
+def test_canonicalize_duplicates(pk, ws):
+    say("canonicalize")
+    n = 40
+    A = wl.random_operator(n, 5000, seed=5, density=0.1)
+    idx = np.random.default_rng(0).integers(0, A.n, size=3000)
+    dup = wl.HostOp(n, np.concatenate([A.x, A.x[idx]]), np.concatenate([A.z, A.z[idx]]),
+                    np.concatenate([A.coef, -A.coef[idx] * 0.5]))
+    want = oracle.canonicalize(dup)
+    raw = pk.PauliOp.from_raw(n, dup.x, dup.z, dup.coef)
+    got = pk.canonicalize(raw, ws=ws).to_host()
+    assert_same_operator(got, want, what="canonicalize")
+
+
+@pytest.mark.parametrize("n", [30, 128])
+def test_norm_and_inner(pk, ws, n):
+    say(f"norm/inner n={n}")
+    A = wl.random_operator(n, 5000, seed=9, density=0.2)
+    B = wl.random_operator(n, 3000, seed=10, density=0.2)
+    B = oracle.canonicalize(wl.HostOp(n, np.concatenate([A.x[:1000], B.x]),
+                                      np.concatenate([A.z[:1000], B.z]),
+                                      np.concatenate([A.coef[:1000] * 0.3, B.coef])))
+    Ad, Bd = up(pk, A, ws), up(pk, B, ws)
+    assert pk.norm2(Ad, ws=ws) == pytest.approx(oracle.norm2(A), rel=1e-15)
+    got = pk.inner(Ad, Bd, ws=ws)
+    want = oracle.inner(A, B)
+    assert abs(got - want) <= 1e-13 * max(1.0, abs(want))
+
+
+# ---------------------------------------------------------------------------
+# Lanczos
+# ---------------------------------------------------------------------------
+def test_lanczos_config_small(pk, ws):
+    say("lanczos N=12 chain, 12 steps")
+    H, O0, steps = wl.config_lanczos_small()
+    want_b, want_basis = oracle.lanczos(H, O0, steps, keep_basis=True)
+    got_b, got_basis = pk.lanczos(up(pk, H, ws), up(pk, O0, ws), steps, ws=ws, keep_basis=True)
+    assert np.allclose(got_b, want_b, rtol=1e-12, atol=0)
+    assert got_b[0] == pytest.approx(2.1, rel=1e-15)
+    for g, w in zip(got_basis, want_basis):
+        assert_same_operator(g.to_host(), w, what="Krylov vector")
+
+
+def test_lanczos_worked_example(pk, ws):
+    say("worked example on the GPU")
+    import test_oracle_pins as pins
+    golden = pins.load_worked_example()
+    n = 10
+    H = wl.xx_plus_zz_defect(n, 4)
+    O0 = wl.from_terms(n, [(1.0, [("X", 1)])])
+    bs, basis = pk.lanczos(up(pk, H, ws), up(pk, O0, ws), 7, pk.Trunc(coef_eps=1e-10), ws=ws,
+                           keep_basis=True)
+    for step in range(1, 8):
+        B = basis[step - 1].to_host()
+        got = {wl.text_of_key(n, k): c for k, c in zip(B.keys(), B.coef)}
+        want = dict((t, c) for c, t in golden[step])
+        assert set(got) == set(want), step
+        for t in want:
+            assert abs(got[t] - want[t]) < 1e-10
+
+
+def test_lanczos_majorana_two_words(pk, ws):
+    say("majorana N=70")
+    n, J, h = 70, 1.0, 0.7
+    H = wl.majorana_chain(n, J, h)
+    O0 = wl.from_terms(n, [(1.0, [("X", 1)])])
+    bs = pk.lanczos(up(pk, H, ws), up(pk, O0, ws), 2 * n + 1, ws=ws)
+    want = [2 * h if k % 2 == 0 else 2 * J for k in range(2 * n - 1)]
+    assert len(bs) == 2 * n
+    assert np.allclose(bs[:-1], want, rtol=1e-14)
+
+
+def test_lanczos_breakdown_conserved(pk, ws):
+    say("breakdown")
+    H, O0 = wl.config_lanczos_split(literal_o0=True)
+    _, b, broke = pk.lanczos_step(up(pk, H, ws), None, up(pk, O0, ws), 0.0, ws=ws)
+    assert broke and b == 0.0
+
+
+def test_lanczos_truncated_vs_oracle(pk, ws):
+    say("lanczos truncated N=64 chain")
+    n = 64
+    H = wl.ising_chain(n)
+    O0 = wl.single_site_sum(n, "Z", 1 / math.sqrt(n))
+    t = oracle.Trunc(max_strings=3000, max_len=10)
+    want = oracle.lanczos(H, O0, 10, t)
+    got = pk.lanczos(up(pk, H, ws), up(pk, O0, ws), 10, pk.Trunc(max_len=10, max_strings=3000),
+                     ws=ws)
+    assert np.allclose(got, want, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Runge-Kutta
+# ---------------------------------------------------------------------------
+def test_rk4_taylor_and_oracle(pk, ws):
+    say("rk4 TFIM")
+    H, O0 = wl.config_rk4_tfim()
+    Hd, Od = up(pk, H, ws), up(pk, O0, ws)
+    O1 = pk.rk4_step(Hd, Od, 0.02, ws=ws)
+    S = pk.inner(Od, O1, ws=ws)
+    want = 1 - 16 * 0.02 ** 2 / 2 + 16 * 32 * 0.02 ** 4 / 24
+    assert abs(S.real - want) < 1e-14 and O1.size == 50
+    assert_same_operator(O1.to_host(), oracle.rk4_step(H, O0, 0.02), what="rk4 step 1")
+    # three truncated steps
+    t = oracle.Trunc(max_len=6, max_strings=400, keep=O0)
+    cur_h, cur_d = O0, Od
+    for k in range(3):
+        cur_h = oracle.rk4_step(H, cur_h, 0.05, t)
+        cur_d = pk.rk4_step(Hd, cur_d, 0.05, pk.Trunc(6, 0.0, 400, Od), ws=ws)
+        assert_same_operator(cur_d.to_host(), cur_h, what=f"rk4 truncated step {k}")
+
+
+# ---------------------------------------------------------------------------
+# Workspace and capacity retries
+# ---------------------------------------------------------------------------
+def test_small_workspace_and_capacity_retry(pk):
+    say("retry paths")
+    import ctypes
+    from paper_2410_09654_amd import _lib
+    H = wl.ising_chain(64)
+    O = wl.random_local_strings(64, 3000, 10, seed=3)
+    small = pk.Workspace(1 << 20)
+    Hd = up(pk, H, small)
+    Od = up(pk, O, small)
+    out = pk.PauliOp(64, 10)
+    L = _lib.load()
+    wss = small.c_struct()
+    wss.bytes = 4096
+    rc = L.pauli_commutator(ctypes.byref(Hd.c_struct()), ctypes.byref(Od.c_struct()), None,
+                            ctypes.byref(out.c_struct()), ctypes.byref(wss),
+                            pk.ops._stream_handle())
+    assert rc == _lib.PAULI_EWORKSPACE and wss.required > 4096
+    got = pk.commutator(Hd, Od, out=out, ws=small).to_host()
+    assert_same_operator(got, oracle.commutator(H, O), what="after retries")
