@@ -34,6 +34,13 @@ def up(pk, host, ws, dtype=0):
     return pk.PauliOp.from_host(host, dtype=dtype, ws=ws)
 
 
+def uph(pk, host):
+    """Hamiltonians are uploaded in their given order: a commutator sums each
+    output coefficient in ascending H index, so the oracle and the GPU must
+    see the same H array."""
+    return pk.PauliOp.from_raw(host.n_qubits, host.x, host.z, host.coef)
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
@@ -50,7 +57,7 @@ def test_commutator_random(pk, ws, n, nh, no, seed):
     H = wl.random_operator(n, nh, seed=seed, density=min(1.0, 3.0 / n + 0.05))
     O = wl.random_operator(n, no, seed=seed + 100, density=min(1.0, 6.0 / n + 0.05))
     want = oracle.commutator(H, O)
-    got = pk.commutator(up(pk, H, ws), up(pk, O, ws), ws=ws).to_host()
+    got = pk.commutator(uph(pk, H), up(pk, O, ws), ws=ws).to_host()
     assert_canonical_unique(got)
     assert_same_operator(got, want, what="commutator")
     assert exact_fraction(got, want) == 1.0
@@ -62,7 +69,7 @@ def test_commutator_chain_local_strings_truncated(pk, ws):
     O = wl.random_local_strings(64, 6000, 10, seed=7)
     t = oracle.Trunc(max_len=8, max_strings=5000)
     want = oracle.truncate(oracle.commutator(H, O), t)
-    got = pk.commutator(up(pk, H, ws), up(pk, O, ws), pk.Trunc(max_len=8, max_strings=5000),
+    got = pk.commutator(uph(pk, H), up(pk, O, ws), pk.Trunc(max_len=8, max_strings=5000),
                         ws=ws).to_host()
     assert got.n == want.n == 5000
     assert_same_operator(got, want, what="truncated commutator")
@@ -72,7 +79,7 @@ def test_commutator_order_is_canonical_and_deterministic(pk, ws):
     say("determinism")
     H = wl.ising_chain(64)
     O = wl.random_local_strings(64, 20000, 10, seed=8)
-    Hd, Od = up(pk, H, ws), up(pk, O, ws)
+    Hd, Od = uph(pk, H), up(pk, O, ws)
     a = pk.commutator(Hd, Od, pk.Trunc(max_strings=30000), ws=ws)
     b = pk.commutator(Hd, Od, pk.Trunc(max_strings=30000), ws=ws)
     n = a.size
@@ -88,13 +95,13 @@ def test_empty_and_commuting_inputs(pk, ws):
     say("empty inputs")
     H = wl.ising_chain(12)
     empty = wl.empty(12)
-    got = pk.commutator(up(pk, H, ws), pk.PauliOp.from_raw(12, empty.x, empty.z, empty.coef),
+    got = pk.commutator(uph(pk, H), pk.PauliOp.from_raw(12, empty.x, empty.z, empty.coef),
                         ws=ws)
     assert got.size == 0
     # Z strings commute with a pure-Z Hamiltonian
     Hz = wl.from_terms(12, [(1.0, [("Z", 1), ("Z", 2)]), (0.5, [("Z", 3)])])
     Oz = wl.from_terms(12, [(1.0, [("Z", 5)]), (2.0, [("Z", 1), ("Z", 7)])])
-    got = pk.commutator(up(pk, Hz, ws), up(pk, Oz, ws), ws=ws)
+    got = pk.commutator(uph(pk, Hz), up(pk, Oz, ws), ws=ws)
     assert got.size == 0
 
 
@@ -186,7 +193,7 @@ def test_lanczos_config_small(pk, ws):
     say("lanczos N=12 chain, 12 steps")
     H, O0, steps = wl.config_lanczos_small()
     want_b, want_basis = oracle.lanczos(H, O0, steps, keep_basis=True)
-    got_b, got_basis = pk.lanczos(up(pk, H, ws), up(pk, O0, ws), steps, ws=ws, keep_basis=True)
+    got_b, got_basis = pk.lanczos(uph(pk, H), up(pk, O0, ws), steps, ws=ws, keep_basis=True)
     assert np.allclose(got_b, want_b, rtol=1e-12, atol=0)
     assert got_b[0] == pytest.approx(2.1, rel=1e-15)
     for g, w in zip(got_basis, want_basis):
@@ -200,7 +207,7 @@ def test_lanczos_worked_example(pk, ws):
     n = 10
     H = wl.xx_plus_zz_defect(n, 4)
     O0 = wl.from_terms(n, [(1.0, [("X", 1)])])
-    bs, basis = pk.lanczos(up(pk, H, ws), up(pk, O0, ws), 7, pk.Trunc(coef_eps=1e-10), ws=ws,
+    bs, basis = pk.lanczos(uph(pk, H), up(pk, O0, ws), 7, pk.Trunc(coef_eps=1e-10), ws=ws,
                            keep_basis=True)
     for step in range(1, 8):
         B = basis[step - 1].to_host()
@@ -216,7 +223,7 @@ def test_lanczos_majorana_two_words(pk, ws):
     n, J, h = 70, 1.0, 0.7
     H = wl.majorana_chain(n, J, h)
     O0 = wl.from_terms(n, [(1.0, [("X", 1)])])
-    bs = pk.lanczos(up(pk, H, ws), up(pk, O0, ws), 2 * n + 1, ws=ws)
+    bs = pk.lanczos(uph(pk, H), up(pk, O0, ws), 2 * n + 1, ws=ws)
     want = [2 * h if k % 2 == 0 else 2 * J for k in range(2 * n - 1)]
     assert len(bs) == 2 * n
     assert np.allclose(bs[:-1], want, rtol=1e-14)
@@ -225,7 +232,7 @@ def test_lanczos_majorana_two_words(pk, ws):
 def test_lanczos_breakdown_conserved(pk, ws):
     say("breakdown")
     H, O0 = wl.config_lanczos_split(literal_o0=True)
-    _, b, broke = pk.lanczos_step(up(pk, H, ws), None, up(pk, O0, ws), 0.0, ws=ws)
+    _, b, broke = pk.lanczos_step(uph(pk, H), None, up(pk, O0, ws), 0.0, ws=ws)
     assert broke and b == 0.0
 
 
@@ -236,7 +243,7 @@ def test_lanczos_truncated_vs_oracle(pk, ws):
     O0 = wl.single_site_sum(n, "Z", 1 / math.sqrt(n))
     t = oracle.Trunc(max_strings=3000, max_len=10)
     want = oracle.lanczos(H, O0, 10, t)
-    got = pk.lanczos(up(pk, H, ws), up(pk, O0, ws), 10, pk.Trunc(max_len=10, max_strings=3000),
+    got = pk.lanczos(uph(pk, H), up(pk, O0, ws), 10, pk.Trunc(max_len=10, max_strings=3000),
                      ws=ws)
     assert np.allclose(got, want, rtol=1e-12, atol=0)
 
@@ -247,7 +254,7 @@ def test_lanczos_truncated_vs_oracle(pk, ws):
 def test_rk4_taylor_and_oracle(pk, ws):
     say("rk4 TFIM")
     H, O0 = wl.config_rk4_tfim()
-    Hd, Od = up(pk, H, ws), up(pk, O0, ws)
+    Hd, Od = uph(pk, H), up(pk, O0, ws)
     O1 = pk.rk4_step(Hd, Od, 0.02, ws=ws)
     S = pk.inner(Od, O1, ws=ws)
     want = 1 - 16 * 0.02 ** 2 / 2 + 16 * 32 * 0.02 ** 4 / 24
@@ -272,7 +279,7 @@ def test_small_workspace_and_capacity_retry(pk):
     H = wl.ising_chain(64)
     O = wl.random_local_strings(64, 3000, 10, seed=3)
     small = pk.Workspace(1 << 20)
-    Hd = up(pk, H, small)
+    Hd = uph(pk, H)
     Od = up(pk, O, small)
     out = pk.PauliOp(64, 10)
     L = _lib.load()
