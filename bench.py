@@ -1,0 +1,147 @@
+"""Benchmark of the hot path: one [H, O] + merge + truncate on one MI355X.
+
+Workload (the commutator microbenchmark): open N=64 chain,
+H = sum Z_i Z_{i+1} + 1.05 sum X_i + 0.5 sum Z_i (191 strings), O = 2^20
+distinct random strings with support on <= 10 contiguous sites and complex
+N(0,1) coefficients (seed 20241009), truncation to length <= 12 and the top
+2^20 strings by |c|.  A step is one full pauli_commutator call with its
+inputs resident in HBM.  Throughput is counted in (H string, O string) pairs
+per second, the loop count of the paper's Alg. 1.
+
+Prints one JSON line.  Single GPU only.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Pauli string products/sec in [H,O]+merge+truncate; b_n rel err vs FP64"
+HBM_PEAK_GBS = 8000.0
+R_BYTES = 32  # one record at N=64 in FP64: 16 B key + 16 B complex coefficient
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--count", type=int, default=1 << 20, help="strings in O")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 17,
+                    help="O strings given to the CPU oracle (0: skip the CPU baseline)")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the engine has no multi-GPU path "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as wl
+    import paper_2410_09654_amd as pk
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    H_host, O_host = wl.config_commutator_bench(args.count)
+    max_len, max_strings = 12, args.count
+    H = pk.PauliOp.from_raw(64, H_host.x, H_host.z, H_host.coef)
+    ws = pk.Workspace(1 << 30)
+    O = pk.PauliOp.from_host(O_host, ws=ws)
+    trunc = pk.Trunc(max_len=max_len, max_strings=max_strings)
+    out = pk.PauliOp(64, max_strings + 16)
+
+    for _ in range(max(args.warmup, 1)):
+        pk.commutator(H, O, trunc, out=out, ws=ws)
+    stats = pk.last_stats()
+
+    # timed region: kernel durations recorded with HIP events on the stream the
+    # library launches on (the current torch stream)
+    kernel_timing = not args.no_kernel_timing
+    pk.profile_enable(kernel_timing)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        pk.commutator(H, O, trunc, out=out, ws=ws)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = pk.profile_read() if kernel_timing else {}
+    pk.profile_enable(False)
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    pairs = H.size * O.size
+    value = pairs * args.steps / wall
+
+    # algorithmic bytes per launch (records of R bytes)
+    nO, pe, u, m_out = O.size, stats["emitted"], stats["survivors"], stats["output"]
+    alg_bytes = {
+        "k_emit_count": nO * R_BYTES,
+        "k_emit_scatter": (nO + pe) * R_BYTES,
+        "k_merge": (pe + u) * R_BYTES,
+        "k_level1": u * R_BYTES,
+        "k_write": (u + m_out) * R_BYTES,
+    }
+    per_kernel = {k: {"launches": c, "avg_ms": ms / c, "total_ms": ms} for k, (c, ms) in kern.items()}
+    roofline = None
+    if per_kernel:
+        dom = max((k for k in per_kernel if k in alg_bytes), key=lambda k: per_kernel[k]["total_ms"])
+        avg_s = per_kernel[dom]["avg_ms"] * 1e-3
+        achieved = alg_bytes[dom] / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "alg_bytes_per_launch": alg_bytes[dom]}
+        mt = ["k_merge", "k_level1", "k_write"]
+        mt_ms = sum(per_kernel[k]["total_ms"] for k in per_kernel
+                    if k not in ("k_emit_count", "k_emit_scatter")) / args.steps
+        mt_bytes = (pe + 2 * u + m_out) * R_BYTES
+        roofline["merge_truncate"] = {"ms_per_step": round(mt_ms, 4),
+                                      "alg_bytes": mt_bytes,
+                                      "achieved": round(mt_bytes / (mt_ms * 1e-3) / 1e9, 1),
+                                      "frac": round(mt_bytes / (mt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        import oracle
+        n = min(args.cpu_sample, O_host.n)
+        sub = wl.HostOp(64, O_host.x[:n], O_host.z[:n], O_host.coef[:n])
+        tc0 = time.perf_counter()
+        C = oracle.commutator(H_host, sub)
+        oracle.truncate(C, oracle.Trunc(max_len=max_len, max_strings=n))
+        tc = time.perf_counter() - tc0
+        cpu = {"value": H_host.n * n / tc, "unit": "products/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n} of the {O_host.n} O strings ({H_host.n * n} pairs), "
+                         f"commutator + truncate (length <= {max_len}, top {n}), "
+                         f"single-threaded C oracle, {tc:.1f} s"}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "products/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "commutator microbenchmark: N=64 chain, |H|=191, |O|=2^20 random "
+                               "strings of support <= 10, one [H,O] + merge + truncate "
+                               "(length <= 12, top 2^20)",
+                   "n_qubits": 64, "H_strings": H.size, "O_strings": O.size,
+                   "max_len": max_len, "max_strings": max_strings, "seed": 20241009},
+        "emitted": pe, "unique": stats["unique"], "output": m_out,
+        "emitted_per_s": pe * args.steps / wall,
+        "gpu_event_ms_per_step": ev0.elapsed_time(ev1) / args.steps,
+        "kernels": per_kernel,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -154,6 +154,18 @@ int pauli_norm2(const pauli_op *A, double *out, pauli_ws *ws, void *stream);
 int pauli_inner(const pauli_op *A, const pauli_op *B, double out[2], pauli_ws *ws,
                 void *stream);
 
+/* Counters of the last engine pass of this thread's last call (diagnostics and
+ * the algorithmic byte counts of the benchmark). */
+typedef struct pauli_stats {
+  int64_t emitted;   /* records produced: anticommuting pairs + operator terms */
+  int64_t unique;    /* distinct strings with a nonzero merged coefficient */
+  int64_t survivors; /* of those, left after the length and |c| filters */
+  int64_t output;    /* strings written to the output */
+  int32_t passes;    /* hash-range passes */
+  int32_t buckets;   /* merge buckets */
+} pauli_stats;
+void pauli_last_stats(pauli_stats *out);
+
 /* Static description of the error code. */
 const char *pauli_strerror(int status);
 /* Text of the last HIP error seen by this thread (empty if none). */

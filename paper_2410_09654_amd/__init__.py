@@ -7,9 +7,10 @@ Python binding over torch device memory.
 """
 from ._lib import PAULI_C128, PAULI_C64K, PauliError
 from .ops import (PauliOp, Trunc, Workspace, add, canonicalize, commutator, inner,
-                  lanczos_step, norm2, profile_enable, profile_read, rk4_step, truncate)
+                  lanczos_step, last_stats, norm2, profile_enable, profile_read, rk4_step,
+                  truncate)
 from .algorithms import evolve, lanczos
 
 __all__ = ["PAULI_C128", "PAULI_C64K", "PauliError", "PauliOp", "Trunc", "Workspace", "add",
            "canonicalize", "commutator", "inner", "lanczos_step", "norm2", "rk4_step",
-           "truncate", "lanczos", "evolve", "profile_enable", "profile_read"]
+           "truncate", "lanczos", "evolve", "profile_enable", "profile_read", "last_stats"]

@@ -13,7 +13,8 @@ PAULI_C128, PAULI_C64K = 0, 1
 
 EXPORTS = ["pauli_commutator", "pauli_add", "pauli_truncate", "pauli_canonicalize",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
-           "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_read"]
+           "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_read",
+           "pauli_last_stats"]
 
 
 class PauliOpC(ctypes.Structure):
@@ -30,6 +31,12 @@ class PauliTruncC(ctypes.Structure):
 class PauliWsC(ctypes.Structure):
     _fields_ = [("ptr", ctypes.c_void_p), ("bytes", ctypes.c_size_t),
                 ("required", ctypes.c_size_t)]
+
+
+class PauliStatsC(ctypes.Structure):
+    _fields_ = [("emitted", ctypes.c_int64), ("unique", ctypes.c_int64),
+                ("survivors", ctypes.c_int64), ("output", ctypes.c_int64),
+                ("passes", ctypes.c_int32), ("buckets", ctypes.c_int32)]
 
 
 class PauliError(RuntimeError):
@@ -68,10 +75,13 @@ def load():
     L.pauli_profile_enable.argtypes = [ctypes.c_int]
     L.pauli_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     L.pauli_profile_read.restype = ctypes.c_size_t
+    L.pauli_last_stats.argtypes = [P(PauliStatsC)]
+    L.pauli_last_stats.restype = None
     for name in EXPORTS:
-        L[name].restype = L[name].restype if name in (
-            "pauli_strerror", "pauli_last_error", "pauli_profile_read") else \
-            (None if name == "pauli_profile_enable" else ctypes.c_int)
+        if name in ("pauli_strerror", "pauli_last_error", "pauli_profile_read",
+                    "pauli_last_stats"):
+            continue
+        L[name].restype = None if name == "pauli_profile_enable" else ctypes.c_int
     _lib = L
     return L
 

@@ -2,7 +2,7 @@
 //
 // Key words: a string on W 64-bit words per mask is kept as 2W words,
 // raw order (x[0..W-1], z[0..W-1]).  Inside the engine strings travel as
-// "mixed keys": a three-round Feistel network over the two halves (x, z)
+// "mixed keys": a two-round Feistel network over the two halves (x, z)
 // whose round function is built from the MurmurHash3 64-bit finalizer
 // (fmix64).  The mix is a bijection, so equal mixed keys mean equal strings,
 // its leading bits are uniformly spread (they choose the hash bins), and the
@@ -18,18 +18,19 @@ namespace pauli {
 constexpr int NBINS_LOG = 14;
 constexpr int NBINS = 1 << NBINS_LOG;   // hash bins of the emit passes
 constexpr int MERGE_CAP = 2048;         // max records of one merge bucket
-constexpr int MERGE_THREADS = 512;
+constexpr int MERGE_THREADS = 1024;
 constexpr int DIGIT_BITS = 11;          // in-bucket counting-sort digit
 constexpr int NDIGITS = 1 << DIGIT_BITS;
 constexpr int EMIT_THREADS = 512;
 constexpr int SEL0_BINS = 2048;         // exponent bins of |c|^2
 constexpr int SEL_BINS = 4096;          // 12-bit digits of later select levels
 constexpr int FINISH_CAP = 2048;
+constexpr int HREP = 64;                // replicas of the select histograms
+                                        // (blocks add into replica blockIdx % HREP)
 constexpr uint32_t GROUP_SHIFT = 28;    // record source id = group << 28 | index
 
 constexpr uint64_t MIX_C1 = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t MIX_C2 = 0xC2B2AE3D27D4EB4Full;
-constexpr uint64_t MIX_C3 = 0x165667B19E3779F9ull;
 
 DEV uint64_t fmix64(uint64_t k) {
   k ^= k >> 33;
@@ -72,9 +73,6 @@ DEV Key<W> mix_key(const Key<W>& raw) {
   mix_round<W>(R, f, MIX_C2);
 #pragma unroll
   for (int i = 0; i < W; i++) L[i] ^= f[i];
-  mix_round<W>(L, f, MIX_C3);
-#pragma unroll
-  for (int i = 0; i < W; i++) R[i] ^= f[i];
   Key<W> m;
 #pragma unroll
   for (int i = 0; i < W; i++) {
@@ -92,9 +90,6 @@ DEV Key<W> unmix_key(const Key<W>& m) {
     L[i] = m.w[i];
     R[i] = m.w[W + i];
   }
-  mix_round<W>(L, f, MIX_C3);
-#pragma unroll
-  for (int i = 0; i < W; i++) R[i] ^= f[i];
   mix_round<W>(R, f, MIX_C2);
 #pragma unroll
   for (int i = 0; i < W; i++) L[i] ^= f[i];

@@ -25,6 +25,7 @@ using namespace pauli;
 namespace {
 
 thread_local std::string g_last_error;
+thread_local pauli_stats g_stats;
 
 // ---------------------------------------------------------------------------
 // Optional kernel timing
@@ -259,10 +260,10 @@ int ws_short(Arena& ar, pauli_ws* ws) {
 
 template <int W, bool F32>
 int Engine::run(Call& c) {
-  using V = RecV<F32>;
   const size_t KB = sizeof(Key<W>);
-  const size_t VB = sizeof(V);
+  const size_t RB = sizeof(Rec<W, F32>);
   ar->bottom = 0;
+  memset(&g_stats, 0, sizeof(g_stats));
   // ----- inputs --------------------------------------------------------------
   const bool comm = c.has_comm && c.H.n > 0 && c.O.n > 0;
   int64_t tstart[MAX_TERMS + 1];
@@ -285,10 +286,10 @@ int Engine::run(Call& c) {
   uint32_t* counts = (uint32_t*)ar->take((size_t)std::max(rows, 1) * NBINS * 4);
   uint32_t* bin_total = (uint32_t*)ar->take(NBINS * 4);
   uint32_t* bin_base = (uint32_t*)ar->take((NBINS + 1) * 4);
-  uint32_t* hist0 = (uint32_t*)ar->take(SEL0_BINS * 4);
+  uint32_t* hist0 = (uint32_t*)ar->take((size_t)HREP * SEL0_BINS * 4);
   uint32_t* histL[2];
-  histL[0] = (uint32_t*)ar->take(SEL_BINS * 4);
-  histL[1] = (uint32_t*)ar->take(SEL_BINS * 4);
+  histL[0] = (uint32_t*)ar->take((size_t)HREP * SEL_BINS * 4);
+  histL[1] = (uint32_t*)ar->take((size_t)HREP * SEL_BINS * 4);
   if (ar->short_) return PAULI_EWORKSPACE;
   TRY(host_ctl(&hctl));
   TRY(zero_u32(dctl, sizeof(Ctl) / 4));
@@ -377,32 +378,40 @@ int Engine::run(Call& c) {
   const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
   const uint32_t max_buckets = (uint32_t)NBINS << pass_bits;
   // ----- records, U, bucket tables, candidate lists -------------------------
-  void* rkey = ar->take(ptot * KB);
-  void* rval = ar->take(ptot * VB);
-  uint32_t* rsrc = (uint32_t*)ar->take(ptot * 4);
+  // source ids fold into the key bits implied by the bin unless an index
+  // needs more than 11 bits (H above 2047 strings, canonicalisation lists)
+  bool wide = comm && c.H.n > 2047;
+  for (int t = 0; t < c.n_terms; t++) wide = wide || c.tlist[t];
+  void* recs = ar->take(ptot * RB);
+  uint32_t* rsrc_wide = wide ? (uint32_t*)ar->take(ptot * 4) : nullptr;
   void* uk = ar->take(ptot * KB);
   double2* uc = (double2*)ar->take(ptot * sizeof(double2));
   uint32_t* b_ubase = (uint32_t*)ar->take((size_t)max_buckets * 4);
   uint32_t* b_slots = (uint32_t*)ar->take((size_t)max_buckets * 4);
   uint32_t* b_surv = (uint32_t*)ar->take((size_t)max_buckets * 4);
   uint32_t* b_keep = (uint32_t*)ar->take((size_t)max_buckets * 4);
+  uint32_t* b_unique = (uint32_t*)ar->take((size_t)max_buckets * 4);
   uint32_t* b_abv = (uint32_t*)ar->take((size_t)max_buckets * 4);
   uint32_t* b_bcnt = (uint32_t*)ar->take((size_t)max_buckets * 4);
   uint32_t* b_obase = (uint32_t*)ar->take((size_t)max_buckets * 4);
   double2* norm_part = (double2*)ar->take((size_t)max_buckets * sizeof(double2));
   const bool want_select = tr && tr->max_strings > 0;
   uint32_t* cand[3] = {nullptr, nullptr, nullptr};
+  uint32_t* ccnt[3] = {nullptr, nullptr, nullptr};
   if (want_select)
-    for (int k = 0; k < 3; k++) cand[k] = (uint32_t*)ar->take(ptot * 8);
+    for (int k = 0; k < 3; k++) {
+      cand[k] = (uint32_t*)ar->take(ptot * 4);
+      ccnt[k] = (uint32_t*)ar->take((size_t)max_buckets * 4);
+    }
   if (ar->short_) return PAULI_EWORKSPACE;
-  TRY(zero_u32(hist0, SEL0_BINS));
+  TRY(zero_u32(hist0, (size_t)HREP * SEL0_BINS));
 
   MergeArgs ma;
   memset(&ma, 0, sizeof(ma));
   ma.bin_base = bin_base;
-  ma.rkey = rkey;
-  ma.rval = rval;
-  ma.rsrc = rsrc;
+  ma.recs = recs;
+  ma.rsrc_wide = rsrc_wide;
+  ma.wide = wide ? 1 : 0;
   for (int g = 0; g < c.n_groups; g++) {
     ma.alpha[g] = c.groups[g].alpha;
     ma.alpha_kind[g] = alpha_kind(c.groups[g].alpha);
@@ -421,13 +430,14 @@ int Engine::run(Call& c) {
   ma.b_slots = b_slots;
   ma.b_surv = b_surv;
   ma.b_keep = b_keep;
+  ma.b_unique = b_unique;
   ma.hist0 = hist0;
   ma.norm_part = norm_part;
   ma.ctl = dctl;
 
-  ea.rkey = rkey;
-  ea.rval = rval;
-  ea.rsrc = rsrc;
+  ea.recs = recs;
+  ea.rsrc_wide = rsrc_wide;
+  ea.wide = wide ? 1 : 0;
   uint32_t nbk = 0;                // buckets written so far
   unsigned long long u_off = 0;   // U slots reserved by earlier passes
   const int npass = 1 << pass_bits;
@@ -444,6 +454,8 @@ int Engine::run(Call& c) {
     LAUNCH("k_emit_scatter", (k_emit<W, F32, true>), rows, EMIT_THREADS, ea);
     ma.g_log = g_log;
     ma.digit_shift = pass_bits + NBINS_LOG - g_log;
+    ma.pass_bits = pass_bits;
+    ma.pass_id = (uint32_t)p;
     ma.u_off = u_off;
     ma.bucket_off = nbk;
     const uint32_t nb_pass = (uint32_t)(NBINS >> g_log);
@@ -451,11 +463,19 @@ int Engine::run(Call& c) {
     nbk += nb_pass;
     u_off += pe;
   }
+  if (nbk)
+    LAUNCH("k_bucket_totals", k_bucket_totals, 1, 1024, b_slots, b_surv, b_keep, b_unique, nbk,
+           dctl);
   TRY(read_ctl());
   if (hctl->overflow) {
     g_last_error = "merge bucket overflow";
     return PAULI_EINTERNAL;
   }
+  g_stats.emitted = (int64_t)pe_all;
+  g_stats.unique = (int64_t)hctl->u_unique;
+  g_stats.survivors = (int64_t)hctl->surv_total;
+  g_stats.passes = npass;
+  g_stats.buckets = (int32_t)nbk;
 
   // ----- Lanczos: b_n from the untruncated sum, then divide and filter -------
   if (c.mode == M_LANCZOS) {
@@ -475,8 +495,6 @@ int Engine::run(Call& c) {
       write_empty();
       return PAULI_BREAKDOWN;
     }
-    // reset survivor totals: the scale pass recounts them
-    TRY(zero_u32(&dctl->surv_total, 4));
     ScaleArgs sa;
     memset(&sa, 0, sizeof(sa));
     sa.b_ubase = b_ubase;
@@ -494,8 +512,13 @@ int Engine::run(Call& c) {
     sa.n_keep = (int)n_keep;
     sa.hist0 = hist0;
     sa.ctl = dctl;
-    if (nbk) LAUNCH("k_scale_filter", (k_scale_filter<W>), nbk, 256, sa);
+    if (nbk) {
+      LAUNCH("k_scale_filter", (k_scale_filter<W>), nbk, 256, sa);
+      LAUNCH("k_bucket_totals", k_bucket_totals, 1, 1024, b_slots, b_surv, b_keep,
+             (const uint32_t*)nullptr, nbk, dctl);
+    }
     TRY(read_ctl());
+    g_stats.survivors = (int64_t)hctl->surv_total;
   }
 
   // ----- top-M --------------------------------------------------------------
@@ -518,59 +541,62 @@ int Engine::run(Call& c) {
       sa.uc = uc;
       sa.keep_mk = keep_mk;
       sa.n_keep = (int)n_keep;
-      sa.cand_cap = ptot;
+      sa.nbk = nbk;
       sa.ctl = dctl;
       TRY(set_u64(&dctl->sel_K, (unsigned long long)budget));
-      TRY(zero_u32(dctl->cand_n, 6));
       LAUNCH("k_select", k_select, 1, 1024, hist0, SEL0_BINS, dctl);
       // level 1: full pass over U into list 0 (kept for the boundary count)
-      TRY(zero_u32(histL[0], SEL_BINS));
-      sa.out_slot = 0;
-      sa.cand_out = cand[0];
+      TRY(zero_u32(histL[0], (size_t)HREP * SEL_BINS));
+      sa.list_out = cand[0];
+      sa.cc_out = ccnt[0];
       sa.hist = histL[0];
-      sa.level = 0;
       LAUNCH("k_level1", (k_level1<W>), nbk, 256, sa);
       TRY(read_ctl());
-      int level = 0, in_slot = 0, hslot = 0;
+      int in = 0;
       unsigned long long cnt = hctl->sel_count;
       if (cnt > FINISH_CAP) {
-        level = 1;
+        int level = 1, hslot = 0;
         LAUNCH("k_select", k_select, 1, 1024, histL[0], SEL_BINS, dctl);
         TRY(read_ctl());
         cnt = hctl->sel_count;
-        int out_slot = 1;
         while (cnt > FINISH_CAP) {
           if (level >= (64 + 128 * W) / 12) {
             g_last_error = "top-M select did not converge";
             return PAULI_EINTERNAL;
           }
+          const int out = in == 1 ? 2 : 1;
           hslot ^= 1;
-          TRY(zero_u32(histL[hslot], SEL_BINS));
-          TRY(zero_u32(&dctl->cand_n[out_slot], 2));
-          sa.in_slot = in_slot;
-          sa.out_slot = out_slot;
-          sa.cand_in = cand[in_slot];
-          sa.cand_out = cand[out_slot];
+          TRY(zero_u32(histL[hslot], (size_t)HREP * SEL_BINS));
+          sa.list_in = cand[in];
+          sa.cc_in = ccnt[in];
+          sa.list_out = cand[out];
+          sa.cc_out = ccnt[out];
           sa.hist = histL[hslot];
           sa.level = level;
-          const int grid = (int)std::min<unsigned long long>((cnt + 255) / 256 + 1, 1024);
-          LAUNCH("k_cand_level", (k_cand_level<W>), grid, 256, sa);
+          LAUNCH("k_cand_level", (k_cand_level<W>), nbk, 256, sa);
           LAUNCH("k_select", k_select, 1, 1024, histL[hslot], SEL_BINS, dctl);
           TRY(read_ctl());
           cnt = hctl->sel_count;
-          in_slot = out_slot;
-          out_slot = out_slot == 1 ? 2 : 1;
+          in = out;
           level++;
         }
+        // narrow to the chosen bin of the last level
+        const int out = in == 1 ? 2 : 1;
+        sa.list_in = cand[in];
+        sa.cc_in = ccnt[in];
+        sa.list_out = cand[out];
+        sa.cc_out = ccnt[out];
+        sa.hist = nullptr;
+        sa.level = level;
+        LAUNCH("k_cand_level", (k_cand_level<W>), nbk, 256, sa);
+        in = out;
       }
-      sa.in_slot = in_slot;
-      sa.cand_in = cand[in_slot];
-      sa.level = level;
+      sa.list_in = cand[in];
+      sa.cc_in = ccnt[in];
       LAUNCH("k_finish", (k_finish<W>), 1, 1024, sa);
-      TRY(zero_u32(b_bcnt, nbk));
-      sa.in_slot = 0;
-      sa.cand_in = cand[0];
-      LAUNCH("k_count_boundary", (k_count_boundary<W>), 512, 256, sa);
+      sa.list_in = cand[0];
+      sa.cc_in = ccnt[0];
+      LAUNCH("k_count_boundary", (k_count_boundary<W>), nbk, 64, sa);
     }
   }
   if (nbk == 0) return write_empty();
@@ -582,6 +608,7 @@ int Engine::run(Call& c) {
     return PAULI_EINTERNAL;
   }
   const unsigned long long nout = hctl->out_total;
+  g_stats.output = (int64_t)nout;
   WriteArgs wa;
   memset(&wa, 0, sizeof(wa));
   wa.b_ubase = b_ubase;
@@ -674,6 +701,10 @@ const char* pauli_strerror(int status) {
 }
 
 const char* pauli_last_error(void) { return g_last_error.c_str(); }
+
+void pauli_last_stats(pauli_stats* out) {
+  if (out) *out = g_stats;
+}
 
 void pauli_profile_enable(int on) {
   std::lock_guard<std::mutex> g(g_prof.mu);

@@ -39,6 +39,7 @@ struct Ctl {
   unsigned int overflow;         // a bucket exceeded MERGE_CAP / u32 overflow
   unsigned int bad_keep;         // keep set not canonical
   unsigned long long u_slots;    // U slots written by the merges
+  unsigned long long u_unique;   // distinct strings with nonzero merged value
   unsigned long long surv_total; // survivors after filters (incl. keep)
   unsigned long long keep_total; // keep-set survivors
   unsigned long long cand_n[3];  // candidate list sizes
@@ -81,13 +82,24 @@ struct EmitArgs {
   uint32_t pass_id;
   uint32_t* counts;
   const uint32_t* bin_base;
-  void* rkey;
-  void* rval;
-  uint32_t* rsrc;
+  void* recs;          // Rec<W, F32>[records]
+  uint32_t* rsrc_wide; // source ids when they do not fit the folded bits
+  int wide;
 };
 
 template <bool F32>
 using RecV = typename std::conditional<F32, float2, double2>::type;
+
+// One emitted record: the mixed key and the value.  The leading
+// NBINS_LOG + pass_bits bits of the key are implied by the record's bin and
+// pass, so they carry the source id instead: group in the top 3 bits, then
+// the index inside the group (H index; 0 for operator terms).  Calls whose
+// ids do not fit (canonicalisation of long lists) keep them in a side array.
+template <int W, bool F32>
+struct Rec {
+  Key<W> k;
+  RecV<F32> v;
+};
 
 template <int W, bool F32, bool SCATTER>
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
@@ -104,11 +116,11 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
     for (int i = tid; i < NBINS; i += EMIT_THREADS) hist[i] = 0u;
   }
   __syncthreads();
-  Key<W>* rkey = reinterpret_cast<Key<W>*>(a.rkey);
-  V* rval = reinterpret_cast<V*>(a.rval);
+  Rec<W, F32>* recs = reinterpret_cast<Rec<W, F32>*>(a.recs);
+  const int F = NBINS_LOG + a.pass_bits;
 
-  auto deposit = [&](const Key<W>& raw, V val, uint32_t src) {
-    const Key<W> mk = mix_key<W>(raw);
+  auto deposit = [&](const Key<W>& raw, V val, uint32_t group, uint32_t index) {
+    Key<W> mk = mix_key<W>(raw);
     uint64_t top = mk.w[0];
     if (a.pass_bits) {
       if ((uint32_t)(top >> (64 - a.pass_bits)) != a.pass_id) return;
@@ -117,9 +129,13 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
     const uint32_t bin = (uint32_t)(top >> (64 - NBINS_LOG));
     const uint32_t pos = atomicAdd(&hist[bin], 1u);
     if (SCATTER) {
-      rkey[pos] = mk;
-      rval[pos] = val;
-      a.rsrc[pos] = src;
+      const uint64_t small = a.wide ? 0ull : (((uint64_t)group << (F - 3)) | index);
+      mk.w[0] = (small << (64 - F)) | (mk.w[0] & (~0ull >> F));
+      Rec<W, F32> r;
+      r.k = mk;
+      r.v = val;
+      recs[pos] = r;
+      if (a.wide) a.rsrc_wide[pos] = (group << GROUP_SHIFT) | index;
     }
   };
 
@@ -176,7 +192,7 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
         V prod;
         if constexpr (F32) prod = cmulf(hc, bc);
         else prod = cmul(hc, bc);
-        deposit(c, times_2ie(prod, e), (a.comm_group << GROUP_SHIFT) | (uint32_t)h);
+        deposit(c, times_2ie(prod, e), a.comm_group, (uint32_t)h);
       };
 
       uint32_t qn = 0;  // wave-uniform queue fill
@@ -235,8 +251,7 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
           val.x = d.x;
           val.y = d.y;
         }
-        const uint32_t src = (a.tgroup[t] << GROUP_SHIFT) | (a.tlist[t] ? (uint32_t)k : 0u);
-        deposit(raw, val, src);
+        deposit(raw, val, a.tgroup[t], a.tlist[t] ? (uint32_t)k : 0u);
       }
     }
   }
@@ -252,7 +267,18 @@ __global__ void k_scan_cols(uint32_t* counts, int rows, uint32_t* bin_total, Ctl
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= NBINS) return;
   unsigned long long run = 0;
-  for (int r = 0; r < rows; ++r) {
+  int r = 0;
+  for (; r + 8 <= rows; r += 8) {
+    uint32_t c[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) c[q] = counts[(size_t)(r + q) * NBINS + b];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      counts[(size_t)(r + q) * NBINS + b] = (uint32_t)run;
+      run += c[q];
+    }
+  }
+  for (; r < rows; ++r) {
     const size_t idx = (size_t)r * NBINS + b;
     const uint32_t c = counts[idx];
     counts[idx] = (uint32_t)run;
@@ -330,9 +356,11 @@ struct MergeArgs {
   const uint32_t* bin_base;
   int g_log;
   int digit_shift;
-  const void* rkey;
-  const void* rval;
-  const uint32_t* rsrc;
+  int pass_bits;
+  uint32_t pass_id;
+  int wide;
+  const void* recs;
+  const uint32_t* rsrc_wide;
   double2 alpha[MAX_GROUPS];
   int alpha_kind[MAX_GROUPS];
   int gkind[MAX_GROUPS];
@@ -351,6 +379,7 @@ struct MergeArgs {
   uint32_t* b_slots;
   uint32_t* b_surv;
   uint32_t* b_keep;
+  uint32_t* b_unique;
   uint32_t* hist0;
   double2* norm_part;
   Ctl* ctl;
@@ -369,11 +398,10 @@ DEV bool keep_lookup(const Key<W>* keep, int n, const Key<W>& mk) {
   return false;
 }
 
-DEV double2 apply_alpha(const MergeArgs& a, int g, double2 v) {
-  const int k = a.alpha_kind[g];
-  if (k == A_ONE) return v;
-  if (k == A_I) return make_double2(-v.y, v.x);
-  return cmul(a.alpha[g], v);
+DEV double2 apply_alpha(int kind, double2 alpha, double2 v) {
+  if (kind == A_ONE) return v;
+  if (kind == A_I) return make_double2(-v.y, v.x);
+  return cmul(alpha, v);
 }
 
 DEV double round_to_f32(double v) { return (double)(float)v; }
@@ -384,12 +412,16 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
   constexpr int PER = MERGE_CAP / MERGE_THREADS;
   constexpr int DPT = NDIGITS / MERGE_THREADS;
   __shared__ Key<W> mk[MERGE_CAP];
+  __shared__ V sv[MERGE_CAP];
   __shared__ uint32_t sx[MERGE_CAP];
   __shared__ uint16_t perm[MERGE_CAP];
   __shared__ uint32_t dh[NDIGITS];
   __shared__ uint32_t h0[SEL0_BINS];
   __shared__ uint32_t scan_tmp[MERGE_THREADS / 64 + 1];
   __shared__ double red_hi[MERGE_THREADS / 64], red_lo[MERGE_THREADS / 64];
+  __shared__ int s_gk[MAX_GROUPS], s_ak[MAX_GROUPS];
+  __shared__ double2 s_al[MAX_GROUPS];
+  __shared__ uint32_t sbb[17];
 
   const int tid = threadIdx.x;
   const uint32_t j = blockIdx.x;
@@ -405,6 +437,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
       a.b_slots[gb] = 0;
       a.b_surv[gb] = 0;
       a.b_keep[gb] = 0;
+      a.b_unique[gb] = 0;
       if (a.mode == M_LANCZOS) a.norm_part[gb] = make_double2(0.0, 0.0);
     }
     return;
@@ -412,26 +445,48 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
   for (int i = tid; i < NDIGITS; i += MERGE_THREADS) dh[i] = 0u;
   if (a.mode == M_PLAIN)
     for (int i = tid; i < SEL0_BINS; i += MERGE_THREADS) h0[i] = 0u;
+  if (tid < MAX_GROUPS) {
+    s_gk[tid] = a.gkind[tid];
+    s_ak[tid] = a.alpha_kind[tid];
+    s_al[tid] = a.alpha[tid];
+  }
+  const int G = 1 << a.g_log;
+  if (tid <= G) sbb[tid] = a.bin_base[(j << a.g_log) + tid];
   __syncthreads();
 
-  const Key<W>* rk = reinterpret_cast<const Key<W>*>(a.rkey) + b0;
-  const V* rv = reinterpret_cast<const V*>(a.rval) + b0;
-  const uint32_t* rs = a.rsrc + b0;
-  uint32_t dig[PER], rnk[PER];
+  const Rec<W, F32>* recs = reinterpret_cast<const Rec<W, F32>*>(a.recs);
+  const int F = NBINS_LOG + a.pass_bits;
+  const uint32_t ibits = (uint32_t)(F - 3);
+  uint32_t dig[PER], rnk[PER], rsx[PER];
+  Key<W> rkey[PER];
+  V rval[PER];
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
     dig[k] = 0;
     rnk[k] = 0;
+    rsx[k] = 0;
     if (i < n) {
-      const Key<W> m = rk[i];
+      const uint32_t pos = b0 + i;
+      const Rec<W, F32> r = recs[pos];
+      int kb = 0;
+      while (kb + 1 < G && sbb[kb + 1] <= pos) kb++;
+      const uint64_t T = ((uint64_t)a.pass_id << NBINS_LOG) | (uint64_t)((j << a.g_log) + kb);
+      const uint32_t small = (uint32_t)(r.k.w[0] >> (64 - F));
+      Key<W> m = r.k;
+      m.w[0] = (T << (64 - F)) | (r.k.w[0] & (~0ull >> F));
+      rkey[k] = m;
+      rval[k] = r.v;
+      rsx[k] = a.wide ? a.rsrc_wide[pos]
+                      : (((small >> ibits) << GROUP_SHIFT) | (small & ((1u << ibits) - 1u)));
       mk[i] = m;
-      sx[i] = rs[i];
+      sx[i] = rsx[k];
       dig[k] = (uint32_t)((m.w[0] << a.digit_shift) >> (64 - DIGIT_BITS));
       rnk[k] = atomicAdd(&dh[dig[k]], 1u);
     }
   }
   __syncthreads();
+  // digit starts (exclusive scan of the digit counts)
   {
     uint32_t loc[DPT], s = 0;
 #pragma unroll
@@ -454,24 +509,38 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
     if (i < n) perm[dh[dig[k]] + rnk[k]] = (uint16_t)i;
   }
   __syncthreads();
-  // This thread owns digits [tid*DPT, tid*DPT + DPT): sorted positions [s0, s1).
-  const uint32_t s0 = dh[tid * DPT];
-  const uint32_t s1 = (tid + 1) * DPT < NDIGITS ? dh[(tid + 1) * DPT] : n;
-  // insertion sort of the range by (mixed key, source id)
-  for (uint32_t p = s0 + 1; p < s1; ++p) {
-    const uint16_t v = perm[p];
-    const Key<W> kv = mk[v];
-    const uint32_t sv = sx[v];
-    int q = (int)p - 1;
-    while (q >= (int)s0) {
-      const uint16_t u = perm[q];
-      const int c = key_cmp<W>(mk[u], kv);
-      if (c < 0 || (c == 0 && sx[u] < sv)) break;
-      perm[q + 1] = u;
-      --q;
+  // Final position of every record: its digit group's start plus the number of
+  // group members that precede it in (mixed key, source id) order.  Each
+  // record compares against its own group only (independent LDS loads).
+  uint32_t fpos[PER];
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const uint32_t i = tid + k * MERGE_THREADS;
+    fpos[k] = 0;
+    if (i < n) {
+      const uint32_t s0 = dh[dig[k]];
+      const uint32_t s1 = dig[k] + 1 < (uint32_t)NDIGITS ? dh[dig[k] + 1] : n;
+      uint32_t rank = 0;
+      for (uint32_t p = s0; p < s1; ++p) {
+        const uint16_t u = perm[p];
+        const int c = key_cmp<W>(mk[u], rkey[k]);
+        rank += (c < 0 || (c == 0 && sx[u] < rsx[k])) ? 1u : 0u;
+      }
+      fpos[k] = s0 + rank;
     }
-    perm[q + 1] = v;
   }
+  __syncthreads();
+  // move keys, sources and values into sorted order
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const uint32_t i = tid + k * MERGE_THREADS;
+    if (i < n) {
+      mk[fpos[k]] = rkey[k];
+      sx[fpos[k]] = rsx[k];
+      sv[fpos[k]] = rval[k];
+    }
+  }
+  __syncthreads();
 
   const Key<W>* keep = reinterpret_cast<const Key<W>*>(a.keep_mk);
   // Fold the run [p, q) of equal keys: groups in ascending id, a SUM group
@@ -485,22 +554,21 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
     float kr = 0.f, kcr = 0.f, ki = 0.f, kci = 0.f;
     auto finish = [&]() {
       double2 gv;
-      if (a.gkind[cur] == G_SUM_KAHAN32) gv = make_double2((double)kr - (double)kcr,
-                                                           (double)ki - (double)kci);
+      if (s_gk[cur] == G_SUM_KAHAN32) gv = make_double2((double)kr - (double)kcr,
+                                                        (double)ki - (double)kci);
       else gv = gs;
-      gv = apply_alpha(a, cur, gv);
+      gv = apply_alpha(s_ak[cur], s_al[cur], gv);
       if (!present) acc = gv;
       else acc = make_double2(acc.x + gv.x, acc.y + gv.y);
       present = true;
     };
     for (uint32_t r = p; r < q; ++r) {
-      const uint16_t idx = perm[r];
-      const int g = (int)(sx[idx] >> GROUP_SHIFT);
-      const V v = rv[idx];
+      const int g = (int)(sx[r] >> GROUP_SHIFT);
+      const V v = sv[r];
       if (g != cur) {
         if (cur >= 0) finish();
         cur = g;
-        if (a.gkind[g] == G_SUM_KAHAN32) {
+        if (s_gk[g] == G_SUM_KAHAN32) {
           kr = 0.f; kcr = 0.f; ki = 0.f; kci = 0.f;
           kahan_add(kr, kcr, (float)v.x);
           kahan_add(ki, kci, (float)v.y);
@@ -508,7 +576,7 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
           gs = make_double2((double)v.x, (double)v.y);
         }
       } else {
-        if (a.gkind[g] == G_SUM_KAHAN32) {
+        if (s_gk[g] == G_SUM_KAHAN32) {
           kahan_add(kr, kcr, (float)v.x);
           kahan_add(ki, kci, (float)v.y);
         } else {
@@ -521,69 +589,56 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
     out = acc;
     return !is_zero(acc);
   };
-  // Filters of the plain mode; returns survival, sets keep membership.
-  auto filters = [&](const Key<W>& m, double2 v, bool& is_keep) -> bool {
-    is_keep = false;
-    if (a.max_len > 0) {
-      const Key<W> raw = unmix_key<W>(m);
-      if (key_length<W>(raw) > a.max_len) return false;
-    }
-    if (a.use_eps && !(weight2(v) >= a.eps2)) return false;
-    if (a.n_keep) is_keep = keep_lookup<W>(keep, a.n_keep, m);
-    return true;
-  };
 
-  // sweep 1: count survivors
-  uint32_t cnt = 0, kc = 0;
+  // Sorted positions in rounds of MERGE_THREADS: the lane at the head of a run
+  // folds it, applies the filters (plain mode) and the survivors of a round
+  // are written in order at the running offset.
+  Key<W>* uk = reinterpret_cast<Key<W>*>(a.uk) + ub;
+  double2* uc = a.uc + ub;
+  uint32_t base = 0, kc = 0, nzu = 0;
   dd nrm = dd_zero();
-  for (uint32_t p = s0; p < s1;) {
-    uint32_t q = p + 1;
-    const Key<W> kp = mk[perm[p]];
-    while (q < s1 && key_eq<W>(mk[perm[q]], kp)) ++q;
-    double2 v;
-    if (fold(p, q, v)) {
-      if (a.mode == M_LANCZOS) {
-        cnt++;
-        nrm = dd_add(nrm, weight2(v));
-      } else {
-        bool isk;
-        if (filters(kp, v, isk)) {
-          cnt++;
-          if (isk) kc++;
-          else {
-            const double m2 = weight2(v);
-            atomicAdd(&h0[(uint32_t)(__double_as_longlong(m2) >> 52)], 1u);
+  const uint32_t nround = (n + MERGE_THREADS - 1) / MERGE_THREADS;
+  for (uint32_t r = 0; r < nround; r++) {
+    const uint32_t p = r * MERGE_THREADS + tid;
+    bool surv = false;
+    double2 v = make_double2(0.0, 0.0);
+    Key<W> raw;
+    if (p < n) {
+      const Key<W> kp = mk[p];
+      const bool head = p == 0 || !key_eq<W>(mk[p - 1], kp);
+      if (head) {
+        uint32_t q = p + 1;
+        while (q < n && key_eq<W>(mk[q], kp)) ++q;
+        if (fold(p, q, v)) {
+          nzu++;
+          raw = unmix_key<W>(kp);
+          surv = true;
+          if (a.mode == M_LANCZOS) {
+            nrm = dd_add(nrm, weight2(v));
+          } else {
+            if (a.max_len > 0 && key_length<W>(raw) > a.max_len) surv = false;
+            if (surv && a.use_eps && !(weight2(v) >= a.eps2)) surv = false;
+            if (surv) {
+              const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, kp) : false;
+              if (isk) kc++;
+              else atomicAdd(&h0[(uint32_t)(__double_as_longlong(weight2(v)) >> 52)], 1u);
+            }
           }
         }
       }
     }
-    p = q;
-  }
-  uint32_t tot_cnt, tot_kc;
-  const uint32_t off = block_exclusive_scan(cnt, scan_tmp, &tot_cnt);
-  (void)block_exclusive_scan(kc, scan_tmp, &tot_kc);
-
-  // sweep 2: write survivors (raw keys) to U
-  if (cnt) {
-    Key<W>* uk = reinterpret_cast<Key<W>*>(a.uk) + ub;
-    double2* uc = a.uc + ub;
-    uint32_t o = off;
-    for (uint32_t p = s0; p < s1;) {
-      uint32_t q = p + 1;
-      const Key<W> kp = mk[perm[p]];
-      while (q < s1 && key_eq<W>(mk[perm[q]], kp)) ++q;
-      double2 v;
-      if (fold(p, q, v)) {
-        bool isk = false;
-        if (a.mode == M_LANCZOS || filters(kp, v, isk)) {
-          uk[o] = unmix_key<W>(kp);
-          uc[o] = v;
-          ++o;
-        }
-      }
-      p = q;
+    uint32_t tot;
+    const uint32_t pos = block_exclusive_scan(surv ? 1u : 0u, scan_tmp, &tot);
+    if (surv) {
+      uk[base + pos] = raw;
+      uc[base + pos] = v;
     }
+    base += tot;
   }
+  uint32_t tot_pk;  // kc and nzu are <= MERGE_CAP: one scan of the packed pair
+  (void)block_exclusive_scan((kc << 16) | nzu, scan_tmp, &tot_pk);
+  const uint32_t tot_kc = tot_pk >> 16, tot_nzu = tot_pk & 0xFFFFu;
+  const uint32_t tot_cnt = base;
   if (a.mode == M_LANCZOS) {
     // block reduction of the double-double norm partial, fixed order
     const int lane = tid & 63, wv = tid >> 6;
@@ -600,22 +655,54 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
   }
   __syncthreads();
   if (a.mode == M_PLAIN) {
+    uint32_t* hrep = a.hist0 + (size_t)(j % HREP) * SEL0_BINS;
     for (int i = tid; i < SEL0_BINS; i += MERGE_THREADS)
-      if (h0[i]) atomicAdd(&a.hist0[i], h0[i]);
+      if (h0[i]) atomicAdd(&hrep[i], h0[i]);
   }
   if (tid == 0) {
     a.b_ubase[gb] = (uint32_t)ub;
     a.b_slots[gb] = tot_cnt;
     a.b_surv[gb] = tot_cnt;
     a.b_keep[gb] = tot_kc;
-    atomicAdd(&a.ctl->u_slots, (unsigned long long)tot_cnt);
-    atomicAdd(&a.ctl->surv_total, (unsigned long long)tot_cnt);
-    atomicAdd(&a.ctl->keep_total, (unsigned long long)tot_kc);
+    a.b_unique[gb] = tot_nzu;
     if (a.mode == M_LANCZOS) {
       dd s = {red_hi[0], red_lo[0]};
       for (int w = 1; w < MERGE_THREADS / 64; w++) s = dd_add(s, dd{red_hi[w], red_lo[w]});
       a.norm_part[gb] = make_double2(s.hi, s.lo);
     }
+  }
+}
+
+// Totals of the per-bucket counters (one block): slots, survivors, keep-set
+// survivors, nonzero uniques.
+__global__ __launch_bounds__(1024) void k_bucket_totals(const uint32_t* b_slots,
+                                                        const uint32_t* b_surv,
+                                                        const uint32_t* b_keep,
+                                                        const uint32_t* b_unique, uint32_t nb,
+                                                        Ctl* ctl) {
+  __shared__ unsigned long long red[4][16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  unsigned long long v[4] = {0, 0, 0, 0};
+  for (uint32_t b = t; b < nb; b += 1024) {
+    v[0] += b_slots[b];
+    v[1] += b_surv[b];
+    v[2] += b_keep[b];
+    if (b_unique) v[3] += b_unique[b];
+  }
+  for (int q = 0; q < 4; q++) {
+    unsigned long long x = v[q];
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_down(x, d, 64);
+    if (lane == 0) red[q][wv] = x;
+  }
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long tot[4] = {0, 0, 0, 0};
+    for (int q = 0; q < 4; q++)
+      for (int w = 0; w < 16; w++) tot[q] += red[q][w];
+    ctl->u_slots = tot[0];
+    ctl->surv_total = tot[1];
+    ctl->keep_total = tot[2];
+    if (b_unique) ctl->u_unique = tot[3];
   }
 }
 
@@ -705,15 +792,12 @@ __global__ __launch_bounds__(256) void k_scale_filter(ScaleArgs a) {
     rk[wv] = kc;
   }
   __syncthreads();
+  uint32_t* hrep = a.hist0 + (size_t)(b % HREP) * SEL0_BINS;
   for (int i = tid; i < SEL0_BINS; i += 256)
-    if (h0[i]) atomicAdd(&a.hist0[i], h0[i]);
+    if (h0[i]) atomicAdd(&hrep[i], h0[i]);
   if (tid == 0) {
-    const uint32_t s = rs[0] + rs[1] + rs[2] + rs[3];
-    const uint32_t k = rk[0] + rk[1] + rk[2] + rk[3];
-    a.b_surv[b] = s;
-    a.b_keep[b] = k;
-    atomicAdd(&a.ctl->surv_total, (unsigned long long)s);
-    atomicAdd(&a.ctl->keep_total, (unsigned long long)k);
+    a.b_surv[b] = rs[0] + rs[1] + rs[2] + rs[3];
+    a.b_keep[b] = rk[0] + rk[1] + rk[2] + rk[3];
   }
 }
 
@@ -762,8 +846,11 @@ __global__ __launch_bounds__(1024) void k_select(const uint32_t* hist, int nbins
   const int per = nbins / 1024;  // nbins is 2048 or 4096
   // thread t owns bins [nbins - (t+1)*per, nbins - t*per), scanned high to low
   const int hiB = nbins - t * per;
+  unsigned int hv[4] = {0u, 0u, 0u, 0u};
+  for (int r = 0; r < HREP; r++)
+    for (int q = 1; q <= per; q++) hv[q - 1] += hist[(size_t)r * nbins + hiB - q];
   unsigned long long s = 0;
-  for (int q = 1; q <= per; q++) s += hist[hiB - q];
+  for (int q = 1; q <= per; q++) s += hv[q - 1];
   const int lane = t & 63, wv = t >> 6;
   unsigned long long x = s;
   for (int d = 1; d < 64; d <<= 1) {
@@ -785,7 +872,7 @@ __global__ __launch_bounds__(1024) void k_select(const uint32_t* hist, int nbins
   unsigned long long cum = tmp[wv] + x - s;  // records in bins above this thread's
   for (int q = 1; q <= per; q++) {
     const int b = hiB - q;
-    const unsigned long long h = hist[b];
+    const unsigned long long h = hv[q - 1];
     if (cum < K && K <= cum + h) {
       ctl->sel_digit = (unsigned int)b;
       ctl->sel_K = K - cum;
@@ -804,32 +891,25 @@ struct SelArgs {
   const double2* uc;
   const void* keep_mk;
   int n_keep;
-  uint32_t* cand_in;   // pairs (U index, bucket)
-  uint32_t* cand_out;
-  unsigned long long cand_cap;
+  uint32_t nbk;
+  // candidate lists: the entries of bucket b sit at [b_ubase[b], b_ubase[b] + cc[b])
+  const uint32_t* list_in;
+  const uint32_t* cc_in;
+  uint32_t* list_out;
+  uint32_t* cc_out;
   int level;
-  uint32_t* hist;      // next-level histogram (SEL_BINS)
+  uint32_t* hist;  // histogram of the next digit (nullable)
   Ctl* ctl;
-  int in_slot, out_slot;
 };
 
-DEV uint32_t wave_append(unsigned long long* counter, bool pred) {
-  const uint64_t m = __ballot(pred);
-  if (!m) return 0;
-  const int leader = __ffsll((long long)m) - 1;
-  unsigned long long base = 0;
-  if ((int)__lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
-  base = __shfl(base, leader, 64);
-  return (uint32_t)(base + mbcnt64(m));
-}
-
-// Level 1: full pass over U.  Counts per bucket the non-keep survivors whose
-// digit 0 is above the chosen bin, collects the chosen bin's records and
-// histograms their digit 1.
+// Level 1: one block per bucket, full pass over its U slots.  Counts the
+// non-keep survivors whose digit 0 is above the chosen bin, collects the
+// chosen bin's records (in bucket order) and histograms their digit 1.
 template <int W>
 __global__ __launch_bounds__(256) void k_level1(SelArgs a) {
   __shared__ uint32_t h[SEL_BINS];
   __shared__ uint32_t ra[4];
+  __shared__ uint32_t scan_tmp[256 / 64 + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint32_t b = blockIdx.x;
   for (int i = tid; i < SEL_BINS; i += 256) h[i] = 0u;
@@ -839,7 +919,7 @@ __global__ __launch_bounds__(256) void k_level1(SelArgs a) {
   const Key<W>* uk = reinterpret_cast<const Key<W>*>(a.uk) + ub;
   const double2* uc = a.uc + ub;
   const Key<W>* keep = reinterpret_cast<const Key<W>*>(a.keep_mk);
-  uint32_t abv = 0;
+  uint32_t abv = 0, nout = 0;
   const uint32_t nround = (ns + 255) / 256;
   for (uint32_t r = 0; r < nround; r++) {
     const uint32_t i = r * 256 + tid;
@@ -858,59 +938,78 @@ __global__ __launch_bounds__(256) void k_level1(SelArgs a) {
         }
       }
     }
-    const uint32_t pos = wave_append(&a.ctl->cand_n[a.out_slot], cand);
-    if (cand && pos < a.cand_cap) {
-      a.cand_out[2 * (size_t)pos] = ub + i;
-      a.cand_out[2 * (size_t)pos + 1] = b;
+    uint32_t tot;
+    const uint32_t pos = block_exclusive_scan(cand ? 1u : 0u, scan_tmp, &tot);
+    if (cand) {
+      a.list_out[ub + nout + pos] = ub + i;
       atomicAdd(&h[comp_digit<W>(c, 1)], 1u);
     }
+    nout += tot;
   }
   for (int d = 32; d >= 1; d >>= 1) abv += __shfl_down(abv, d, 64);
   if (lane == 0) ra[wv] = abv;
   __syncthreads();
+  uint32_t* hrep = a.hist + (size_t)(b % HREP) * SEL_BINS;
   for (int i = tid; i < SEL_BINS; i += 256)
-    if (h[i]) atomicAdd(&a.hist[i], h[i]);
-  if (tid == 0) a.b_abv[b] = ra[0] + ra[1] + ra[2] + ra[3];
+    if (h[i]) atomicAdd(&hrep[i], h[i]);
+  if (tid == 0) {
+    a.b_abv[b] = ra[0] + ra[1] + ra[2] + ra[3];
+    a.cc_out[b] = nout;
+  }
 }
 
-// Level L >= 1 over a candidate list: keep the records whose digit L equals
-// the chosen bin, histogram their digit L+1.
+// Level L >= 1, one block per bucket over its candidates: keep those whose
+// digit L equals the chosen bin, histogram their digit L+1 (if hist given).
 template <int W>
 __global__ __launch_bounds__(256) void k_cand_level(SelArgs a) {
   __shared__ uint32_t h[SEL_BINS];
+  __shared__ uint32_t scan_tmp[256 / 64 + 1];
   const int tid = threadIdx.x;
-  for (int i = tid; i < SEL_BINS; i += 256) h[i] = 0u;
+  const uint32_t b = blockIdx.x;
+  const uint32_t n = a.cc_in[b];
+  if (n == 0) {
+    if (tid == 0) a.cc_out[b] = 0;
+    return;
+  }
+  const bool with_hist = a.hist != nullptr;
+  if (with_hist)
+    for (int i = tid; i < SEL_BINS; i += 256) h[i] = 0u;
   __syncthreads();
   const uint32_t D = a.ctl->sel_digit;
-  const unsigned long long n = a.ctl->cand_n[a.in_slot];
+  const uint32_t ub = a.b_ubase[b];
   const Key<W>* ukb = reinterpret_cast<const Key<W>*>(a.uk);
-  const unsigned long long stride = (unsigned long long)gridDim.x * 256;
-  const unsigned long long nround = (n + stride - 1) / stride;
-  for (unsigned long long r = 0; r < nround; r++) {
-    const unsigned long long i = r * stride + (unsigned long long)blockIdx.x * 256 + tid;
+  uint32_t nout = 0;
+  const uint32_t nround = (n + 255) / 256;
+  for (uint32_t r = 0; r < nround; r++) {
+    const uint32_t i = r * 256 + tid;
     bool keepit = false;
     uint64_t c[1 + 2 * W];
-    uint32_t ui = 0, bk = 0;
+    uint32_t ui = 0;
     if (i < n) {
-      ui = a.cand_in[2 * i];
-      bk = a.cand_in[2 * i + 1];
+      ui = a.list_in[ub + i];
       composite<W>(a.uc[ui], ukb[ui], c);
       keepit = comp_digit<W>(c, a.level) == D;
     }
-    const uint32_t pos = wave_append(&a.ctl->cand_n[a.out_slot], keepit);
-    if (keepit && pos < a.cand_cap) {
-      a.cand_out[2 * (size_t)pos] = ui;
-      a.cand_out[2 * (size_t)pos + 1] = bk;
-      atomicAdd(&h[comp_digit<W>(c, a.level + 1)], 1u);
+    uint32_t tot;
+    const uint32_t pos = block_exclusive_scan(keepit ? 1u : 0u, scan_tmp, &tot);
+    if (keepit) {
+      a.list_out[ub + nout + pos] = ui;
+      if (with_hist) atomicAdd(&h[comp_digit<W>(c, a.level + 1)], 1u);
     }
+    nout += tot;
   }
   __syncthreads();
-  for (int i = tid; i < SEL_BINS; i += 256)
-    if (h[i]) atomicAdd(&a.hist[i], h[i]);
+  if (with_hist) {
+    uint32_t* hrep = a.hist + (size_t)(b % HREP) * SEL_BINS;
+    for (int i = tid; i < SEL_BINS; i += 256)
+      if (h[i]) atomicAdd(&hrep[i], h[i]);
+  }
+  if (tid == 0) a.cc_out[b] = nout;
 }
 
-// Final level: at most FINISH_CAP candidates of the chosen bin; the one of
-// rank K-1 (descending composite) is the threshold T.
+// Final level (one block): every entry of list_in belongs to the chosen bin
+// and there are at most FINISH_CAP of them; the entry of rank K-1
+// (descending composite) is the threshold T.
 template <int W>
 __global__ __launch_bounds__(1024) void k_finish(SelArgs a) {
   constexpr int NW = 1 + 2 * W;
@@ -919,14 +1018,15 @@ __global__ __launch_bounds__(1024) void k_finish(SelArgs a) {
   const int tid = threadIdx.x;
   if (tid == 0) m = 0;
   __syncthreads();
-  const uint32_t D = a.ctl->sel_digit;
-  const unsigned long long n = a.ctl->cand_n[a.in_slot];
   const Key<W>* ukb = reinterpret_cast<const Key<W>*>(a.uk);
-  for (unsigned long long i = tid; i < n; i += 1024) {
-    uint64_t c[NW];
-    const uint32_t ui = a.cand_in[2 * i];
-    composite<W>(a.uc[ui], ukb[ui], c);
-    if (comp_digit<W>(c, a.level) == D) {
+  for (uint32_t b = tid; b < a.nbk; b += 1024) {
+    const uint32_t n = a.cc_in[b];
+    if (!n) continue;
+    const uint32_t ub = a.b_ubase[b];
+    for (uint32_t k = 0; k < n; k++) {
+      const uint32_t ui = a.list_in[ub + k];
+      uint64_t c[NW];
+      composite<W>(a.uc[ui], ukb[ui], c);
       const unsigned int p = atomicAdd(&m, 1u);
       if (p < FINISH_CAP)
         for (int q = 0; q < NW; q++) cs[p][q] = c[q];
@@ -945,21 +1045,27 @@ __global__ __launch_bounds__(1024) void k_finish(SelArgs a) {
   }
 }
 
-// Per bucket: level-1 candidates at or above the threshold.
+// Per bucket (one wave): level-1 candidates at or above the threshold.
 template <int W>
-__global__ __launch_bounds__(256) void k_count_boundary(SelArgs a) {
+__global__ __launch_bounds__(64) void k_count_boundary(SelArgs a) {
   constexpr int NW = 1 + 2 * W;
-  const unsigned long long n = a.ctl->cand_n[a.in_slot];
-  uint64_t T[NW];
-  for (int q = 0; q < NW; q++) T[q] = a.ctl->T[q];
-  const Key<W>* ukb = reinterpret_cast<const Key<W>*>(a.uk);
-  for (unsigned long long i = (unsigned long long)blockIdx.x * 256 + threadIdx.x; i < n;
-       i += (unsigned long long)gridDim.x * 256) {
-    const uint32_t ui = a.cand_in[2 * i], bk = a.cand_in[2 * i + 1];
-    uint64_t c[NW];
-    composite<W>(a.uc[ui], ukb[ui], c);
-    if (comp_cmp<W>(c, T) >= 0) atomicAdd(&a.b_bcnt[bk], 1u);
+  const uint32_t b = blockIdx.x;
+  const uint32_t n = a.cc_in[b];
+  uint32_t cnt = 0;
+  if (n) {
+    uint64_t T[NW];
+    for (int q = 0; q < NW; q++) T[q] = a.ctl->T[q];
+    const uint32_t ub = a.b_ubase[b];
+    const Key<W>* ukb = reinterpret_cast<const Key<W>*>(a.uk);
+    for (uint32_t i = threadIdx.x; i < n; i += 64) {
+      const uint32_t ui = a.list_in[ub + i];
+      uint64_t c[NW];
+      composite<W>(a.uc[ui], ukb[ui], c);
+      if (comp_cmp<W>(c, T) >= 0) cnt++;
+    }
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_down(cnt, d, 64);
   }
+  if (threadIdx.x == 0) a.b_bcnt[b] = cnt;
 }
 
 // Output bases: survivors per bucket are counted according to the select

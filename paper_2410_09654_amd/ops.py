@@ -353,3 +353,10 @@ def profile_read() -> dict:
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+def last_stats() -> dict:
+    """Counters of the last engine pass on this thread (see pauli_stats)."""
+    st = _lib.PauliStatsC()
+    _lib.load().pauli_last_stats(ctypes.byref(st))
+    return {k: getattr(st, k) for k, _ in _lib.PauliStatsC._fields_}

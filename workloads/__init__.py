@@ -232,11 +232,13 @@ def random_local_strings(n_qubits: int, count: int, max_support: int = 10,
     W = n_words(n_qubits)
     rng = np.random.Generator(np.random.PCG64(seed))
     max_support = min(max_support, n_qubits)
+    rowtype = np.dtype((np.void, 16 * W))
     xs = np.zeros((0, W), np.uint64)
     zs = np.zeros((0, W), np.uint64)
-    seen_rows = None
+    seen = np.zeros(0, rowtype)  # sorted void view of the rows kept so far
     while xs.shape[0] < count:
-        batch = max(1024, int((count - xs.shape[0]) * 1.3))
+        need = count - xs.shape[0]
+        batch = max(4096, 2 * need + count // 4)
         length = rng.integers(1, max_support + 1, size=batch)
         start = rng.integers(0, n_qubits - length + 1)  # 0-based first site
         paulis = rng.integers(1, 4, size=(batch, max_support))  # 1=X 2=Z 3=Y
@@ -253,15 +255,14 @@ def random_local_strings(n_qubits: int, count: int, max_support: int = 10,
                 sel = word == w
                 bx[:, w] |= np.where(px & sel, np.uint64(1) << bit, np.uint64(0))
                 bz[:, w] |= np.where(pz & sel, np.uint64(1) << bit, np.uint64(0))
-        cx = np.concatenate([xs, bx])
-        cz = np.concatenate([zs, bz])
-        rows = np.concatenate([cx, cz], axis=1)
-        _, first = np.unique(rows, axis=0, return_index=True)
-        first.sort()
-        keep = first[:count]
-        xs, zs = cx[keep], cz[keep]
-        seen_rows = rows
-    del seen_rows
+        rows = np.ascontiguousarray(np.concatenate([bx, bz], axis=1)).view(rowtype).ravel()
+        _, first = np.unique(rows, return_index=True)
+        first.sort()                                   # first draws within the batch, in order
+        fresh = first[~np.isin(rows[first], seen)]     # skip strings drawn in earlier batches
+        fresh = fresh[:need]
+        xs = np.concatenate([xs, bx[fresh]])
+        zs = np.concatenate([zs, bz[fresh]])
+        seen = np.sort(np.concatenate([seen, rows[fresh]]))
     coef = rng.standard_normal(count) + 1j * rng.standard_normal(count)
     if coef_dist != "normal":
         raise ValueError(coef_dist)
