@@ -35,11 +35,27 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 17,
                     help="O strings given to the CPU oracle (0: skip the CPU baseline)")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times "
+                         "(reference for the HBM traffic counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(nbytes: int):
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 5}), flush=True)
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the engine has no multi-GPU path "
               "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)

@@ -290,6 +290,7 @@ int Engine::run(Call& c) {
   uint32_t* histL[2];
   histL[0] = (uint32_t*)ar->take((size_t)HREP * SEL_BINS * 4);
   histL[1] = (uint32_t*)ar->take((size_t)HREP * SEL_BINS * 4);
+  uint32_t* hsum = (uint32_t*)ar->take(SEL_BINS * 4);
   if (ar->short_) return PAULI_EWORKSPACE;
   TRY(host_ctl(&hctl));
   TRY(zero_u32(dctl, sizeof(Ctl) / 4));
@@ -482,6 +483,7 @@ int Engine::run(Call& c) {
     double* nrm = (double*)ar->take(16);
     if (ar->short_) return PAULI_EWORKSPACE;
     if (nbk) {
+      LAUNCH("k_norm_bucket", k_norm_bucket, nbk, 256, b_ubase, b_slots, uc, norm_part);
       LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, norm_part, nbk, nrm);
       HIP_TRY(hipMemcpyAsync(&hctl->norm_hi, nrm, 16, hipMemcpyDeviceToHost, stream));
       HIP_TRY(hipStreamSynchronize(stream));
@@ -544,7 +546,8 @@ int Engine::run(Call& c) {
       sa.nbk = nbk;
       sa.ctl = dctl;
       TRY(set_u64(&dctl->sel_K, (unsigned long long)budget));
-      LAUNCH("k_select", k_select, 1, 1024, hist0, SEL0_BINS, dctl);
+      LAUNCH("k_hist_reduce", k_hist_reduce, SEL0_BINS / 256, 256, hist0, SEL0_BINS, hsum);
+      LAUNCH("k_select", k_select, 1, 1024, hsum, SEL0_BINS, dctl);
       // level 1: full pass over U into list 0 (kept for the boundary count)
       TRY(zero_u32(histL[0], (size_t)HREP * SEL_BINS));
       sa.list_out = cand[0];
@@ -556,7 +559,8 @@ int Engine::run(Call& c) {
       unsigned long long cnt = hctl->sel_count;
       if (cnt > FINISH_CAP) {
         int level = 1, hslot = 0;
-        LAUNCH("k_select", k_select, 1, 1024, histL[0], SEL_BINS, dctl);
+        LAUNCH("k_hist_reduce", k_hist_reduce, SEL_BINS / 256, 256, histL[0], SEL_BINS, hsum);
+        LAUNCH("k_select", k_select, 1, 1024, hsum, SEL_BINS, dctl);
         TRY(read_ctl());
         cnt = hctl->sel_count;
         while (cnt > FINISH_CAP) {
@@ -574,7 +578,9 @@ int Engine::run(Call& c) {
           sa.hist = histL[hslot];
           sa.level = level;
           LAUNCH("k_cand_level", (k_cand_level<W>), nbk, 256, sa);
-          LAUNCH("k_select", k_select, 1, 1024, histL[hslot], SEL_BINS, dctl);
+          LAUNCH("k_hist_reduce", k_hist_reduce, SEL_BINS / 256, 256, histL[hslot], SEL_BINS,
+                 hsum);
+          LAUNCH("k_select", k_select, 1, 1024, hsum, SEL_BINS, dctl);
           TRY(read_ctl());
           cnt = hctl->sel_count;
           in = out;

@@ -407,21 +407,26 @@ DEV double2 apply_alpha(int kind, double2 alpha, double2 v) {
 DEV double round_to_f32(double v) { return (double)(float)v; }
 
 template <int W, bool F32>
-__global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
+__global__ __launch_bounds__(MERGE_THREADS)
+__attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
   using V = RecV<F32>;
-  constexpr int PER = MERGE_CAP / MERGE_THREADS;
+  constexpr int PER = (MERGE_CAP + MERGE_THREADS - 1) / MERGE_THREADS;
   constexpr int DPT = NDIGITS / MERGE_THREADS;
+  static_assert(SEL0_BINS == NDIGITS, "digit counts and |c|^2 histogram share LDS");
+  // mk / sx hold the records first in digit-group order (while ranks are
+  // computed), then in final sorted order; dh holds the digit counts and
+  // starts, then the exponent histogram of |c|^2.
   __shared__ Key<W> mk[MERGE_CAP];
   __shared__ V sv[MERGE_CAP];
   __shared__ uint32_t sx[MERGE_CAP];
-  __shared__ uint16_t perm[MERGE_CAP];
   __shared__ uint32_t dh[NDIGITS];
-  __shared__ uint32_t h0[SEL0_BINS];
+  uint32_t* const h0 = dh;
   __shared__ uint32_t scan_tmp[MERGE_THREADS / 64 + 1];
-  __shared__ double red_hi[MERGE_THREADS / 64], red_lo[MERGE_THREADS / 64];
   __shared__ int s_gk[MAX_GROUPS], s_ak[MAX_GROUPS];
   __shared__ double2 s_al[MAX_GROUPS];
   __shared__ uint32_t sbb[17];
+  constexpr int NHW = (MERGE_CAP + 63) / 64;
+  __shared__ uint64_t hmask[NHW];  // bit p: sorted position p starts a run of equal keys
 
   const int tid = threadIdx.x;
   const uint32_t j = blockIdx.x;
@@ -438,13 +443,10 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
       a.b_surv[gb] = 0;
       a.b_keep[gb] = 0;
       a.b_unique[gb] = 0;
-      if (a.mode == M_LANCZOS) a.norm_part[gb] = make_double2(0.0, 0.0);
     }
     return;
   }
   for (int i = tid; i < NDIGITS; i += MERGE_THREADS) dh[i] = 0u;
-  if (a.mode == M_PLAIN)
-    for (int i = tid; i < SEL0_BINS; i += MERGE_THREADS) h0[i] = 0u;
   if (tid < MAX_GROUPS) {
     s_gk[tid] = a.gkind[tid];
     s_ak[tid] = a.alpha_kind[tid];
@@ -459,7 +461,6 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
   const uint32_t ibits = (uint32_t)(F - 3);
   uint32_t dig[PER], rnk[PER], rsx[PER];
   Key<W> rkey[PER];
-  V rval[PER];
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
@@ -476,11 +477,8 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
       Key<W> m = r.k;
       m.w[0] = (T << (64 - F)) | (r.k.w[0] & (~0ull >> F));
       rkey[k] = m;
-      rval[k] = r.v;
       rsx[k] = a.wide ? a.rsrc_wide[pos]
                       : (((small >> ibits) << GROUP_SHIFT) | (small & ((1u << ibits) - 1u)));
-      mk[i] = m;
-      sx[i] = rsx[k];
       dig[k] = (uint32_t)((m.w[0] << a.digit_shift) >> (64 - DIGIT_BITS));
       rnk[k] = atomicAdd(&dh[dig[k]], 1u);
     }
@@ -503,15 +501,18 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
     }
   }
   __syncthreads();
+  // records in digit-group order
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
-    if (i < n) perm[dh[dig[k]] + rnk[k]] = (uint16_t)i;
+    if (i < n) {
+      mk[dh[dig[k]] + rnk[k]] = rkey[k];
+      sx[dh[dig[k]] + rnk[k]] = rsx[k];
+    }
   }
   __syncthreads();
   // Final position of every record: its digit group's start plus the number of
-  // group members that precede it in (mixed key, source id) order.  Each
-  // record compares against its own group only (independent LDS loads).
+  // group members that precede it in (mixed key, source id) order.
   uint32_t fpos[PER];
 #pragma unroll
   for (int k = 0; k < PER; k++) {
@@ -521,23 +522,37 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
       const uint32_t s0 = dh[dig[k]];
       const uint32_t s1 = dig[k] + 1 < (uint32_t)NDIGITS ? dh[dig[k] + 1] : n;
       uint32_t rank = 0;
-      for (uint32_t p = s0; p < s1; ++p) {
-        const uint16_t u = perm[p];
-        const int c = key_cmp<W>(mk[u], rkey[k]);
-        rank += (c < 0 || (c == 0 && sx[u] < rsx[k])) ? 1u : 0u;
+      for (uint32_t p = s0; p < s1; p += 2) {
+        // two group members per step: both LDS loads are issued before use
+        Key<W> k0 = mk[p], k1 = k0;
+        uint32_t x0 = sx[p], x1 = 0;
+        const bool two = p + 1 < s1;
+        if (two) {
+          k1 = mk[p + 1];
+          x1 = sx[p + 1];
+        }
+        const int c0 = key_cmp<W>(k0, rkey[k]);
+        rank += (c0 < 0 || (c0 == 0 && x0 < rsx[k])) ? 1u : 0u;
+        if (two) {
+          const int c1 = key_cmp<W>(k1, rkey[k]);
+          rank += (c1 < 0 || (c1 == 0 && x1 < rsx[k])) ? 1u : 0u;
+        }
       }
       fpos[k] = s0 + rank;
     }
   }
   __syncthreads();
-  // move keys, sources and values into sorted order
+  // keys, sources and values in sorted order; the digit counts become the
+  // exponent histogram
+  if (a.mode == M_PLAIN)
+    for (int i = tid; i < SEL0_BINS; i += MERGE_THREADS) h0[i] = 0u;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
     if (i < n) {
       mk[fpos[k]] = rkey[k];
       sx[fpos[k]] = rsx[k];
-      sv[fpos[k]] = rval[k];
+      sv[fpos[k]] = recs[b0 + i].v;  // second read of the record, from cache
     }
   }
   __syncthreads();
@@ -551,24 +566,38 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
     double2 acc = make_double2(0.0, 0.0);
     int cur = -1;
     double2 gs = make_double2(0.0, 0.0);
-    float kr = 0.f, kcr = 0.f, ki = 0.f, kci = 0.f;
+    float kr = 0.f, kcr = 0.f, ki = 0.f, kci = 0.f;  // Kahan state (FP32 records only)
     auto finish = [&]() {
-      double2 gv;
-      if (s_gk[cur] == G_SUM_KAHAN32) gv = make_double2((double)kr - (double)kcr,
-                                                        (double)ki - (double)kci);
-      else gv = gs;
+      double2 gv = gs;
+      if constexpr (F32) {
+        if (s_gk[cur] == G_SUM_KAHAN32)
+          gv = make_double2((double)kr - (double)kcr, (double)ki - (double)kci);
+      }
       gv = apply_alpha(s_ak[cur], s_al[cur], gv);
       if (!present) acc = gv;
       else acc = make_double2(acc.x + gv.x, acc.y + gv.y);
       present = true;
     };
-    for (uint32_t r = p; r < q; ++r) {
-      const int g = (int)(sx[r] >> GROUP_SHIFT);
-      const V v = sv[r];
+    constexpr int FU = 2;  // run entries loaded per step (LDS loads issued together)
+    for (uint32_t r0 = p; r0 < q; r0 += FU) {
+     uint32_t gx[FU];
+     V vv[FU];
+#pragma unroll
+     for (int u = 0; u < FU; u++)
+       if (r0 + u < q) {
+         gx[u] = sx[r0 + u];
+         vv[u] = sv[r0 + u];
+       }
+#pragma unroll
+     for (int u = 0; u < FU; u++) {
+      if (r0 + u >= q) break;
+      const int g = (int)(gx[u] >> GROUP_SHIFT);
+      const V v = vv[u];
+      const bool kahan = F32 && s_gk[g] == G_SUM_KAHAN32;
       if (g != cur) {
         if (cur >= 0) finish();
         cur = g;
-        if (s_gk[g] == G_SUM_KAHAN32) {
+        if (kahan) {
           kr = 0.f; kcr = 0.f; ki = 0.f; kci = 0.f;
           kahan_add(kr, kcr, (float)v.x);
           kahan_add(ki, kci, (float)v.y);
@@ -576,13 +605,14 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
           gs = make_double2((double)v.x, (double)v.y);
         }
       } else {
-        if (s_gk[g] == G_SUM_KAHAN32) {
+        if (kahan) {
           kahan_add(kr, kcr, (float)v.x);
           kahan_add(ki, kci, (float)v.y);
         } else {
           gs = make_double2(gs.x + (double)v.x, gs.y + (double)v.y);
         }
       }
+     }
     }
     if (cur >= 0) finish();
     if (a.round32) acc = make_double2(round_to_f32(acc.x), round_to_f32(acc.y));
@@ -596,26 +626,42 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
   Key<W>* uk = reinterpret_cast<Key<W>*>(a.uk) + ub;
   double2* uc = a.uc + ub;
   uint32_t base = 0, kc = 0, nzu = 0;
-  dd nrm = dd_zero();
   const uint32_t nround = (n + MERGE_THREADS - 1) / MERGE_THREADS;
+  const uint32_t nwords = (n + 63) / 64;
+  for (uint32_t r = 0; r < nround; r++) {
+    const uint32_t p = r * MERGE_THREADS + tid;
+    const bool head = p < n && (p == 0 || !key_eq<W>(mk[p - 1], mk[p]));
+    const uint64_t m = __ballot(head);
+    if ((tid & 63) == 0 && (p >> 6) < (uint32_t)NHW) hmask[p >> 6] = m;
+  }
+  __syncthreads();
   for (uint32_t r = 0; r < nround; r++) {
     const uint32_t p = r * MERGE_THREADS + tid;
     bool surv = false;
     double2 v = make_double2(0.0, 0.0);
     Key<W> raw;
-    if (p < n) {
+    if (p < n && ((hmask[p >> 6] >> (p & 63)) & 1ull)) {
       const Key<W> kp = mk[p];
-      const bool head = p == 0 || !key_eq<W>(mk[p - 1], kp);
-      if (head) {
-        uint32_t q = p + 1;
-        while (q < n && key_eq<W>(mk[q], kp)) ++q;
+      {
+        // end of the run: the next head bit after p (or n)
+        uint32_t q = n;
+        const uint32_t w = p >> 6, bp = p & 63;
+        const uint64_t rest = bp == 63 ? 0ull : (hmask[w] >> (bp + 1));
+        if (rest) {
+          q = p + 1 + (uint32_t)__builtin_ctzll(rest);
+        } else {
+          for (uint32_t ww = w + 1; ww < nwords; ww++)
+            if (hmask[ww]) {
+              q = ww * 64 + (uint32_t)__builtin_ctzll(hmask[ww]);
+              break;
+            }
+        }
+        if (q > n) q = n;
         if (fold(p, q, v)) {
           nzu++;
           raw = unmix_key<W>(kp);
           surv = true;
-          if (a.mode == M_LANCZOS) {
-            nrm = dd_add(nrm, weight2(v));
-          } else {
+          if (a.mode != M_LANCZOS) {
             if (a.max_len > 0 && key_length<W>(raw) > a.max_len) surv = false;
             if (surv && a.use_eps && !(weight2(v) >= a.eps2)) surv = false;
             if (surv) {
@@ -639,20 +685,6 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
   (void)block_exclusive_scan((kc << 16) | nzu, scan_tmp, &tot_pk);
   const uint32_t tot_kc = tot_pk >> 16, tot_nzu = tot_pk & 0xFFFFu;
   const uint32_t tot_cnt = base;
-  if (a.mode == M_LANCZOS) {
-    // block reduction of the double-double norm partial, fixed order
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int d = 32; d >= 1; d >>= 1) {
-      dd o2;
-      o2.hi = __shfl_down(nrm.hi, d, 64);
-      o2.lo = __shfl_down(nrm.lo, d, 64);
-      if (lane < d) nrm = dd_add(nrm, o2);
-    }
-    if (lane == 0) {
-      red_hi[wv] = nrm.hi;
-      red_lo[wv] = nrm.lo;
-    }
-  }
   __syncthreads();
   if (a.mode == M_PLAIN) {
     uint32_t* hrep = a.hist0 + (size_t)(j % HREP) * SEL0_BINS;
@@ -665,11 +697,35 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_merge(MergeArgs a) {
     a.b_surv[gb] = tot_cnt;
     a.b_keep[gb] = tot_kc;
     a.b_unique[gb] = tot_nzu;
-    if (a.mode == M_LANCZOS) {
-      dd s = {red_hi[0], red_lo[0]};
-      for (int w = 1; w < MERGE_THREADS / 64; w++) s = dd_add(s, dd{red_hi[w], red_lo[w]});
-      a.norm_part[gb] = make_double2(s.hi, s.lo);
-    }
+  }
+}
+
+// Lanczos: double-double partial of sum |c|^2 over one bucket of the merged,
+// untruncated O'_n (fixed reduction order).
+__global__ __launch_bounds__(256) void k_norm_bucket(const uint32_t* b_ubase,
+                                                     const uint32_t* b_slots, const double2* uc,
+                                                     double2* part) {
+  __shared__ double rh[4], rl[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t b = blockIdx.x;
+  const uint32_t ub = b_ubase[b], ns = b_slots[b];
+  dd s = dd_zero();
+  for (uint32_t i = tid; i < ns; i += 256) s = dd_add(s, weight2(uc[ub + i]));
+  for (int d = 32; d >= 1; d >>= 1) {
+    dd o;
+    o.hi = __shfl_down(s.hi, d, 64);
+    o.lo = __shfl_down(s.lo, d, 64);
+    if (lane < d) s = dd_add(s, o);
+  }
+  if (lane == 0) {
+    rh[wv] = s.hi;
+    rl[wv] = s.lo;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    dd t = {rh[0], rl[0]};
+    for (int w = 1; w < 4; w++) t = dd_add(t, dd{rh[w], rl[w]});
+    part[b] = make_double2(t.hi, t.lo);
   }
 }
 
@@ -837,6 +893,16 @@ DEV int comp_cmp(const uint64_t* a, const uint64_t* b) {
   return 0;
 }
 
+// Sum of the HREP replicas of a select histogram.
+__global__ void k_hist_reduce(const uint32_t* rep, int nbins, uint32_t* sum) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  uint32_t s = 0;
+#pragma unroll 8
+  for (int r = 0; r < HREP; r++) s += rep[(size_t)r * nbins + b];
+  sum[b] = s;
+}
+
 // Pick the bin holding the K-th largest: K from ctl->sel_K (1-based).
 __global__ __launch_bounds__(1024) void k_select(const uint32_t* hist, int nbins, Ctl* ctl) {
   __shared__ unsigned long long tmp[17];
@@ -847,8 +913,7 @@ __global__ __launch_bounds__(1024) void k_select(const uint32_t* hist, int nbins
   // thread t owns bins [nbins - (t+1)*per, nbins - t*per), scanned high to low
   const int hiB = nbins - t * per;
   unsigned int hv[4] = {0u, 0u, 0u, 0u};
-  for (int r = 0; r < HREP; r++)
-    for (int q = 1; q <= per; q++) hv[q - 1] += hist[(size_t)r * nbins + hiB - q];
+  for (int q = 1; q <= per; q++) hv[q - 1] = hist[hiB - q];
   unsigned long long s = 0;
   for (int q = 1; q <= per; q++) s += hv[q - 1];
   const int lane = t & 63, wv = t >> 6;
