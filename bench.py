@@ -36,9 +36,34 @@ def parse():
                     help="O strings given to the CPU oracle (0: skip the CPU baseline)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
-                    help="only run a plain device-to-device copy of BYTES bytes 5 times "
+                    help="only run a plain elementwise copy of BYTES bytes 5 times "
                          "(reference for the HBM traffic counters) and exit")
     return ap.parse_args()
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "device_common.hpp", "engine.hip"):
+        with open(os.path.join(ROOT, "paper_2410_09654_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "commutator_microbench_traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("source_sha") != kernel_source_sha() or kernel not in t["kernels"]:
+        return None
+    k = t["kernels"][kernel]
+    return {"fetch_bytes": round(k["fetch_bytes"]), "write_bytes": round(k["write_bytes"]),
+            "total_bytes": round(k["fetch_bytes"] + k["write_bytes"])}
 
 
 def calibrate_copy(nbytes: int):
@@ -46,7 +71,7 @@ def calibrate_copy(nbytes: int):
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(5):
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)  # elementwise kernel: reads and writes nbytes
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes, "launches": 5}), flush=True)
 
@@ -115,7 +140,7 @@ def main():
         achieved = alg_bytes[dom] / avg_s / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None, "alg_bytes_per_launch": alg_bytes[dom]}
+                    "traffic": measured_traffic(dom), "alg_bytes_per_launch": alg_bytes[dom]}
         mt = ["k_merge", "k_level1", "k_write"]
         mt_ms = sum(per_kernel[k]["total_ms"] for k in per_kernel
                     if k not in ("k_emit_count", "k_emit_scatter")) / args.steps
