@@ -29,12 +29,21 @@ R_BYTES = 32  # one record at N=64 in FP64: 16 B key + 16 B complex coefficient
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 calls; 40 Lanczos / 200 RK4 steps for "
+                         "the other workloads)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--count", type=int, default=1 << 20, help="strings in O")
     ap.add_argument("--cpu-sample", type=int, default=1 << 17,
                     help="O strings given to the CPU oracle (0: skip the CPU baseline)")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--workload", default="commutator",
+                    choices=["commutator", "lanczos-split", "rk4-tfim", "lanczos-small"],
+                    help="commutator: the benchmark line (default); the others run the "
+                         "Lanczos precision-split, RK4 and small-Lanczos configurations and "
+                         "print their own result line")
+    ap.add_argument("--max-strings", type=int, default=0,
+                    help="truncation M for lanczos-split / rk4-tfim (0: the configuration's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain elementwise copy of BYTES bytes 5 times "
                          "(reference for the HBM traffic counters) and exit")
@@ -76,10 +85,115 @@ def calibrate_copy(nbytes: int):
     print(json.dumps({"copy_bytes": nbytes, "launches": 5}), flush=True)
 
 
+def run_lanczos_split(args):
+    """N=128 chain sum(XX+YY+0.5ZZ) + 0.3 sum r_i Z_i, O0 = sum X_i/sqrt(N),
+    M = 2^23, 40 steps: FP64 and the FP32 + Kahan precision split side by side."""
+    import torch
+    import workloads as wl
+    import paper_2410_09654_amd as pk
+    steps = args.steps
+    M = args.max_strings or (1 << 23)
+    H_host, O0_host = wl.config_lanczos_split()
+    H = pk.PauliOp.from_raw(128, H_host.x, H_host.z, H_host.coef)
+    # the same H in reverse order: FP64 with another summation order, which
+    # measures how far the truncated recursion itself amplifies rounding noise
+    Hr = pk.PauliOp.from_raw(128, H_host.x[::-1], H_host.z[::-1], H_host.coef[::-1])
+    ws = pk.Workspace(1 << 30)
+    res = {}
+    for name, dt, Hn in (("f64", pk.PAULI_C128, H), ("f32_kahan", pk.PAULI_C64K, H),
+                         ("f64_reversed_H", pk.PAULI_C128, Hr)):
+        H = Hn
+        O0 = pk.PauliOp.from_host(O0_host, dtype=dt, ws=ws)
+        trunc = pk.Trunc(max_strings=M)
+        prev, cur, b_prev = None, O0, 0.0
+        bs, sizes, pairs, emitted = [], [], 0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pairs += H.size * cur.size
+            nxt, b, broke = pk.lanczos_step(H, prev, cur, b_prev, trunc, ws=ws)
+            emitted += pk.last_stats()["emitted"]
+            bs.append(b)
+            sizes.append(nxt.size)
+            if broke:
+                break
+            prev, cur, b_prev = cur, nxt, b
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[name] = {"b": bs, "strings": sizes, "seconds": wall, "ms_per_step": 1e3 * wall / len(bs),
+                     "pairs_per_s": pairs / wall, "emitted_per_s": emitted / wall}
+    b64, b32, b64r = res["f64"]["b"], res["f32_kahan"]["b"], res["f64_reversed_H"]["b"]
+    m = min(len(b64), len(b32), len(b64r))
+    rel = [abs(b32[k] - b64[k]) / abs(b64[k]) for k in range(m)]
+    rel_r = [abs(b64r[k] - b64[k]) / abs(b64[k]) for k in range(m)]
+    full = [k for k in range(m) if res["f64"]["strings"][k] < M]  # steps before the cut binds
+    print(json.dumps({"workload": "lanczos precision split: N=128 XXZ(0.5) + 0.3 r_i Z_i, "
+                                  "O0 = sum X_i/sqrt(N)", "steps": steps, "max_strings": M,
+                      "b_rel_err_vs_f64": rel, "max_b_rel_err": max(rel) if rel else None,
+                      "max_b_rel_err_untruncated_steps": max([rel[k] for k in full], default=None),
+                      "f64_order_sensitivity": rel_r,
+                      "max_f64_order_sensitivity": max(rel_r) if rel_r else None,
+                      **res}), flush=True)
+
+
+def run_rk4_tfim(args):
+    """8x8 open TFIM (J=1, hx=2), O0 = Z at site (4,4), dt = 0.02, 200 steps,
+    M = 2^22, length <= 16, keep = {O0}; S(t) = <O0, O(t)>."""
+    import torch
+    import workloads as wl
+    import paper_2410_09654_amd as pk
+    steps = args.steps
+    M = args.max_strings or (1 << 22)
+    H_host, O0_host = wl.config_rk4_tfim()
+    H = pk.PauliOp.from_raw(64, H_host.x, H_host.z, H_host.coef)
+    ws = pk.Workspace(1 << 30)
+    O0 = pk.PauliOp.from_host(O0_host, ws=ws)
+    trunc = pk.Trunc(max_len=16, max_strings=M, keep=O0)
+    n0 = pk.norm2(O0, ws=ws)
+    S, sizes, pairs = [1.0], [O0.size], 0
+    cur = O0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pairs += 4 * H.size * cur.size  # lower bound: the stages grow beyond |O|
+        cur = pk.rk4_step(H, cur, 0.02, trunc, ws=ws)
+        S.append(pk.inner(cur, O0, ws=ws).conjugate().real / n0)
+        sizes.append(cur.size)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(json.dumps({"workload": "rk4 8x8 TFIM J=1 hx=2, O0 = Z(4,4), dt = 0.02",
+                      "steps": steps, "max_strings": M, "max_len": 16,
+                      "seconds": wall, "ms_per_step": 1e3 * wall / steps, "S": S,
+                      "strings": sizes}), flush=True)
+
+
+def run_lanczos_small(args):
+    """N=12 chain, O0 = Z_1, 12 untruncated FP64 Lanczos steps."""
+    import workloads as wl
+    import paper_2410_09654_amd as pk
+    H_host, O0_host, steps = wl.config_lanczos_small()
+    H = pk.PauliOp.from_raw(12, H_host.x, H_host.z, H_host.coef)
+    bs, basis = pk.lanczos(H, pk.PauliOp.from_host(O0_host), steps, keep_basis=True)
+    counts = [B.size for B in basis[1:]]
+    small = [int(np.sum(np.abs(B.to_host().coef) > 1e-12)) for B in basis[1:]]
+    print(json.dumps({"workload": "lanczos N=12 chain, O0 = Z_1", "b": bs,
+                      "strings": counts, "strings_above_1e-12": small}), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.steps is None:
+        args.steps = {"commutator": 20, "lanczos-split": 40, "rk4-tfim": 200}.get(args.workload, 0)
+    if args.workload != "commutator":
+        import torch
+        import numpy as np  # noqa: F401
+        globals()["np"] = np
+        torch.cuda.set_device(0)
+        {"lanczos-split": run_lanczos_split, "rk4-tfim": run_rk4_tfim,
+         "lanczos-small": run_lanczos_small}[args.workload](args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the engine has no multi-GPU path "

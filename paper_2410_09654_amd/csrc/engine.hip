@@ -276,6 +276,11 @@ int Engine::run(Call& c) {
   if (n_keep > 65536) return PAULI_EINVAL;
   if (keep && words_of(keep->n_qubits) != W) return PAULI_EINVAL;
 
+  // every string's contributions must fit one merge bucket
+  if (comm && c.H.n + c.n_terms + 8 > MERGE_CAP) {
+    g_last_error = "H has more strings than one merge bucket holds";
+    return PAULI_EINVAL;
+  }
   int comm_rows = comm ? (int)std::min<int64_t>((c.O.n + EMIT_THREADS - 1) / EMIT_THREADS, 512) : 0;
   int term_rows = nterm_rec > 0 ? (int)std::min<int64_t>((nterm_rec + EMIT_THREADS - 1) / EMIT_THREADS, 256) : 0;
   const int rows = comm_rows + term_rows;
@@ -367,17 +372,22 @@ int Engine::run(Call& c) {
     return PAULI_EINTERNAL;
   }
   const unsigned long long pe_all = hctl->pe_total;
-  // passes over disjoint hash ranges keep every bucket within MERGE_CAP
+  // passes over disjoint hash ranges keep every bucket within MERGE_CAP; the
+  // largest bin does not always halve with each extra pass bit (all records
+  // of one string share a bin), so a pass that still overflows restarts the
+  // loop with one more pass bit
   int pass_bits = 0;
   {
     unsigned long long mx = hctl->maxg[0];
-    while (mx > (unsigned long long)(MERGE_CAP * 7 / 8) && pass_bits < 10) {
+    while (mx > (unsigned long long)(MERGE_CAP * 3 / 4) && pass_bits < 10) {
       pass_bits++;
       mx = (mx + 1) / 2;
     }
   }
+  constexpr int MAX_PASS_BITS = 12;
+  const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
   const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
-  const uint32_t max_buckets = (uint32_t)NBINS << pass_bits;
+  const uint32_t max_buckets = (uint32_t)NBINS << table_bits;
   // ----- records, U, bucket tables, candidate lists -------------------------
   // source ids fold into the key bits implied by the bin unless an index
   // needs more than 11 bits (H above 2047 strings, canonicalisation lists)
@@ -405,7 +415,6 @@ int Engine::run(Call& c) {
       ccnt[k] = (uint32_t*)ar->take((size_t)max_buckets * 4);
     }
   if (ar->short_) return PAULI_EWORKSPACE;
-  TRY(zero_u32(hist0, (size_t)HREP * SEL0_BINS));
 
   MergeArgs ma;
   memset(&ma, 0, sizeof(ma));
@@ -439,30 +448,46 @@ int Engine::run(Call& c) {
   ea.recs = recs;
   ea.rsrc_wide = rsrc_wide;
   ea.wide = wide ? 1 : 0;
-  uint32_t nbk = 0;                // buckets written so far
-  unsigned long long u_off = 0;   // U slots reserved by earlier passes
-  const int npass = 1 << pass_bits;
-  for (int p = 0; p < npass; p++) {
-    if (pass_bits) TRY(count_pass(pass_bits, (uint32_t)p));
-    const unsigned long long pe = hctl->pe_total;
-    int g_log = 4;
-    while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)MERGE_CAP) g_log--;
-    if (hctl->maxg[0] > (unsigned int)MERGE_CAP) {
-      g_last_error = "hash bucket above merge capacity";
-      return PAULI_EINTERNAL;
+  uint32_t nbk = 0;  // buckets written so far
+  int npass = 1 << pass_bits;
+  for (bool done = false; !done;) {
+    done = true;
+    nbk = 0;
+    unsigned long long u_off = 0;  // U slots reserved by earlier passes
+    npass = 1 << pass_bits;
+    TRY(zero_u32(hist0, (size_t)HREP * SEL0_BINS));
+    for (int p = 0; p < npass; p++) {
+      if (pass_bits) TRY(count_pass(pass_bits, (uint32_t)p));
+      const unsigned long long pe = hctl->pe_total;
+      if (hctl->maxg[0] > (unsigned int)MERGE_CAP) {
+        if (pass_bits >= table_bits) {
+          char msg[256];
+          snprintf(msg, sizeof(msg),
+                   "hash bucket above merge capacity: pass %d of %d, largest bin %u, "
+                   "records in pass %llu, records in all passes %llu",
+                   p, npass, hctl->maxg[0], (unsigned long long)pe, pe_all);
+          g_last_error = msg;
+          return PAULI_EINTERNAL;
+        }
+        pass_bits++;
+        done = false;
+        break;
+      }
+      int g_log = 4;
+      while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)MERGE_CAP) g_log--;
+      if (pe == 0) continue;
+      LAUNCH("k_emit_scatter", (k_emit<W, F32, true>), rows, EMIT_THREADS, ea);
+      ma.g_log = g_log;
+      ma.digit_shift = pass_bits + NBINS_LOG - g_log;
+      ma.pass_bits = pass_bits;
+      ma.pass_id = (uint32_t)p;
+      ma.u_off = u_off;
+      ma.bucket_off = nbk;
+      const uint32_t nb_pass = (uint32_t)(NBINS >> g_log);
+      LAUNCH("k_merge", (k_merge<W, F32>), nb_pass, MERGE_THREADS, ma);
+      nbk += nb_pass;
+      u_off += pe;
     }
-    if (pe == 0) continue;
-    LAUNCH("k_emit_scatter", (k_emit<W, F32, true>), rows, EMIT_THREADS, ea);
-    ma.g_log = g_log;
-    ma.digit_shift = pass_bits + NBINS_LOG - g_log;
-    ma.pass_bits = pass_bits;
-    ma.pass_id = (uint32_t)p;
-    ma.u_off = u_off;
-    ma.bucket_off = nbk;
-    const uint32_t nb_pass = (uint32_t)(NBINS >> g_log);
-    LAUNCH("k_merge", (k_merge<W, F32>), nb_pass, MERGE_THREADS, ma);
-    nbk += nb_pass;
-    u_off += pe;
   }
   if (nbk)
     LAUNCH("k_bucket_totals", k_bucket_totals, 1, 1024, b_slots, b_surv, b_keep, b_unique, nbk,

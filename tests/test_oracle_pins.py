@@ -389,3 +389,66 @@ def test_truncate_properties(seed):
         for kd in dropped:
             a, b = m2(kept[kk]), m2(surv[kd])
             assert a > b or (a == b and key_order(kk, W) < key_order(kd, W))
+
+
+# ---------------------------------------------------------------------------
+# Precision split: FP32 products with Kahan-compensated sums
+# ---------------------------------------------------------------------------
+
+def test_f32k_equals_f64_when_everything_is_exact():
+    """Dyadic coefficients with few bits: FP32 products and sums are exact, so
+    the FP32 mode must reproduce the FP64 commutator bit for bit."""
+    n = 6
+    rng = np.random.default_rng(3)
+    H = wl.random_operator(n, 8, seed=71, density=0.5)
+    O = wl.random_operator(n, 12, seed=72, density=0.6)
+    H.coef = (rng.integers(-8, 9, H.n) + 1j * rng.integers(-8, 9, H.n)) / 4
+    O.coef = (rng.integers(-8, 9, O.n) + 1j * rng.integers(-8, 9, O.n)) / 8
+    a = oracle.commutator(H, O, oracle.F64)
+    b = oracle.commutator(H, O, oracle.F32K)
+    assert a.as_dict() == b.as_dict()
+
+
+def test_kahan_sum_matches_exact_sum():
+    """One output string collecting many contributions of very different size:
+    the compensated FP32 sum stays within a few FP32 ulps of the exact sum of
+    the (FP32-rounded) contributions, where a plain FP32 sum loses everything."""
+    n = 20
+    k = 200
+    rng = np.random.default_rng(5)
+    # a_i = X_1 S_i, b_i = Y_1 S_i with distinct S_i on sites 2..n: every pair
+    # (a_i, b_i) anticommutes and yields Z_1 (X Y = iZ on site 1)
+    S = set()
+    while len(S) < k:
+        S.add(tuple(int(v) for v in rng.integers(0, 4, n - 1)))
+    S = sorted(S)
+    def op(first, coefs):
+        terms = []
+        for s, c in zip(S, coefs):
+            f = [(first, 1)] + [("IXZY"[p], j + 2) for j, p in enumerate(s) if p]
+            terms.append((c, f))
+        return wl.from_terms(n, terms)
+    H = op("X", np.ones(k))
+    big = np.where(np.arange(k) % 2 == 0, 1.0e7, -1.0e7)
+    small = rng.uniform(0.5, 1.5, k)
+    O = op("Y", np.where(np.arange(k) < k - 50, big, small))
+    C = oracle.commutator(H, O, oracle.F32K).as_dict()
+    z1 = (0,) + (1,)  # x word 0, z word 0 of Z_1
+    got = C[z1]
+    # contribution of pair i: [X S, c Y S] = 2i c Z_1 (only the i = j pairs give Z_1)
+    contrib = [2.0 * float(np.float32(c)) for c in O.coef.real]
+    exact = math.fsum(contrib)
+    assert abs(got.real) == 0.0
+    assert abs(got.imag - exact) <= 4 * np.spacing(np.float32(abs(exact))) + 1e-30
+    naive = np.float32(0.0)
+    for c in contrib:
+        naive = np.float32(naive + np.float32(c))
+    assert abs(float(naive) - exact) > abs(got.imag - exact)
+
+
+def test_f32k_lanczos_within_split_tolerance():
+    H, O0, steps = wl.config_lanczos_small()
+    b64 = oracle.lanczos(H, O0, steps, prec=oracle.F64)
+    b32 = oracle.lanczos(H, O0, steps, prec=oracle.F32K)
+    rel = np.abs(np.array(b32) - np.array(b64)) / np.array(b64)
+    assert rel.max() < 1e-6
