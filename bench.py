@@ -38,10 +38,11 @@ def parse():
                     help="O strings given to the CPU oracle (0: skip the CPU baseline)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--workload", default="commutator",
-                    choices=["commutator", "lanczos-split", "rk4-tfim", "lanczos-small"],
+                    choices=["commutator", "lanczos-split", "rk4-tfim", "lanczos-small",
+                             "surrogate"],
                     help="commutator: the benchmark line (default); the others run the "
-                         "Lanczos precision-split, RK4 and small-Lanczos configurations and "
-                         "print their own result line")
+                         "Lanczos precision-split, RK4, small-Lanczos and b_n-surrogate "
+                         "configurations and print their own result line")
     ap.add_argument("--max-strings", type=int, default=0,
                     help="truncation M for lanczos-split / rk4-tfim (0: the configuration's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -180,11 +181,82 @@ def run_lanczos_small(args):
                       "strings": counts, "strings_above_1e-12": small}), flush=True)
 
 
+MLP_FWD_FLOP = 2 * (16 * 256 + 256 * 256 + 256 * 16)  # per window
+MLP_TRAIN_FLOP = 3 * MLP_FWD_FLOP  # forward, input gradient, weight gradient
+
+
+def run_surrogate(args):
+    """b_n continuation network: 512 random couplings (hx ~ U[0.5,1.5],
+    hz ~ U[0,1], seed 5) of the N=64 Ising chain with O0 = sum Z_i/sqrt(N),
+    truncated Lanczos to 46 steps at M = 2^20 for training; 64 held-out
+    couplings (seed 55) computed to 30 steps and continued to 46 by one
+    network pass, judged by their plain 46-step recursion."""
+    import math
+    import torch
+    import workloads as wl
+    import paper_2410_09654_amd as pk
+    from paper_2410_09654_amd import surrogate as sg
+    M = args.max_strings or (1 << 20)
+    ws = pk.Workspace(1 << 30)
+
+    def tables(couplings, steps):
+        out = []
+        for hx, hz in couplings:
+            H = wl.ising_chain(64, hx=float(hx), hz=float(hz))
+            O0 = wl.single_site_sum(64, "Z", 1 / math.sqrt(64))
+            Hd = pk.PauliOp.from_raw(64, H.x, H.z, H.coef)
+            out.append(pk.lanczos(Hd, pk.PauliOp.from_host(O0, ws=ws), steps,
+                                  pk.Trunc(max_strings=M), ws=ws))
+        torch.cuda.synchronize()
+        return np.array(out)
+
+    t0 = time.perf_counter()
+    train = tables(zip(*wl.surrogate_couplings(512, seed=5)), 46)
+    t_gen = time.perf_counter() - t0
+    cpl = list(zip(*wl.surrogate_couplings(64, seed=55)))
+    t0 = time.perf_counter()
+    short = tables(cpl, 30)
+    t1 = time.perf_counter()
+    held = tables(cpl, 46)
+    t_lanczos16 = (time.perf_counter() - t1) - (t1 - t0)
+    x, t, mask = sg.make_windows(train, 46)
+    net = sg.BnSurrogate(seed=0, ws=ws)
+    epochs, batch = 100, 256
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = net.train(x.cuda(), t.cuda(), mask.cuda(), epochs=epochs, batch=batch, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pred = sg.predict_continuation(net, short, 30, 46)
+    torch.cuda.synchronize()
+    t_mlp = time.perf_counter() - t0
+    truth = held[:, 30:46]
+    err = lambda p: float(np.mean(np.abs(p - truth) / truth))
+    flops = MLP_TRAIN_FLOP * x.shape[0] * epochs
+    print(json.dumps({
+        "workload": "b_n surrogate: N=64 Ising chain, 512 train / 64 held-out couplings, "
+                    "46-step truncated Lanczos, 16 -> 256 -> 256 -> 16 GELU",
+        "max_strings": M, "train_windows": int(x.shape[0]), "epochs": epochs, "batch": batch,
+        "held_out_mean_rel_err": {"mlp": err(pred),
+                                  "constant_b30": err(sg.baseline_constant(short, 30, 46)),
+                                  "linear_fit_b15_b30": err(sg.baseline_linear(short, 30, 46))},
+        "loss_curve": hist[::10] + [hist[-1]],
+        "seconds": {"training_tables": t_gen, "training": t_train, "mlp_continuation": t_mlp,
+                    "lanczos_steps_31_46": t_lanczos16},
+        "training_tflops": flops / t_train / 1e12,
+        "training_frac_of_bf16_peak": flops / t_train / 2.5e15}), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the engine has no multi-GPU path; "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
     if args.steps is None:
         args.steps = {"commutator": 20, "lanczos-split": 40, "rk4-tfim": 200}.get(args.workload, 0)
     if args.workload != "commutator":
@@ -193,12 +265,8 @@ def main():
         globals()["np"] = np
         torch.cuda.set_device(0)
         {"lanczos-split": run_lanczos_split, "rk4-tfim": run_rk4_tfim,
-         "lanczos-small": run_lanczos_small}[args.workload](args)
+         "lanczos-small": run_lanczos_small, "surrogate": run_surrogate}[args.workload](args)
         return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the engine has no multi-GPU path "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
     import torch
     import workloads as wl
     import paper_2410_09654_amd as pk

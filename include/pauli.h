@@ -154,6 +154,47 @@ int pauli_norm2(const pauli_op *A, double *out, pauli_ws *ws, void *stream);
 int pauli_inner(const pauli_op *A, const pauli_op *B, double out[2], pauli_ws *ws,
                 void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* b_n continuation network: a window of 16 Lanczos coefficients in, the next */
+/* 16 out; 16 -> 256 -> 256 -> 16, GELU(x) = x (1 + erf(x/sqrt 2))/2 on the   */
+/* hidden layers.  Every matrix product runs on the matrix cores with BF16    */
+/* operands (round to nearest even) and FP32 accumulation; biases, GELU, the  */
+/* loss and Adam run in FP32.  All pointers are device pointers owned by the   */
+/* caller.  The flat parameter vector holds, in order: W1[256][16], b1[256],   */
+/* W2[256][256], b2[256], W3[16][256], b3[16] (pauli_mlp_num_params() floats). */
+/* ------------------------------------------------------------------------ */
+typedef struct pauli_mlp {
+  int32_t n_in, n_hidden, n_out; /* must be 16, 256, 16 */
+  float *params;                 /* fp32 master weights */
+  uint16_t *params_bf16;         /* bf16 copy used by the matrix products */
+  float *grads;                  /* written by pauli_mlp_loss_grad */
+  float *adam_m, *adam_v;        /* Adam moments (start at zero) */
+} pauli_mlp;
+
+int64_t pauli_mlp_num_params(void);
+/* params_bf16 = bf16(params). */
+int pauli_mlp_sync(const pauli_mlp *net, void *stream);
+/* y[batch][16] = net(x[batch][16]); batch a positive multiple of 32. */
+int pauli_mlp_forward(const pauli_mlp *net, const float *x, int64_t batch, float *y,
+                      pauli_ws *ws, void *stream);
+/* Masked mean-squared error L = sum mask (y - t)^2 / sum mask over the batch
+ * (*loss, host) and its gradient with respect to every parameter (net->grads).
+ * acts (nullable, device, batch * 2112 floats) receives the intermediate
+ * tensors as FP32, in order: X_bf16[16], Z1[256], Y1_bf16[256], Z2[256],
+ * Y2_bf16[256], Y[16], dY_bf16[16], dY2[256], dZ2_bf16[256], dY1[256],
+ * dZ1_bf16[256] per row, each block batch-major. */
+int pauli_mlp_loss_grad(const pauli_mlp *net, const float *x, const float *target,
+                        const float *mask, int64_t batch, double *loss, float *acts,
+                        pauli_ws *ws, void *stream);
+/* One Adam step (step index t >= 1) from net->grads; refreshes params_bf16. */
+int pauli_mlp_adam(const pauli_mlp *net, double lr, double beta1, double beta2, double eps,
+                   int64_t t, void *stream);
+/* C[M][N] (fp32) = A(M x K) B(K x N) with BF16 operands on the matrix cores;
+ * A(m,k) = transA ? A[k*lda + m] : A[m*lda + k], B(k,n) = transB ? B[n*ldb + k]
+ * : B[k*ldb + n]; M and N multiples of 16. */
+int pauli_gemm_bf16(const uint16_t *A, int lda, int transA, const uint16_t *B, int ldb,
+                    int transB, float *C, int ldc, int M, int N, int K, void *stream);
+
 /* Counters of the last engine pass of this thread's last call (diagnostics and
  * the algorithmic byte counts of the benchmark). */
 typedef struct pauli_stats {

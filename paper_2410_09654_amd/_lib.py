@@ -14,7 +14,8 @@ PAULI_C128, PAULI_C64K = 0, 1
 EXPORTS = ["pauli_commutator", "pauli_add", "pauli_truncate", "pauli_canonicalize",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
            "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_read",
-           "pauli_last_stats"]
+           "pauli_last_stats", "pauli_mlp_num_params", "pauli_mlp_sync", "pauli_mlp_forward",
+           "pauli_mlp_loss_grad", "pauli_mlp_adam", "pauli_gemm_bf16"]
 
 
 class PauliOpC(ctypes.Structure):
@@ -80,6 +81,9 @@ def load():
     for name in EXPORTS:
         if name in ("pauli_strerror", "pauli_last_error", "pauli_profile_read",
                     "pauli_last_stats"):
+            continue
+        if name == "pauli_mlp_num_params":
+            L[name].restype = ctypes.c_int64
             continue
         L[name].restype = None if name == "pauli_profile_enable" else ctypes.c_int
     _lib = L

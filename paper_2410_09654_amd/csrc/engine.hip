@@ -19,6 +19,7 @@
 
 #include "../../include/pauli.h"
 #include "kernels.hpp"
+#include "mlp.hpp"
 
 using namespace pauli;
 
@@ -1022,6 +1023,208 @@ int pauli_inner(const pauli_op* A, const pauli_op* B, double out[2], pauli_ws* w
   if (bad) return PAULI_EINVAL;
   out[0] = h[0];
   out[1] = h[2];
+  return PAULI_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// b_n continuation network
+// ---------------------------------------------------------------------------
+int64_t pauli_mlp_num_params(void) { return mlp::NPARAM; }
+
+static int mlp_check(const pauli_mlp* net) {
+  if (!net || net->n_in != mlp::NIN || net->n_hidden != mlp::NHID || net->n_out != mlp::NOUT)
+    return PAULI_EINVAL;
+  if (!net->params || !net->params_bf16) return PAULI_EINVAL;
+  return PAULI_OK;
+}
+
+static int gemm_launch(hipStream_t stream, const uint16_t* A, int lda, int transA,
+                       const uint16_t* B, int ldb, int transB, float* C, uint16_t* Cb, int ldc,
+                       const float* bias, int M, int N, int K, int epilogue) {
+  if (M <= 0 || N <= 0 || K <= 0 || M % 16 || N % 16) return PAULI_EINVAL;
+  mlp::GemmArgs g;
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.Cb = Cb;
+  g.bias = bias;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.transA = transA;
+  g.transB = transB;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.epilogue = epilogue;
+  LAUNCH("k_gemm_bf16", mlp::k_gemm_bf16, dim3((N + 31) / 32, (M + 31) / 32), 256, g);
+  return PAULI_OK;
+}
+
+int pauli_gemm_bf16(const uint16_t* A, int lda, int transA, const uint16_t* B, int ldb, int transB,
+                    float* C, int ldc, int M, int N, int K, void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!A || !B || !C) return PAULI_EINVAL;
+  TRY(gemm_launch(stream, A, lda, transA, B, ldb, transB, C, nullptr, ldc, nullptr, M, N, K,
+                  mlp::EP_STORE));
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  return PAULI_OK;
+}
+
+int pauli_mlp_sync(const pauli_mlp* net, void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  TRY(mlp_check(net));
+  LAUNCH("k_to_bf16", mlp::k_to_bf16, (mlp::NPARAM + 255) / 256, 256, net->params,
+         net->params_bf16, mlp::NPARAM);
+  HIP_TRY(hipStreamSynchronize(stream));
+  return PAULI_OK;
+}
+
+namespace {
+struct MlpBufs {
+  uint16_t *xb, *y1b, *y2b, *dyb, *dz2b, *dz1b;
+  float *z1, *z2, *yh, *dy, *dy2, *dz2, *dy1, *dz1;
+  double *row_err, *row_cnt, *loss;
+};
+int mlp_bufs(Arena& ar, int64_t B, MlpBufs& m) {
+  const size_t b = (size_t)B;
+  m.xb = (uint16_t*)ar.take(b * 16 * 2);
+  m.y1b = (uint16_t*)ar.take(b * 256 * 2);
+  m.y2b = (uint16_t*)ar.take(b * 256 * 2);
+  m.dyb = (uint16_t*)ar.take(b * 16 * 2);
+  m.dz2b = (uint16_t*)ar.take(b * 256 * 2);
+  m.dz1b = (uint16_t*)ar.take(b * 256 * 2);
+  m.z1 = (float*)ar.take(b * 256 * 4);
+  m.z2 = (float*)ar.take(b * 256 * 4);
+  m.yh = (float*)ar.take(b * 16 * 4);
+  m.dy = (float*)ar.take(b * 16 * 4);
+  m.dy2 = (float*)ar.take(b * 256 * 4);
+  m.dz2 = (float*)ar.take(b * 256 * 4);
+  m.dy1 = (float*)ar.take(b * 256 * 4);
+  m.dz1 = (float*)ar.take(b * 256 * 4);
+  m.row_err = (double*)ar.take(b * 8);
+  m.row_cnt = (double*)ar.take(b * 8);
+  m.loss = (double*)ar.take(16);
+  return ar.short_ ? PAULI_EWORKSPACE : PAULI_OK;
+}
+
+// forward pass into the buffers
+int mlp_forward_bufs(hipStream_t stream, const pauli_mlp* net, const float* x, int64_t B,
+                     MlpBufs& m) {
+  using namespace mlp;
+  const uint16_t* P = net->params_bf16;
+  const float* Pf = net->params;
+  LAUNCH("k_to_bf16", k_to_bf16, (B * NIN + 255) / 256, 256, x, m.xb, B * NIN);
+  // Z1 = X W1^T + b1, Y1 = GELU(Z1)
+  TRY(gemm_launch(stream, m.xb, NIN, 0, P + OFF_W1, NIN, 1, m.z1, m.y1b, NHID, Pf + OFF_B1,
+                  (int)B, NHID, NIN, EP_BIAS_GELU));
+  TRY(gemm_launch(stream, m.y1b, NHID, 0, P + OFF_W2, NHID, 1, m.z2, m.y2b, NHID, Pf + OFF_B2,
+                  (int)B, NHID, NHID, EP_BIAS_GELU));
+  TRY(gemm_launch(stream, m.y2b, NHID, 0, P + OFF_W3, NHID, 1, m.yh, nullptr, NOUT, Pf + OFF_B3,
+                  (int)B, NOUT, NHID, EP_BIAS));
+  return PAULI_OK;
+}
+}  // namespace
+
+int pauli_mlp_forward(const pauli_mlp* net, const float* x, int64_t B, float* y, pauli_ws* ws,
+                      void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!ws || !x || !y || B <= 0 || B % 32) return PAULI_EINVAL;
+  TRY(mlp_check(net));
+  Arena ar = make_arena(ws);
+  MlpBufs m;
+  if (mlp_bufs(ar, B, m) != PAULI_OK) return ws_short(ar, ws);
+  TRY(mlp_forward_bufs(stream, net, x, B, m));
+  HIP_TRY(hipMemcpyAsync(y, m.yh, (size_t)B * mlp::NOUT * 4, hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  return PAULI_OK;
+}
+
+int pauli_mlp_loss_grad(const pauli_mlp* net, const float* x, const float* t, const float* mask,
+                        int64_t B, double* loss, float* acts, pauli_ws* ws, void* stream_) {
+  using namespace mlp;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!ws || !x || !t || !mask || B <= 0 || B % 32) return PAULI_EINVAL;
+  TRY(mlp_check(net));
+  if (!net->grads) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  MlpBufs m;
+  if (mlp_bufs(ar, B, m) != PAULI_OK) return ws_short(ar, ws);
+  TRY(mlp_forward_bufs(stream, net, x, B, m));
+  const uint16_t* P = net->params_bf16;
+  float* G = net->grads;
+  const int64_t nb = (B + 255) / 256;
+  LAUNCH("k_mse_rows", k_mse_rows, nb, 256, m.yh, t, mask, B, m.row_err, m.row_cnt);
+  LAUNCH("k_sum_rows", k_sum_rows, 1, 256, m.row_err, m.row_cnt, B, m.loss);
+  LAUNCH("k_mse_grad", k_mse_grad, (B * NOUT + 255) / 256, 256, m.yh, t, mask, B * NOUT, m.loss,
+         m.dy, m.dyb);
+  // layer 3: dW3[16][256] = dY^T Y2, db3 = column sums of dY, dY2 = dY W3
+  TRY(gemm_launch(stream, m.dyb, NOUT, 1, m.y2b, NHID, 0, G + OFF_W3, nullptr, NHID, nullptr,
+                  NOUT, NHID, (int)B, EP_STORE));
+  LAUNCH("k_col_sum", k_col_sum, 1, 256, m.dy, B, NOUT, G + OFF_B3);
+  TRY(gemm_launch(stream, m.dyb, NOUT, 0, P + OFF_W3, NHID, 0, m.dy2, nullptr, NHID, nullptr,
+                  (int)B, NHID, NOUT, EP_STORE));
+  LAUNCH("k_gelu_back", k_gelu_back, (B * NHID + 255) / 256, 256, m.dy2, m.z2, B * NHID, m.dz2,
+         m.dz2b);
+  // layer 2
+  TRY(gemm_launch(stream, m.dz2b, NHID, 1, m.y1b, NHID, 0, G + OFF_W2, nullptr, NHID, nullptr,
+                  NHID, NHID, (int)B, EP_STORE));
+  LAUNCH("k_col_sum", k_col_sum, 1, 256, m.dz2, B, NHID, G + OFF_B2);
+  TRY(gemm_launch(stream, m.dz2b, NHID, 0, P + OFF_W2, NHID, 0, m.dy1, nullptr, NHID, nullptr,
+                  (int)B, NHID, NHID, EP_STORE));
+  LAUNCH("k_gelu_back", k_gelu_back, (B * NHID + 255) / 256, 256, m.dy1, m.z1, B * NHID, m.dz1,
+         m.dz1b);
+  // layer 1
+  TRY(gemm_launch(stream, m.dz1b, NHID, 1, m.xb, NIN, 0, G + OFF_W1, nullptr, NIN, nullptr, NHID,
+                  NIN, (int)B, EP_STORE));
+  LAUNCH("k_col_sum", k_col_sum, 1, 256, m.dz1, B, NHID, G + OFF_B1);
+  if (acts) {
+    float* o = acts;
+    auto bf = [&](const uint16_t* src, int64_t n) -> int {
+      LAUNCH("k_bf_to_f", k_bf_to_f, (n + 255) / 256, 256, src, o, n);
+      o += n;
+      return PAULI_OK;
+    };
+    auto fc = [&](const float* src, int64_t n) -> int {
+      HIP_TRY(hipMemcpyAsync(o, src, (size_t)n * 4, hipMemcpyDeviceToDevice, stream));
+      o += n;
+      return PAULI_OK;
+    };
+    TRY(bf(m.xb, B * NIN));
+    TRY(fc(m.z1, B * NHID));
+    TRY(bf(m.y1b, B * NHID));
+    TRY(fc(m.z2, B * NHID));
+    TRY(bf(m.y2b, B * NHID));
+    TRY(fc(m.yh, B * NOUT));
+    TRY(bf(m.dyb, B * NOUT));
+    TRY(fc(m.dy2, B * NHID));
+    TRY(bf(m.dz2b, B * NHID));
+    TRY(fc(m.dy1, B * NHID));
+    TRY(bf(m.dz1b, B * NHID));
+  }
+  double h[2];
+  HIP_TRY(hipMemcpyAsync(h, m.loss, 16, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  if (loss) *loss = h[0];
+  return PAULI_OK;
+}
+
+int pauli_mlp_adam(const pauli_mlp* net, double lr, double b1, double b2, double eps, int64_t t,
+                   void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  TRY(mlp_check(net));
+  if (!net->grads || !net->adam_m || !net->adam_v || t < 1) return PAULI_EINVAL;
+  const float c1 = (float)(1.0 - std::pow(b1, (double)t));
+  const float c2 = (float)(1.0 - std::pow(b2, (double)t));
+  LAUNCH("k_adam", mlp::k_adam, (mlp::NPARAM + 255) / 256, 256, net->params, net->grads,
+         net->adam_m, net->adam_v, net->params_bf16, mlp::NPARAM, (float)lr, (float)b1,
+         (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps, c1, c2);
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
   return PAULI_OK;
 }
 

@@ -1,0 +1,191 @@
+"""GPU checks of the b_n continuation network: the BF16 matrix-core product,
+the forward/backward pass layer by layer against the float64 reference on the
+same BF16 operands, Adam, and the held-out gain of a trained network over
+extrapolating without it."""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import mlp as ref
+from helpers import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sg():
+    from paper_2410_09654_amd import surrogate
+    surrogate.lib()
+    return surrogate
+
+
+def bf16_bits(x):
+    """float array -> (int16 bit patterns, exact float64 values) of its bf16 rounding."""
+    import torch
+    v = ref.bf16(x)
+    bits = (v.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+    return torch.from_numpy(bits.copy()).cuda(), v
+
+
+@pytest.mark.parametrize("M,N,K", [(32, 32, 32), (64, 48, 16), (48, 256, 512), (16, 256, 96),
+                                   (256, 16, 544)])
+def test_gemm_bf16_all_layouts(sg, M, N, K):
+    say(f"gemm {M}x{N}x{K}")
+    rng = np.random.default_rng(M * 7 + N + K)
+    for ta in (0, 1):
+        for tb in (0, 1):
+            A = rng.standard_normal((K, M) if ta else (M, K))
+            B = rng.standard_normal((N, K) if tb else (K, N))
+            At, Av = bf16_bits(A)
+            Bt, Bv = bf16_bits(B)
+            C = sg.gemm_bf16(At, Bt, bool(ta), bool(tb)).cpu().numpy().astype(np.float64)
+            opA = Av.T if ta else Av
+            opB = Bv.T if tb else Bv
+            want = opA @ opB
+            scale = np.abs(opA) @ np.abs(opB)
+            assert np.all(np.abs(C - want) <= 2e-6 * scale + 1e-30), (ta, tb)
+
+
+def test_forward_backward_layerwise(sg):
+    say("mlp layers")
+    import torch
+    net = sg.BnSurrogate(seed=3)
+    B = 64
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((B, 16)).astype(np.float32)
+    t = rng.standard_normal((B, 16)).astype(np.float32)
+    mask = (rng.random((B, 16)) < 0.6).astype(np.float32)
+    mask[0, :] = 1.0
+    loss, acts, Bp = net.loss_grad(torch.from_numpy(x), torch.from_numpy(t),
+                                   torch.from_numpy(mask), want_acts=True)
+    a = acts.cpu().numpy().astype(np.float64)
+    sizes = [16, 256, 256, 256, 256, 16, 16, 256, 256, 256, 256]
+    names = ["xb", "z1", "y1b", "z2", "y2b", "y", "dyb", "dy2", "dz2b", "dy1", "dz1b"]
+    T, o = {}, 0
+    for nm, s in zip(names, sizes):
+        T[nm] = a[o:o + Bp * s].reshape(Bp, s)[:B]
+        o += Bp * s
+    p = net.params.cpu().numpy().astype(np.float64)
+    w = ref.unpack(p)
+    wb = {k: ref.bf16(v) for k, v in w.items()}
+
+    def close(got, want, scale, tol=2e-6):
+        assert np.all(np.abs(got - want) <= tol * scale + 1e-30)
+
+    def bf_close(got, want_float):
+        # bf16 of the same quantity computed in float64: equal up to one bf16 ulp
+        want = ref.bf16(want_float)
+        assert np.all(np.abs(got - want) <= np.abs(want) * 2.0 ** -7 + 1e-30)
+        assert np.mean(got == want) > 0.99
+
+    assert np.array_equal(T["xb"], ref.bf16(x))
+    close(T["z1"], T["xb"] @ wb["W1"].T + w["b1"], np.abs(T["xb"]) @ np.abs(wb["W1"]).T + abs(w["b1"]))
+    bf_close(T["y1b"], ref.gelu(T["z1"]))
+    close(T["z2"], T["y1b"] @ wb["W2"].T + w["b2"], np.abs(T["y1b"]) @ np.abs(wb["W2"]).T + abs(w["b2"]))
+    bf_close(T["y2b"], ref.gelu(T["z2"]))
+    close(T["y"], T["y2b"] @ wb["W3"].T + w["b3"], np.abs(T["y2b"]) @ np.abs(wb["W3"]).T + abs(w["b3"]))
+    m = mask.astype(np.float64)
+    want_loss = float((m * (T["y"] - t) ** 2).sum() / m.sum())
+    assert abs(loss - want_loss) <= 1e-12 * want_loss
+    dy = 2 * m * (T["y"] - t) / m.sum()
+    bf_close(T["dyb"], dy)
+    g = ref.unpack(net.grads.cpu().numpy().astype(np.float64))
+    close(g["W3"], T["dyb"].T @ T["y2b"], np.abs(T["dyb"]).T @ np.abs(T["y2b"]))
+    assert np.allclose(g["b3"], dy.sum(0), rtol=1e-5, atol=1e-7)
+    close(T["dy2"], T["dyb"] @ wb["W3"], np.abs(T["dyb"]) @ np.abs(wb["W3"]))
+    dz2 = T["dy2"] * ref.gelu_grad(T["z2"])
+    bf_close(T["dz2b"], dz2)
+    close(g["W2"], T["dz2b"].T @ T["y1b"], np.abs(T["dz2b"]).T @ np.abs(T["y1b"]))
+    assert np.allclose(g["b2"], dz2.sum(0), rtol=1e-4, atol=1e-7)
+    close(T["dy1"], T["dz2b"] @ wb["W2"], np.abs(T["dz2b"]) @ np.abs(wb["W2"]))
+    dz1 = T["dy1"] * ref.gelu_grad(T["z1"])
+    bf_close(T["dz1b"], dz1)
+    close(g["W1"], T["dz1b"].T @ T["xb"], np.abs(T["dz1b"]).T @ np.abs(T["xb"]))
+    assert np.allclose(g["b1"], dz1.sum(0), rtol=1e-4, atol=1e-7)
+    # end to end: the BF16 gradient stays close to the exact float64 gradient
+    _, g64 = ref.loss_and_grad(p, x.astype(np.float64), t.astype(np.float64), m)
+    gg = ref.pack(g)
+    assert np.linalg.norm(gg - g64) <= 0.03 * np.linalg.norm(g64)
+
+
+def test_adam_matches_reference(sg):
+    say("adam")
+    import torch
+    net = sg.BnSurrogate(seed=5)
+    rng = np.random.default_rng(6)
+    g = rng.standard_normal(net.n).astype(np.float32)
+    p0 = net.params.cpu().numpy().astype(np.float64)
+    net.grads.copy_(torch.from_numpy(g).cuda())
+    net.adam(lr=1e-3)
+    net.adam(lr=1e-3)
+    m = np.zeros(net.n)
+    v = np.zeros(net.n)
+    p = p0
+    for t in (1, 2):
+        p, m, v = ref.adam_step(p, g.astype(np.float64), m, v, t, lr=1e-3)
+    assert np.allclose(net.params.cpu().numpy(), p, rtol=1e-5, atol=1e-8)
+    pb = net.params_bf16.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    assert np.array_equal(pb.view(np.float32).astype(np.float64), ref.bf16(net.params.cpu().numpy()))
+
+
+def lanczos_tables(pk, couplings, steps, M, n=64):
+    out = []
+    for hx, hz in couplings:
+        H = wl.ising_chain(n, hx=float(hx), hz=float(hz))
+        O0 = wl.single_site_sum(n, "Z", 1 / math.sqrt(n))
+        Hd = pk.PauliOp.from_raw(n, H.x, H.z, H.coef)
+        bs = pk.lanczos(Hd, pk.PauliOp.from_host(O0), steps, pk.Trunc(max_strings=M))
+        assert len(bs) == steps
+        out.append(bs)
+    return np.array(out)
+
+
+def test_trained_network_gains_over_extrapolation(sg):
+    """Train on 46-step b_n runs of 512 random couplings, then continue 64
+    held-out couplings from b_15..b_30 to b_46 in one network pass; the plain
+    truncated Lanczos recursion run to 46 steps judges the result against
+    holding b_30 constant and a least-squares line through b_15..b_30."""
+    import torch
+    import paper_2410_09654_amd as pk
+    M = 1 << 16
+    hx, hz = wl.surrogate_couplings(512, seed=5)
+    say("generating training b_n")
+    train = lanczos_tables(pk, zip(hx, hz), 46, M)
+    hxo, hzo = wl.surrogate_couplings(64, seed=55)
+    say("generating held-out b_n")
+    t0 = time.perf_counter()
+    short = lanczos_tables(pk, zip(hxo, hzo), 30, M)
+    t1 = time.perf_counter()
+    held = lanczos_tables(pk, zip(hxo, hzo), 46, M)
+    t_lanczos = (time.perf_counter() - t1) - (t1 - t0)  # steps 31..46 of every held-out run
+    assert np.array_equal(short, held[:, :30])
+    x, t, mask = sg.make_windows(train, 46)
+    net = sg.BnSurrogate(seed=0)
+    say(f"training on {x.shape[0]} windows")
+    hist = net.train(x.cuda(), t.cuda(), mask.cuda(), epochs=100, batch=256, lr=1e-3)
+    assert hist[-1] < 0.2 * hist[0]
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pred = sg.predict_continuation(net, short, 30, 46)
+    torch.cuda.synchronize()
+    t_mlp = time.perf_counter() - t2
+    truth = held[:, 30:46]
+    err = lambda p: float(np.mean(np.abs(p - truth) / truth))
+    e_mlp = err(pred)
+    e_const = err(sg.baseline_constant(short, 30, 46))
+    e_lin = err(sg.baseline_linear(short, 30, 46))
+    say(f"loss {hist[0]:.3e} -> {hist[-1]:.3e}; held-out mean rel err: mlp {e_mlp:.4f}  "
+        f"constant {e_const:.4f}  linear {e_lin:.4f}; "
+        f"mlp {t_mlp*1e3:.1f} ms vs 16 Lanczos steps {t_lanczos*1e3:.1f} ms")
+    assert e_mlp < 0.8 * min(e_const, e_lin)
+    assert t_mlp < t_lanczos
