@@ -54,7 +54,7 @@ def parse():
 def kernel_source_sha() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "device_common.hpp", "engine.hip"):
+    for f in ("kernels.hpp", "select.hpp", "device_common.hpp", "engine.hip"):
         with open(os.path.join(ROOT, "paper_2410_09654_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpauli.so")
 SOURCES = [os.path.join(CSRC, "engine.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("kernels.hpp", "device_common.hpp", "mlp.hpp")] + \
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("kernels.hpp", "select.hpp", "device_common.hpp", "mlp.hpp")] + \
     [os.path.join(HERE, "..", "include", "pauli.h")]
 
 HIPCC_FLAGS = [

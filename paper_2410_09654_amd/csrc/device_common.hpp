@@ -109,17 +109,32 @@ DEV Key<W> unmix_key(const Key<W>& m) {
 // -1 / 0 / 1 lexicographic comparison, word 0 most significant.
 template <int W>
 DEV int key_cmp(const Key<W>& a, const Key<W>& b) {
+  // lexicographic over the words, written without branches (the word
+  // comparisons are combined with bitwise operators)
+  bool lt = false, gt = false;
 #pragma unroll
-  for (int i = 0; i < 2 * W; i++)
-    if (a.w[i] != b.w[i]) return a.w[i] < b.w[i] ? -1 : 1;
-  return 0;
+  for (int i = 2 * W - 1; i >= 0; i--) {
+    const bool eq = a.w[i] == b.w[i];
+    lt = (a.w[i] < b.w[i]) | (eq & lt);
+    gt = (a.w[i] > b.w[i]) | (eq & gt);
+  }
+  return (int)gt - (int)lt;
+}
+
+// (a, xa) < (b, xb) in (key, source id) order, without branches.
+template <int W>
+DEV bool key_src_less(const Key<W>& a, uint32_t xa, const Key<W>& b, uint32_t xb) {
+  bool lt = xa < xb;
+#pragma unroll
+  for (int i = 2 * W - 1; i >= 0; i--) lt = (a.w[i] < b.w[i]) | ((a.w[i] == b.w[i]) & lt);
+  return lt;
 }
 
 template <int W>
 DEV bool key_eq(const Key<W>& a, const Key<W>& b) {
   bool e = true;
 #pragma unroll
-  for (int i = 0; i < 2 * W; i++) e = e && (a.w[i] == b.w[i]);
+  for (int i = 0; i < 2 * W; i++) e = e & (a.w[i] == b.w[i]);
   return e;
 }
 
@@ -236,20 +251,17 @@ DEV uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
   }
   if (lane == 63) tmp[wv] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int i = 0; i < nw; i++) {
-      uint32_t t = tmp[i];
-      tmp[i] = run;
-      run += t;
-    }
-    tmp[nw] = run;
+  // every wave scans the (at most 16) wave totals itself
+  uint32_t t = lane < nw ? tmp[lane] : 0u;
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) {
+    uint32_t y = __shfl_up(t, d, 64);
+    if (lane >= d) t += y;
   }
-  __syncthreads();
-  uint32_t r = tmp[wv] + x - v;
-  *total = tmp[nw];
-  __syncthreads();
-  return r;
+  const uint32_t before = wv > 0 ? __shfl(t, wv - 1, 64) : 0u;
+  *total = __shfl(t, nw - 1, 64);
+  __syncthreads();  // tmp may be reused by the next scan
+  return before + x - v;
 }
 
 }  // namespace pauli

@@ -19,6 +19,7 @@
 
 #include "../../include/pauli.h"
 #include "kernels.hpp"
+#include "select.hpp"
 #include "mlp.hpp"
 
 using namespace pauli;
@@ -379,11 +380,13 @@ int Engine::run(Call& c) {
   // loop with one more pass bit
   int pass_bits = 0;
   {
+    // the count pass measured every bin exactly: one pass when they all fit
     unsigned long long mx = hctl->maxg[0];
-    while (mx > (unsigned long long)(MERGE_CAP * 3 / 4) && pass_bits < 10) {
-      pass_bits++;
-      mx = (mx + 1) / 2;
-    }
+    if (mx > (unsigned long long)MERGE_CAP)
+      while (mx > (unsigned long long)(MERGE_CAP * 3 / 4) && pass_bits < 10) {
+        pass_bits++;
+        mx = (mx + 1) / 2;
+      }
   }
   constexpr int MAX_PASS_BITS = 12;
   const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
@@ -490,31 +493,34 @@ int Engine::run(Call& c) {
       u_off += pe;
     }
   }
-  if (nbk)
-    LAUNCH("k_bucket_totals", k_bucket_totals, 1, 1024, b_slots, b_surv, b_keep, b_unique, nbk,
-           dctl);
-  TRY(read_ctl());
-  if (hctl->overflow) {
-    g_last_error = "merge bucket overflow";
-    return PAULI_EINTERNAL;
-  }
   g_stats.emitted = (int64_t)pe_all;
-  g_stats.unique = (int64_t)hctl->u_unique;
-  g_stats.survivors = (int64_t)hctl->surv_total;
   g_stats.passes = npass;
   g_stats.buckets = (int32_t)nbk;
+  if (nbk == 0) {
+    TRY(read_ctl());
+    if (hctl->overflow) {
+      g_last_error = "merge bucket overflow";
+      return PAULI_EINTERNAL;
+    }
+    g_stats.unique = 0;
+    g_stats.survivors = 0;
+    g_stats.output = 0;
+    if (c.mode == M_LANCZOS) {
+      if (c.b_out) *c.b_out = 0.0;
+      write_empty();
+      return PAULI_BREAKDOWN;
+    }
+    return write_empty();
+  }
 
   // ----- Lanczos: b_n from the untruncated sum, then divide and filter -------
   if (c.mode == M_LANCZOS) {
-    double* nrm = (double*)ar->take(16);
-    if (ar->short_) return PAULI_EWORKSPACE;
-    if (nbk) {
-      LAUNCH("k_norm_bucket", k_norm_bucket, nbk, 256, b_ubase, b_slots, uc, norm_part);
-      LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, norm_part, nbk, nrm);
-      HIP_TRY(hipMemcpyAsync(&hctl->norm_hi, nrm, 16, hipMemcpyDeviceToHost, stream));
-      HIP_TRY(hipStreamSynchronize(stream));
-    } else {
-      hctl->norm_hi = 0.0;
+    LAUNCH("k_norm_bucket", k_norm_bucket, nbk, 256, b_ubase, b_slots, uc, norm_part);
+    LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, norm_part, nbk, &dctl->norm_hi);
+    TRY(read_ctl());
+    if (hctl->overflow) {
+      g_last_error = "merge bucket overflow";
+      return PAULI_EINTERNAL;
     }
     const double b = std::sqrt(hctl->norm_hi);
     if (c.b_out) *c.b_out = b;
@@ -540,16 +546,129 @@ int Engine::run(Call& c) {
     sa.n_keep = (int)n_keep;
     sa.hist0 = hist0;
     sa.ctl = dctl;
-    if (nbk) {
-      LAUNCH("k_scale_filter", (k_scale_filter<W>), nbk, 256, sa);
-      LAUNCH("k_bucket_totals", k_bucket_totals, 1, 1024, b_slots, b_surv, b_keep,
-             (const uint32_t*)nullptr, nbk, dctl);
-    }
-    TRY(read_ctl());
-    g_stats.survivors = (int64_t)hctl->surv_total;
+    LAUNCH("k_scale_filter", (k_scale_filter<W>), nbk, 256, sa);
   }
 
-  // ----- top-M --------------------------------------------------------------
+  // ----- top-M threshold, output offsets and write, decided on the device ---
+  const int nchunk = (int)((nbk + SEL_CHUNK - 1) / SEL_CHUNK);
+  Sel2Args s2;
+  memset(&s2, 0, sizeof(s2));
+  s2.b_ubase = b_ubase;
+  s2.b_slots = b_slots;
+  s2.b_abv = b_abv;
+  s2.b_bcnt = b_bcnt;
+  s2.uk = uk;
+  s2.uc = uc;
+  s2.keep_mk = keep_mk;
+  s2.n_keep = (int)n_keep;
+  s2.nbk = nbk;
+  s2.ctl = dctl;
+  if (want_select) {
+    // the candidate lists of the multi-level select double as these lists
+    s2.list0 = cand[1];
+    s2.cc0 = ccnt[1];
+    s2.listf = cand[0];
+    s2.listfb = cand[2];
+    s2.hist1 = histL[1];
+    LAUNCH("k_hist_reduce", k_hist_reduce, SEL0_BINS / 256, 256, hist0, SEL0_BINS, hsum);
+  }
+  PlanArgs pa;
+  memset(&pa, 0, sizeof(pa));
+  pa.b_slots = b_slots;
+  pa.b_surv = b_surv;
+  pa.b_keep = b_keep;
+  pa.b_unique = b_unique;
+  pa.nbk = nbk;
+  pa.want_select = want_select ? 1 : 0;
+  pa.max_strings = want_select ? (long long)tr->max_strings : 0;
+  pa.hsum0 = hsum;
+  pa.ctl = dctl;
+  LAUNCH("k_sel_plan", k_sel_plan, 1, 1024, pa);
+  if (want_select) {
+    TRY(zero_u32(histL[1], (size_t)HREP * SEL_BINS));
+    LAUNCH("k_sel_pass1", (k_sel_pass1<W>), nchunk, 256, s2);
+    LAUNCH("k_hist_reduce", k_hist_reduce, SEL_BINS / 256, 256, histL[1], SEL_BINS, hsum);
+    LAUNCH("k_sel_pick1", k_sel_pick1, 1, 1024, hsum, dctl);
+    LAUNCH("k_sel_narrow", (k_sel_narrow<W>), nchunk, 256, s2);
+    LAUNCH("k_sel_finish", (k_sel_finish<W>), 1, 1024, s2);
+  }
+  LAUNCH("k_scan_out", k_scan_out, 1, 1024, b_surv, b_keep, b_abv, b_bcnt, nbk, b_obase, dctl);
+
+  WriteArgs wa;
+  memset(&wa, 0, sizeof(wa));
+  wa.b_ubase = b_ubase;
+  wa.b_slots = b_slots;
+  wa.b_obase = b_obase;
+  wa.uk = uk;
+  wa.uc = uc;
+  wa.keep_mk = keep_mk;
+  wa.n_keep = (int)n_keep;
+  wa.ctl = dctl;
+  wa.out_f32 = c.out.f32;
+  if (c.out.to_arena) {
+    // the output never exceeds the records emitted, nor max(M, |keep|) when
+    // a top-M cut is asked for
+    unsigned long long bound = pe_all;
+    if (want_select)
+      bound = std::min<unsigned long long>(
+          bound, (unsigned long long)std::max<long long>((long long)tr->max_strings, n_keep));
+    const size_t n = (size_t)std::max<unsigned long long>(bound, 1);
+    uint64_t* ox = (uint64_t*)ar->take_top(n * 8 * W);
+    uint64_t* oz = (uint64_t*)ar->take_top(n * 8 * W);
+    void* oc = ar->take_top(n * (c.out.f32 ? 8 : 16));
+    if (ar->short_) return PAULI_EWORKSPACE;
+    c.out.arena_op.W = W;
+    c.out.arena_op.f32 = c.out.f32;
+    c.out.arena_op.n = 0;
+    c.out.arena_op.cap = (int64_t)n;
+    c.out.arena_op.x = ox;
+    c.out.arena_op.z = oz;
+    c.out.arena_op.c = oc;
+    wa.ox = ox;
+    wa.oz = oz;
+    wa.oc = oc;
+    wa.ocap = (int64_t)n;
+  } else {
+    pauli_op* o = c.out.user;
+    wa.ox = o->x;
+    wa.oz = o->z;
+    wa.oc = o->coef;
+    wa.ocap = o->capacity;
+  }
+  LAUNCH("k_write_out", (k_write_out<W>), nchunk, 256, wa, nbk);
+  TRY(read_ctl());
+  if (hctl->overflow) {
+    g_last_error = "merge bucket overflow";
+    return PAULI_EINTERNAL;
+  }
+  g_stats.unique = (int64_t)hctl->u_unique;
+  g_stats.survivors = (int64_t)hctl->surv_total;
+
+  // Output size known: report it, or fall back to the host-driven multi-level
+  // select when the device select stopped at a large group of equal |c|.
+  auto finish_output = [&](unsigned long long nout) -> int {
+    g_stats.output = (int64_t)nout;
+    if ((unsigned long long)wa.ocap < nout) {
+      if (c.out.to_arena) {
+        g_last_error = "output above its bound";
+        return PAULI_EINTERNAL;
+      }
+      c.out.user->size = (int64_t)nout;
+      return PAULI_ECAPACITY;
+    }
+    if (c.out.to_arena) c.out.arena_op.n = (int64_t)nout;
+    else c.out.user->size = (int64_t)nout;
+    return PAULI_OK;
+  };
+  if (!hctl->deep) {
+    if (hctl->sel_mode == S_THRESHOLD && !hctl->t_found) {
+      g_last_error = "top-M threshold not found";
+      return PAULI_EINTERNAL;
+    }
+    return finish_output(hctl->out_total);
+  }
+
+  // ----- fallback: threshold by as many 12-bit levels as the ties need ------
   const unsigned long long surv = hctl->surv_total, fk = hctl->keep_total;
   const unsigned long long nonkeep = surv - fk;
   int sel_mode = S_ALL;
@@ -631,7 +750,6 @@ int Engine::run(Call& c) {
       LAUNCH("k_count_boundary", (k_count_boundary<W>), nbk, 64, sa);
     }
   }
-  if (nbk == 0) return write_empty();
   LAUNCH("k_scan_buckets", k_scan_buckets, 1, 1024, b_surv, b_keep, b_abv, b_bcnt, nbk, sel_mode,
          b_obase, dctl);
   TRY(read_ctl());
@@ -640,52 +758,13 @@ int Engine::run(Call& c) {
     return PAULI_EINTERNAL;
   }
   const unsigned long long nout = hctl->out_total;
-  g_stats.output = (int64_t)nout;
-  WriteArgs wa;
-  memset(&wa, 0, sizeof(wa));
-  wa.b_ubase = b_ubase;
-  wa.b_slots = b_slots;
-  wa.b_obase = b_obase;
-  wa.uk = uk;
-  wa.uc = uc;
-  wa.keep_mk = keep_mk;
-  wa.n_keep = (int)n_keep;
-  wa.sel_mode = sel_mode;
-  wa.ctl = dctl;
-  wa.out_f32 = c.out.f32;
-  if (c.out.to_arena) {
-    const size_t n = (size_t)std::max<unsigned long long>(nout, 1);
-    uint64_t* ox = (uint64_t*)ar->take_top(n * 8 * W);
-    uint64_t* oz = (uint64_t*)ar->take_top(n * 8 * W);
-    void* oc = ar->take_top(n * (c.out.f32 ? 8 : 16));
-    if (ar->short_) return PAULI_EWORKSPACE;
-    c.out.arena_op.W = W;
-    c.out.arena_op.f32 = c.out.f32;
-    c.out.arena_op.n = (int64_t)nout;
-    c.out.arena_op.cap = (int64_t)n;
-    c.out.arena_op.x = ox;
-    c.out.arena_op.z = oz;
-    c.out.arena_op.c = oc;
-    wa.ox = ox;
-    wa.oz = oz;
-    wa.oc = oc;
-    wa.ocap = (int64_t)n;
-  } else {
-    pauli_op* o = c.out.user;
-    if ((unsigned long long)o->capacity < nout) {
-      o->size = (int64_t)nout;
-      return PAULI_ECAPACITY;
-    }
-    wa.ox = o->x;
-    wa.oz = o->z;
-    wa.oc = o->coef;
-    wa.ocap = o->capacity;
+  if ((unsigned long long)wa.ocap >= nout && nout) {
+    wa.sel_mode = sel_mode;
+    LAUNCH("k_write", (k_write<W>), nbk, 256, wa);
+    HIP_TRY(hipStreamSynchronize(stream));
+    g_prof.resolve();
   }
-  if (nout) LAUNCH("k_write", (k_write<W>), nbk, 256, wa);
-  HIP_TRY(hipStreamSynchronize(stream));
-  g_prof.resolve();
-  if (!c.out.to_arena) c.out.user->size = (int64_t)nout;
-  return PAULI_OK;
+  return finish_output(nout);
 }
 
 int dispatch(Engine& e, Call& c) {

@@ -51,6 +51,10 @@ struct Ctl {
   unsigned long long out_total;
   double norm_hi, norm_lo;
   double inner[4];
+  int sel_mode;                  // SelMode chosen on the device
+  unsigned int fin_level;        // 0: finish on the level-1 list, 1: after digit 1
+  unsigned int deep;             // the device select stopped: the host finishes it
+  unsigned int sel_d0, sel_d1;   // threshold digits 0 and 1
 };
 
 struct EmitArgs {
@@ -101,6 +105,16 @@ struct Rec {
   RecV<F32> v;
 };
 
+// Row of the count matrix (and so the place of a workgroup's records inside
+// every bin) for workgroup b of a grid of n: workgroups go to the eight XCDs
+// round robin (b mod 8), so this numbering gives each XCD a contiguous range
+// of rows.  Its partial cache lines in a bin then fill up inside its own L2
+// instead of reaching memory as separate partial writes.
+__device__ __forceinline__ uint32_t layout_row(uint32_t b, uint32_t n) {
+  const uint32_t n8 = n & ~7u;
+  return b < n8 ? (b & 7u) * (n8 >> 3) + (b >> 3) : b;
+}
+
 template <int W, bool F32, bool SCATTER>
 __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
   using V = RecV<F32>;
@@ -109,8 +123,9 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int row = blockIdx.x;
+  const uint32_t lrow = layout_row(blockIdx.x, gridDim.x);
   if (SCATTER) {
-    const uint32_t* crow = a.counts + (size_t)row * NBINS;
+    const uint32_t* crow = a.counts + (size_t)lrow * NBINS;
     for (int i = tid; i < NBINS; i += EMIT_THREADS) hist[i] = a.bin_base[i] + crow[i];
   } else {
     for (int i = tid; i < NBINS; i += EMIT_THREADS) hist[i] = 0u;
@@ -257,7 +272,7 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
   }
   __syncthreads();
   if (!SCATTER) {
-    uint32_t* crow = a.counts + (size_t)row * NBINS;
+    uint32_t* crow = a.counts + (size_t)lrow * NBINS;
     for (int i = tid; i < NBINS; i += EMIT_THREADS) crow[i] = hist[i];
   }
 }
@@ -288,19 +303,21 @@ __global__ void k_scan_cols(uint32_t* counts, int rows, uint32_t* bin_total, Ctl
   bin_total[b] = (uint32_t)run;
 }
 
-// Exclusive scan of the bin totals (one block of 1024 threads, 16 bins each)
+// Exclusive scan of the bin totals (one block of 1024 threads, NBINS/1024 bins each)
 // and the largest total over aligned groups of 1, 2, 4, 8, 16 bins.
 __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, uint32_t* bin_base,
                                                     Ctl* ctl) {
   __shared__ unsigned long long tmp[1024 / 64 + 1];
   __shared__ unsigned int gmax[5];
+  constexpr int BPT = NBINS / 1024;
+  static_assert(BPT >= 16 && BPT * 1024 == NBINS, "k_scan_bins covers NBINS with 1024 threads");
   const int t = threadIdx.x;
   if (t < 5) gmax[t] = 0;
-  uint32_t v[16];
+  uint32_t v[BPT];
   unsigned long long s = 0;
 #pragma unroll
-  for (int k = 0; k < 16; k++) {
-    v[k] = bin_total[t * 16 + k];
+  for (int k = 0; k < BPT; k++) {
+    v[k] = bin_total[t * BPT + k];
     s += v[k];
   }
   unsigned int lm[5];
@@ -308,7 +325,7 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   for (int lg = 0; lg < 5; lg++) {
     const int g = 1 << lg;
     unsigned int best = 0;
-    for (int k = 0; k < 16; k += g) {
+    for (int k = 0; k < BPT; k += g) {
       unsigned long long acc = 0;
       for (int q = 0; q < g; q++) acc += v[k + q];
       if (acc > best) best = acc > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned int)acc;
@@ -339,8 +356,8 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   for (int lg = 0; lg < 5; lg++) atomicMax(&gmax[lg], lm[lg]);
   unsigned long long pre = tmp[wv] + x - s;
 #pragma unroll
-  for (int k = 0; k < 16; k++) {
-    bin_base[t * 16 + k] = (uint32_t)pre;
+  for (int k = 0; k < BPT; k++) {
+    bin_base[t * BPT + k] = (uint32_t)pre;
     pre += v[k];
   }
   __syncthreads();
@@ -531,12 +548,8 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
           k1 = mk[p + 1];
           x1 = sx[p + 1];
         }
-        const int c0 = key_cmp<W>(k0, rkey[k]);
-        rank += (c0 < 0 || (c0 == 0 && x0 < rsx[k])) ? 1u : 0u;
-        if (two) {
-          const int c1 = key_cmp<W>(k1, rkey[k]);
-          rank += (c1 < 0 || (c1 == 0 && x1 < rsx[k])) ? 1u : 0u;
-        }
+        rank += key_src_less<W>(k0, x0, rkey[k], rsx[k]) ? 1u : 0u;
+        rank += (two & key_src_less<W>(k1, x1, rkey[k], rsx[k])) ? 1u : 0u;
       }
       fpos[k] = s0 + rank;
     }
