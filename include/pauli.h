@@ -125,6 +125,20 @@ int pauli_truncate(const pauli_op *in, const pauli_trunc *t, pauli_op *out, paul
  * zeros dropped, library order.  Duplicates allowed; up to 2^28 strings. */
 int pauli_canonicalize(const pauli_op *in, pauli_op *out, pauli_ws *ws, void *stream);
 
+/* Order keys: for every string of A its 2W-word key whose ascending
+ * lexicographic order (word 0 most significant, unsigned) is the library's
+ * canonical storage order.  The key is a bijective mix of the string's x and
+ * z words (two Feistel rounds with the MurmurHash3 fmix64 finalizer).  keys:
+ * device array [A->size][2W], caller-owned.  Synchronous at return. */
+int pauli_order_keys(const pauli_op *A, uint64_t *keys, void *stream);
+
+/* Inverse of pauli_order_keys: the x and z words (word-major, capacity cap,
+ * caller-owned device arrays) of n strings of n_qubits sites from their order
+ * keys [n][2W].  The caller passes keys of n_qubits-site strings; bits beyond
+ * n_qubits are returned as the inverse produces them.  Synchronous. */
+int pauli_strings_from_order_keys(int32_t n_qubits, const uint64_t *keys, int64_t n,
+                                  uint64_t *x, uint64_t *z, int64_t cap, void *stream);
+
 /* One classical Runge-Kutta step of the Heisenberg equation dO/dt = i[H, O]
  * (Heisenberg time evolution section):
  *   k1 = i[H,O];  S2 = trunc(O + fl(dt/2) k1);  k2 = i[H,S2];

@@ -14,7 +14,8 @@ PAULI_C128, PAULI_C64K = 0, 1
 EXPORTS = ["pauli_commutator", "pauli_add", "pauli_truncate", "pauli_canonicalize",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
            "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_read",
-           "pauli_last_stats", "pauli_mlp_num_params", "pauli_mlp_sync", "pauli_mlp_forward",
+           "pauli_last_stats", "pauli_order_keys", "pauli_strings_from_order_keys",
+           "pauli_mlp_num_params", "pauli_mlp_sync", "pauli_mlp_forward",
            "pauli_mlp_loss_grad", "pauli_mlp_adam", "pauli_gemm_bf16"]
 
 
@@ -78,6 +79,10 @@ def load():
     L.pauli_profile_read.restype = ctypes.c_size_t
     L.pauli_last_stats.argtypes = [P(PauliStatsC)]
     L.pauli_last_stats.restype = None
+    L.pauli_order_keys.argtypes = [P(PauliOpC), ctypes.c_void_p, ctypes.c_void_p]
+    L.pauli_strings_from_order_keys.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                                ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_int64, ctypes.c_void_p]
     for name in EXPORTS:
         if name in ("pauli_strerror", "pauli_last_error", "pauli_profile_read",
                     "pauli_last_stats"):

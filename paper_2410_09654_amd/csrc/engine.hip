@@ -432,6 +432,7 @@ int Engine::run(Call& c) {
     ma.gkind[g] = c.groups[g].kind;
   }
   ma.mode = c.mode;
+  ma.single = (c.n_groups == 1 && c.groups[0].kind != G_SUM_KAHAN32) ? 1 : 0;
   ma.round32 = c.round32 ? 1 : 0;
   ma.max_len = tr ? tr->max_len : 0;
   ma.use_eps = (tr && tr->coef_eps > 0.0) ? 1 : 0;
@@ -1031,6 +1032,43 @@ int pauli_rk4_step(const pauli_op* H, const pauli_op* O, double dt, const pauli_
   c.trunc = t;
   c.out.user = out;
   return run_call(ar, ws, stream, c);
+}
+
+int pauli_order_keys(const pauli_op* A, uint64_t* keys, void* stream_) {
+  if (!keys || check_op(A, false)) return PAULI_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  const int64_t n = A->size;
+  if (n == 0) return PAULI_OK;
+  const int W = words_of(A->n_qubits);
+  const int64_t blocks = (n + 255) / 256;
+  if (W == 1)
+    LAUNCH("k_order_keys", k_order_keys<1>, blocks, 256, A->x, A->z, A->capacity, n,
+           reinterpret_cast<Key<1>*>(keys));
+  else
+    LAUNCH("k_order_keys", k_order_keys<2>, blocks, 256, A->x, A->z, A->capacity, n,
+           reinterpret_cast<Key<2>*>(keys));
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  return PAULI_OK;
+}
+
+int pauli_strings_from_order_keys(int32_t n_qubits, const uint64_t* keys, int64_t n, uint64_t* x,
+                                  uint64_t* z, int64_t cap, void* stream_) {
+  if (n_qubits < 1 || n_qubits > 128 || n < 0 || cap < n || (n && (!keys || !x || !z)))
+    return PAULI_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (n == 0) return PAULI_OK;
+  const int W = words_of(n_qubits);
+  const int64_t blocks = (n + 255) / 256;
+  if (W == 1)
+    LAUNCH("k_from_order_keys", k_from_order_keys<1>, blocks, 256,
+           reinterpret_cast<const Key<1>*>(keys), n, x, z, cap);
+  else
+    LAUNCH("k_from_order_keys", k_from_order_keys<2>, blocks, 256,
+           reinterpret_cast<const Key<2>*>(keys), n, x, z, cap);
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  return PAULI_OK;
 }
 
 int pauli_norm2(const pauli_op* A, double* out, pauli_ws* ws, void* stream_) {

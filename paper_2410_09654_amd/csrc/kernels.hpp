@@ -382,6 +382,7 @@ struct MergeArgs {
   int alpha_kind[MAX_GROUPS];
   int gkind[MAX_GROUPS];
   int mode;
+  int single;  // one group, not Kahan: runs fold as plain sums
   int round32;
   int max_len;
   int use_eps;
@@ -423,6 +424,67 @@ DEV double2 apply_alpha(int kind, double2 alpha, double2 v) {
 
 DEV double round_to_f32(double v) { return (double)(float)v; }
 
+// The DIGIT_BITS + 32 bits of a mixed key that follow its first `shift`
+// bits (0 <= shift < 64): the in-bucket digit on top, then 32 sort bits.
+template <int W>
+DEV uint64_t key_window(const Key<W>& m, int shift) {
+  const uint64_t hi = shift ? ((m.w[0] << shift) | (m.w[1] >> (64 - shift))) : m.w[0];
+  return hi >> (64 - DIGIT_BITS - 32);
+}
+
+// Rank of every record of the block inside its digit group by full
+// (mixed key, source id) comparison, used when two distinct keys of a group
+// share their 32 sort bits.  On entry mk/sx/sv hold the n records grouped by
+// digit (ascending); on return they are in (key, source id) order.
+template <int W, bool F32>
+DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, int shift) {
+  constexpr int PER = (MERGE_CAP + MERGE_THREADS - 1) / MERGE_THREADS;
+  Key<W> k[PER];
+  uint32_t x[PER], pos[PER];
+  RecV<F32> v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const uint32_t p = threadIdx.x + q * MERGE_THREADS;
+    pos[q] = p;
+    if (p < n) {
+      k[q] = mk[p];
+      x[q] = sx[p];
+      v[q] = sv[p];
+      const uint32_t d = (uint32_t)(key_window<W>(k[q], shift) >> 32);
+      // digit group [s0, s1): binary searches on the (ascending) digits
+      uint32_t lo = 0, hi = p;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint32_t)(key_window<W>(mk[mid], shift) >> 32) < d) lo = mid + 1;
+        else hi = mid;
+      }
+      const uint32_t s0 = lo;
+      lo = p + 1;
+      hi = n;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint32_t)(key_window<W>(mk[mid], shift) >> 32) <= d) lo = mid + 1;
+        else hi = mid;
+      }
+      const uint32_t s1 = lo;
+      uint32_t rank = 0;
+      for (uint32_t r = s0; r < s1; r++) rank += key_src_less<W>(mk[r], sx[r], k[q], x[q]) ? 1u : 0u;
+      pos[q] = s0 + rank;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const uint32_t p = threadIdx.x + q * MERGE_THREADS;
+    if (p < n) {
+      mk[pos[q]] = k[q];
+      sx[pos[q]] = x[q];
+      sv[pos[q]] = v[q];
+    }
+  }
+  __syncthreads();
+}
+
 template <int W, bool F32>
 __global__ __launch_bounds__(MERGE_THREADS)
 __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
@@ -430,12 +492,20 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
   constexpr int PER = (MERGE_CAP + MERGE_THREADS - 1) / MERGE_THREADS;
   constexpr int DPT = NDIGITS / MERGE_THREADS;
   static_assert(SEL0_BINS == NDIGITS, "digit counts and |c|^2 histogram share LDS");
-  // mk / sx hold the records first in digit-group order (while ranks are
-  // computed), then in final sorted order; dh holds the digit counts and
-  // starts, then the exponent histogram of |c|^2.
+  // Sort: a counting sort on the DIGIT_BITS key bits after the bucket bits,
+  // then the rank of every record inside its digit group by a 64-bit sort
+  // word (the next 32 key bits, then the source id), read from `swd` (which
+  // aliases sv until the values are written).  mk / sx / sv then hold the
+  // records in sorted order; dh holds the digit counts and starts, then the
+  // exponent histogram of |c|^2.  Two distinct keys of one digit group with
+  // equal sort bits show up as adjacent entries with equal windows but
+  // different keys; the block then ranks by full keys (merge_full_rank).
   __shared__ Key<W> mk[MERGE_CAP];
-  __shared__ V sv[MERGE_CAP];
+  __shared__ __align__(16) V sv[MERGE_CAP];
+  static_assert(sizeof(V) >= sizeof(uint64_t), "sort words alias the values");
+  uint64_t* const swd = reinterpret_cast<uint64_t*>(sv);
   __shared__ uint32_t sx[MERGE_CAP];
+  __shared__ int s_collide;
   __shared__ uint32_t dh[NDIGITS];
   uint32_t* const h0 = dh;
   __shared__ uint32_t scan_tmp[MERGE_THREADS / 64 + 1];
@@ -471,6 +541,7 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
   }
   const int G = 1 << a.g_log;
   if (tid <= G) sbb[tid] = a.bin_base[(j << a.g_log) + tid];
+  if (tid == 0) s_collide = 0;
   __syncthreads();
 
   const Rec<W, F32>* recs = reinterpret_cast<const Rec<W, F32>*>(a.recs);
@@ -478,6 +549,10 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
   const uint32_t ibits = (uint32_t)(F - 3);
   uint32_t dig[PER], rnk[PER], rsx[PER];
   Key<W> rkey[PER];
+  // sort word of record k (recomputed where needed to spare registers)
+  auto sort_word = [&](int k) -> uint64_t {
+    return (key_window<W>(rkey[k], a.digit_shift) << 32) | rsx[k];
+  };
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
@@ -496,7 +571,7 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
       rkey[k] = m;
       rsx[k] = a.wide ? a.rsrc_wide[pos]
                       : (((small >> ibits) << GROUP_SHIFT) | (small & ((1u << ibits) - 1u)));
-      dig[k] = (uint32_t)((m.w[0] << a.digit_shift) >> (64 - DIGIT_BITS));
+      dig[k] = (uint32_t)(key_window<W>(m, a.digit_shift) >> 32);
       rnk[k] = atomicAdd(&dh[dig[k]], 1u);
     }
   }
@@ -518,18 +593,15 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
     }
   }
   __syncthreads();
-  // records in digit-group order
+  // sort words in digit-group order
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
-    if (i < n) {
-      mk[dh[dig[k]] + rnk[k]] = rkey[k];
-      sx[dh[dig[k]] + rnk[k]] = rsx[k];
-    }
+    if (i < n) swd[dh[dig[k]] + rnk[k]] = sort_word(k);
   }
   __syncthreads();
   // Final position of every record: its digit group's start plus the number of
-  // group members that precede it in (mixed key, source id) order.
+  // group members with a smaller sort word (equal words: earlier entry first).
   uint32_t fpos[PER];
 #pragma unroll
   for (int k = 0; k < PER; k++) {
@@ -538,18 +610,20 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
     if (i < n) {
       const uint32_t s0 = dh[dig[k]];
       const uint32_t s1 = dig[k] + 1 < (uint32_t)NDIGITS ? dh[dig[k] + 1] : n;
+      const uint32_t me = s0 + rnk[k];
+      const uint64_t w = sort_word(k);
       uint32_t rank = 0;
-      for (uint32_t p = s0; p < s1; p += 2) {
-        // two group members per step: both LDS loads are issued before use
-        Key<W> k0 = mk[p], k1 = k0;
-        uint32_t x0 = sx[p], x1 = 0;
-        const bool two = p + 1 < s1;
-        if (two) {
-          k1 = mk[p + 1];
-          x1 = sx[p + 1];
-        }
-        rank += key_src_less<W>(k0, x0, rkey[k], rsx[k]) ? 1u : 0u;
-        rank += (two & key_src_less<W>(k1, x1, rkey[k], rsx[k])) ? 1u : 0u;
+      uint32_t p = s0;
+      for (; p + 4 <= s1; p += 4) {
+        const uint64_t w0 = swd[p], w1 = swd[p + 1], w2 = swd[p + 2], w3 = swd[p + 3];
+        rank += ((w0 < w) | ((w0 == w) & (p < me))) ? 1u : 0u;
+        rank += ((w1 < w) | ((w1 == w) & (p + 1 < me))) ? 1u : 0u;
+        rank += ((w2 < w) | ((w2 == w) & (p + 2 < me))) ? 1u : 0u;
+        rank += ((w3 < w) | ((w3 == w) & (p + 3 < me))) ? 1u : 0u;
+      }
+      for (; p < s1; p++) {
+        const uint64_t w0 = swd[p];
+        rank += ((w0 < w) | ((w0 == w) & (p < me))) ? 1u : 0u;
       }
       fpos[k] = s0 + rank;
     }
@@ -575,6 +649,33 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
   // adds its contributions in ascending source index, then
   // acc = g0, acc = fl(acc + g1), ... after scaling each group by its alpha.
   auto fold = [&](uint32_t p, uint32_t q, double2& out) -> bool {
+    if (a.single) {
+      // one group: the sequential sum of the run, then the group's alpha
+      const int g = (int)(sx[p] >> GROUP_SHIFT);
+      const V v0 = sv[p];
+      double sr = (double)v0.x, si = (double)v0.y;
+      uint32_t r = p + 1;
+      for (; r + 4 <= q; r += 4) {
+        const V v1 = sv[r], v2 = sv[r + 1], v3 = sv[r + 2], v4 = sv[r + 3];
+        sr = sr + (double)v1.x;
+        si = si + (double)v1.y;
+        sr = sr + (double)v2.x;
+        si = si + (double)v2.y;
+        sr = sr + (double)v3.x;
+        si = si + (double)v3.y;
+        sr = sr + (double)v4.x;
+        si = si + (double)v4.y;
+      }
+      for (; r < q; r++) {
+        const V v1 = sv[r];
+        sr = sr + (double)v1.x;
+        si = si + (double)v1.y;
+      }
+      double2 acc = apply_alpha(s_ak[g], s_al[g], make_double2(sr, si));
+      if (a.round32) acc = make_double2(round_to_f32(acc.x), round_to_f32(acc.y));
+      out = acc;
+      return !is_zero(acc);
+    }
     bool present = false;
     double2 acc = make_double2(0.0, 0.0);
     int cur = -1;
@@ -643,11 +744,31 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
   const uint32_t nwords = (n + 63) / 64;
   for (uint32_t r = 0; r < nround; r++) {
     const uint32_t p = r * MERGE_THREADS + tid;
-    const bool head = p < n && (p == 0 || !key_eq<W>(mk[p - 1], mk[p]));
+    bool head = false;
+    if (p < n) {
+      head = p == 0;
+      if (p > 0) {
+        const Key<W> k0 = mk[p - 1], k1 = mk[p];
+        head = !key_eq<W>(k0, k1);
+        if (head && key_window<W>(k0, a.digit_shift) == key_window<W>(k1, a.digit_shift))
+          s_collide = 1;
+      }
+    }
     const uint64_t m = __ballot(head);
     if ((tid & 63) == 0 && (p >> 6) < (uint32_t)NHW) hmask[p >> 6] = m;
   }
   __syncthreads();
+  if (s_collide) {
+    // rare: distinct keys with equal sort bits; rank again by full keys
+    merge_full_rank<W, F32>(mk, sx, sv, n, a.digit_shift);
+    for (uint32_t r = 0; r < nround; r++) {
+      const uint32_t p = r * MERGE_THREADS + tid;
+      const bool head = p < n && (p == 0 || !key_eq<W>(mk[p - 1], mk[p]));
+      const uint64_t m = __ballot(head);
+      if ((tid & 63) == 0 && (p >> 6) < (uint32_t)NHW) hmask[p >> 6] = m;
+    }
+    __syncthreads();
+  }
   for (uint32_t r = 0; r < nround; r++) {
     const uint32_t p = r * MERGE_THREADS + tid;
     bool surv = false;
@@ -1307,6 +1428,34 @@ __global__ void k_mix_keys(const uint64_t* x, const uint64_t* z, int64_t cap, in
       rp.w[W + w] = z[(size_t)w * cap + i - 1];
     }
     if (key_cmp<W>(mix_key<W>(rp), m) >= 0) atomicOr(bad, 1u);
+  }
+}
+
+// Order keys of an operator's strings, and the strings of order keys.
+template <int W>
+__global__ void k_order_keys(const uint64_t* x, const uint64_t* z, int64_t cap, int64_t n,
+                             Key<W>* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Key<W> raw;
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    raw.w[w] = x[(size_t)w * cap + i];
+    raw.w[W + w] = z[(size_t)w * cap + i];
+  }
+  out[i] = mix_key<W>(raw);
+}
+
+template <int W>
+__global__ void k_from_order_keys(const Key<W>* keys, int64_t n, uint64_t* x, uint64_t* z,
+                                  int64_t cap) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Key<W> raw = unmix_key<W>(keys[i]);
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    x[(size_t)w * cap + i] = raw.w[w];
+    z[(size_t)w * cap + i] = raw.w[W + w];
   }
 }
 

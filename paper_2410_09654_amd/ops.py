@@ -337,6 +337,33 @@ def inner(A: PauliOp, B: PauliOp, ws: Workspace | None = None) -> complex:
     return complex(r[0], r[1])
 
 
+def order_keys(A: PauliOp) -> torch.Tensor:
+    """[A.size, 2W] int64 order keys: ascending (word 0 first, unsigned) is the
+    canonical storage order."""
+    L = _lib.load()
+    keys = torch.empty((max(A.size, 1), 2 * A.W), dtype=torch.int64, device=A.device)
+    As = A.c_struct()
+    st = L.pauli_order_keys(ctypes.byref(As), keys.data_ptr(), _stream_handle())
+    if st != PAULI_OK:
+        raise PauliError(st, "pauli_order_keys", _lib.last_error())
+    return keys[:A.size]
+
+
+def strings_from_order_keys(n_qubits: int, keys: torch.Tensor):
+    """(x, z) int64 [W, n] of the strings with the given [n, 2W] order keys."""
+    L = _lib.load()
+    keys = keys.contiguous()
+    n = keys.shape[0]
+    W = (n_qubits + 63) // 64
+    x = torch.zeros((W, max(n, 1)), dtype=torch.int64, device=keys.device)
+    z = torch.zeros_like(x)
+    st = L.pauli_strings_from_order_keys(n_qubits, keys.data_ptr(), n, x.data_ptr(), z.data_ptr(),
+                                         x.shape[1], _stream_handle())
+    if st != PAULI_OK:
+        raise PauliError(st, "pauli_strings_from_order_keys", _lib.last_error())
+    return x[:, :n], z[:, :n]
+
+
 # -- kernel timing -------------------------------------------------------------
 
 def profile_enable(on: bool = True):

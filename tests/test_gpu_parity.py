@@ -291,3 +291,62 @@ def test_small_workspace_and_capacity_retry(pk):
     assert rc == _lib.PAULI_EWORKSPACE and wss.required > 4096
     got = pk.commutator(Hd, Od, out=out, ws=small).to_host()
     assert_same_operator(got, oracle.commutator(H, O), what="after retries")
+
+
+def _colliding_operator(pk, n, seed):
+    """A random operator plus groups of strings whose order keys agree in
+    their whole first word (so they share merge bucket, in-bucket digit and
+    sort bits) and differ only in the low bits of the next word."""
+    import torch
+    rng = np.random.default_rng(seed)
+    base = wl.random_operator(n, 3000, seed=seed, density=0.1)
+    Bd = pk.PauliOp.from_raw(n, base.x, base.z, base.coef)
+    keys = pk.order_keys(Bd).cpu().numpy().view(np.uint64)
+    W = (n + 63) // 64
+    extra = []
+    for g in range(40):
+        k0 = keys[rng.integers(len(keys))].copy()
+        for v in rng.choice(4096, size=int(rng.integers(2, 6)), replace=False):
+            k = k0.copy()
+            k[1] = (k[1] & ~np.uint64(0xFFF)) | np.uint64(v)
+            extra.append(k)
+    ek = torch.from_numpy(np.array(extra, dtype=np.uint64).view(np.int64)).cuda()
+    ex, ez = pk.strings_from_order_keys(n, ek)
+    ex = ex.cpu().numpy().view(np.uint64).T.copy()
+    ez = ez.cpu().numpy().view(np.uint64).T.copy()
+    if n % 64:  # keep only strings of n sites
+        top = np.uint64((1 << (n % 64)) - 1)
+        ok = ((ex[:, W - 1] & ~top) == 0) & ((ez[:, W - 1] & ~top) == 0)
+        ex, ez = ex[ok], ez[ok]
+    coef = rng.standard_normal(len(ex)) + 1j * rng.standard_normal(len(ex))
+    allx = np.concatenate([base.x, ex])
+    allz = np.concatenate([base.z, ez])
+    allc = np.concatenate([base.coef, coef])
+    # drop strings the extra ones happen to repeat
+    _, first = np.unique(np.concatenate([allx, allz], 1), axis=0, return_index=True)
+    first = np.sort(first)
+    return wl.HostOp(n, allx[first], allz[first], allc[first]), len(ex)
+
+
+@pytest.mark.parametrize("n,seed", [(64, 3), (128, 4)])
+def test_sort_bit_collisions(pk, ws, n, seed):
+    """Distinct strings whose order keys share the first word: the merge's
+    sort words tie and the block ranks by full keys; values and canonical
+    order must still come out right."""
+    say(f"sort-bit collisions n={n}")
+    O, nx = _colliding_operator(pk, n, seed)
+    assert nx > 60
+    for M in (0, O.n // 2):
+        t = oracle.Trunc(max_strings=M)
+        want = oracle.truncate(O, t)
+        got = pk.truncate(up(pk, O, ws), pk.Trunc(max_strings=M), ws=ws)
+        assert_same_operator(got.to_host(), want, rtol=0.0, what=f"collisions M={M}")
+        k = pk.order_keys(got).cpu().numpy().view(np.uint64)
+        order = np.lexsort(k.T[::-1])
+        assert (order == np.arange(len(k))).all(), "output not in ascending order-key order"
+    # the same strings as the sum of two operators (two groups)
+    A = wl.HostOp(n, O.x[::2], O.z[::2], O.coef[::2])
+    B = wl.HostOp(n, O.x[1::2], O.z[1::2], O.coef[1::2])
+    want = oracle.add(A, 1.0, B, -0.5)
+    got = pk.add(up(pk, A, ws), 1.0, up(pk, B, ws), -0.5, ws=ws).to_host()
+    assert_same_operator(got, want, rtol=0.0, what="collisions add")
