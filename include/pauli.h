@@ -212,8 +212,10 @@ int pauli_gemm_bf16(const uint16_t *A, int lda, int transA, const uint16_t *B, i
 /* Counters of the last engine pass of this thread's last call (diagnostics and
  * the algorithmic byte counts of the benchmark). */
 typedef struct pauli_stats {
-  int64_t emitted;   /* records produced: anticommuting pairs + operator terms */
-  int64_t unique;    /* distinct strings with a nonzero merged coefficient */
+  int64_t emitted;   /* records produced: anticommuting pairs + operator terms
+                        (calls other than the Lanczos step leave out strings
+                        above the length cap, which depends on the key alone) */
+  int64_t unique;    /* distinct emitted strings with a nonzero merged coefficient */
   int64_t survivors; /* of those, left after the length and |c| filters */
   int64_t output;    /* strings written to the output */
   int32_t passes;    /* hash-range passes */

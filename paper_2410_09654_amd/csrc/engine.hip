@@ -283,8 +283,10 @@ int Engine::run(Call& c) {
     g_last_error = "H has more strings than one merge bucket holds";
     return PAULI_EINVAL;
   }
-  int comm_rows = comm ? (int)std::min<int64_t>((c.O.n + EMIT_THREADS - 1) / EMIT_THREADS, 512) : 0;
-  int term_rows = nterm_rec > 0 ? (int)std::min<int64_t>((nterm_rec + EMIT_THREADS - 1) / EMIT_THREADS, 256) : 0;
+  // at most 2^18 (commutator) and 2^17 (operator terms) threads of emit rows
+  constexpr int64_t COMM_ROWS_MAX = (1 << 18) / EMIT_THREADS, TERM_ROWS_MAX = (1 << 17) / EMIT_THREADS;
+  int comm_rows = comm ? (int)std::min<int64_t>((c.O.n + EMIT_THREADS - 1) / EMIT_THREADS, COMM_ROWS_MAX) : 0;
+  int term_rows = nterm_rec > 0 ? (int)std::min<int64_t>((nterm_rec + EMIT_THREADS - 1) / EMIT_THREADS, TERM_ROWS_MAX) : 0;
   const int rows = comm_rows + term_rows;
 
   dctl = (Ctl*)ar->take(sizeof(Ctl));
@@ -358,6 +360,7 @@ int Engine::run(Call& c) {
   for (int t = 0; t <= c.n_terms; t++) ea.tstart[t] = tstart[t];
   ea.counts = counts;
   ea.bin_base = bin_base;
+  ea.max_len = (c.mode == M_PLAIN && tr) ? tr->max_len : 0;
 
   auto count_pass = [&](int pass_bits, uint32_t pass_id) -> int {
     ea.pass_bits = pass_bits;

@@ -81,6 +81,9 @@ struct EmitArgs {
   uint32_t tgroup[MAX_TERMS];
   int tlist[MAX_TERMS];
   int64_t tstart[MAX_TERMS + 1];
+  // strings longer than this are not emitted (plain mode; 0: no cap): the
+  // length cap depends on the key alone, so it can act before the merge
+  int max_len;
   // binning
   int pass_bits;
   uint32_t pass_id;
@@ -135,6 +138,7 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
   const int F = NBINS_LOG + a.pass_bits;
 
   auto deposit = [&](const Key<W>& raw, V val, uint32_t group, uint32_t index) {
+    if (a.max_len > 0 && key_length<W>(raw) > a.max_len) return;
     Key<W> mk = mix_key<W>(raw);
     uint64_t top = mk.w[0];
     if (a.pass_bits) {
@@ -793,11 +797,11 @@ __attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
         if (q > n) q = n;
         if (fold(p, q, v)) {
           nzu++;
-          raw = unmix_key<W>(kp);
+          raw = kp;  // U keeps order keys; raw strings are restored where needed
           surv = true;
           if (a.mode != M_LANCZOS) {
-            if (a.max_len > 0 && key_length<W>(raw) > a.max_len) surv = false;
-            if (surv && a.use_eps && !(weight2(v) >= a.eps2)) surv = false;
+            // the length cap was applied when the records were emitted
+            if (a.use_eps && !(weight2(v) >= a.eps2)) surv = false;
             if (surv) {
               const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, kp) : false;
               if (isk) kc++;
@@ -960,12 +964,12 @@ __global__ __launch_bounds__(256) void k_scale_filter(ScaleArgs a) {
     v = make_double2(v.x / a.bnorm, v.y / a.bnorm);
     if (a.round32) v = make_double2(round_to_f32(v.x), round_to_f32(v.y));
     bool ok = !is_zero(v);
-    const Key<W> raw = uk[i];
-    if (ok && a.max_len > 0 && key_length<W>(raw) > a.max_len) ok = false;
+    const Key<W> mk = uk[i];
+    if (ok && a.max_len > 0 && key_length<W>(unmix_key<W>(mk)) > a.max_len) ok = false;
     if (ok && a.use_eps && !(weight2(v) >= a.eps2)) ok = false;
     if (ok) {
       surv++;
-      bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mix_key<W>(raw)) : false;
+      bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mk) : false;
       if (isk) kc++;
       else atomicAdd(&h0[(uint32_t)(__double_as_longlong(weight2(v)) >> 52)], 1u);
     } else {
@@ -1127,10 +1131,10 @@ __global__ __launch_bounds__(256) void k_level1(SelArgs a) {
     if (i < ns) {
       const double2 v = uc[i];
       if (!is_zero(v)) {
-        const Key<W> raw = uk[i];
-        const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mix_key<W>(raw)) : false;
+        const Key<W> mk = uk[i];
+        const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mk) : false;
         if (!isk) {
-          composite<W>(v, raw, c);
+          composite<W>(v, unmix_key<W>(mk), c);
           const uint32_t d0 = comp_digit<W>(c, 0);
           if (d0 > D) abv++;
           else if (d0 == D) cand = true;
@@ -1186,7 +1190,7 @@ __global__ __launch_bounds__(256) void k_cand_level(SelArgs a) {
     uint32_t ui = 0;
     if (i < n) {
       ui = a.list_in[ub + i];
-      composite<W>(a.uc[ui], ukb[ui], c);
+      composite<W>(a.uc[ui], unmix_key<W>(ukb[ui]), c);
       keepit = comp_digit<W>(c, a.level) == D;
     }
     uint32_t tot;
@@ -1225,7 +1229,7 @@ __global__ __launch_bounds__(1024) void k_finish(SelArgs a) {
     for (uint32_t k = 0; k < n; k++) {
       const uint32_t ui = a.list_in[ub + k];
       uint64_t c[NW];
-      composite<W>(a.uc[ui], ukb[ui], c);
+      composite<W>(a.uc[ui], unmix_key<W>(ukb[ui]), c);
       const unsigned int p = atomicAdd(&m, 1u);
       if (p < FINISH_CAP)
         for (int q = 0; q < NW; q++) cs[p][q] = c[q];
@@ -1259,7 +1263,7 @@ __global__ __launch_bounds__(64) void k_count_boundary(SelArgs a) {
     for (uint32_t i = threadIdx.x; i < n; i += 64) {
       const uint32_t ui = a.list_in[ub + i];
       uint64_t c[NW];
-      composite<W>(a.uc[ui], ukb[ui], c);
+      composite<W>(a.uc[ui], unmix_key<W>(ukb[ui]), c);
       if (comp_cmp<W>(c, T) >= 0) cnt++;
     }
     for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_down(cnt, d, 64);
@@ -1361,11 +1365,11 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
     if (i < ns) {
       v = uc[i];
       if (!is_zero(v)) {
-        raw = uk[i];
+        raw = unmix_key<W>(uk[i]);
         if (a.sel_mode == S_ALL) {
           s = true;
         } else {
-          const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mix_key<W>(raw)) : false;
+          const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, uk[i]) : false;
           if (isk) s = true;
           else if (a.sel_mode == S_THRESHOLD) {
             uint64_t c[NW];

@@ -1,8 +1,8 @@
 // Top-M selection and output compaction, driven from the device.
 //
 // After the merge every bucket b holds its surviving strings (length cap and
-// coefficient threshold applied) at U slots [b_ubase[b], b_ubase[b] +
-// b_slots[b]), with per-bucket counts of survivors and keep-set survivors and
+// coefficient threshold applied; keys as order keys) at U slots
+// [b_ubase[b], b_ubase[b] + b_slots[b]), with per-bucket counts of survivors and keep-set survivors and
 // a replicated exponent histogram of |c|^2 over the non-keep survivors.  The
 // kernels below decide, without a host round trip, whether a threshold is
 // needed (the keep set is always kept and counts toward M; ties are broken by
@@ -212,10 +212,10 @@ __global__ __launch_bounds__(256) void k_sel_pass1(Sel2Args a) {
       if (i < ns) {
         if (!is_zero(v)) {
           bool isk = false;
-          Key<W> raw;
+          Key<W> mk;
           if (a.n_keep) {
-            raw = ukb[ub + i];
-            isk = keep_lookup<W>(keep, a.n_keep, mix_key<W>(raw));
+            mk = ukb[ub + i];
+            isk = keep_lookup<W>(keep, a.n_keep, mk);
           }
           if (!isk) {
             const uint32_t d0 = (uint32_t)((uint64_t)__double_as_longlong(weight2(v)) >> 52);
@@ -224,9 +224,9 @@ __global__ __launch_bounds__(256) void k_sel_pass1(Sel2Args a) {
             } else if (d0 == D0) {
               cand = true;
               if (lvl1) {
-                if (!a.n_keep) raw = ukb[ub + i];
+                if (!a.n_keep) mk = ukb[ub + i];
                 uint64_t c[NW];
-                composite<W>(v, raw, c);
+                composite<W>(v, unmix_key<W>(mk), c);
                 atomicAdd(&hrep[comp_digit<W>(c, 1)], 1u);
               }
             }
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void k_sel_narrow(Sel2Args a) {
         take = true;
         if (l1) {
           uint64_t c[NW];
-          composite<W>(a.uc[ui], ukb[ui], c);
+          composite<W>(a.uc[ui], unmix_key<W>(ukb[ui]), c);
           const uint32_t d1 = comp_digit<W>(c, 1);
           take = d1 == D1;
           above += d1 > D1 ? 1u : 0u;
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(1024) void k_sel_finish(Sel2Args a) {
     if ((unsigned long long)i < n) {
       const uint32_t ui = a.listf[i];
       bk = a.listfb[i];
-      composite<W>(a.uc[ui], ukb[ui], c);
+      composite<W>(a.uc[ui], unmix_key<W>(ukb[ui]), c);
     } else {
 #pragma unroll
       for (int q = 0; q < NW; q++) c[q] = 0ull;  // below every entry
@@ -480,11 +480,7 @@ __global__ __launch_bounds__(256) void k_write_out(WriteArgs a, uint32_t nbk) {
             s = true;
           } else {
             bool isk = false;
-            if (a.n_keep) {
-              raw = ukb[ub + i];
-              have_raw = true;
-              isk = keep_lookup<W>(keep, a.n_keep, mix_key<W>(raw));
-            }
+            if (a.n_keep) isk = keep_lookup<W>(keep, a.n_keep, ukb[ub + i]);
             if (isk) {
               s = true;
             } else if (mode == S_THRESHOLD) {
@@ -493,7 +489,7 @@ __global__ __launch_bounds__(256) void k_write_out(WriteArgs a, uint32_t nbk) {
               if (m2 != T[0]) {
                 s = m2 > T[0];
               } else {
-                if (!have_raw) raw = ukb[ub + i];
+                raw = unmix_key<W>(ukb[ub + i]);
                 have_raw = true;
                 uint64_t c[NW];
                 composite<W>(v, raw, c);
@@ -505,7 +501,7 @@ __global__ __launch_bounds__(256) void k_write_out(WriteArgs a, uint32_t nbk) {
       }
       const uint64_t m = __ballot(s);
       if (s) {
-        if (!have_raw) raw = ukb[ub + i];
+        if (!have_raw) raw = unmix_key<W>(ukb[ub + i]);
         const size_t o = (size_t)obase + mbcnt64(m);
 #pragma unroll
         for (int w = 0; w < W; w++) {
