@@ -99,10 +99,16 @@ def run_lanczos_split(args):
     # the same H in reverse order: FP64 with another summation order, which
     # measures how far the truncated recursion itself amplifies rounding noise
     Hr = pk.PauliOp.from_raw(128, H_host.x[::-1], H_host.z[::-1], H_host.coef[::-1])
+    # control: FP64 with H's coefficients perturbed by 2^-24 relative (FP32's
+    # unit roundoff), to separate the recursion's sensitivity to the strings
+    # kept at the cut from the precision split itself
+    rs = np.random.default_rng(11).choice([-1.0, 1.0], size=len(H_host.coef))
+    Hp = pk.PauliOp.from_raw(128, H_host.x, H_host.z, H_host.coef * (1.0 + rs * 2.0 ** -24))
     ws = pk.Workspace(1 << 30)
     res = {}
     for name, dt, Hn in (("f64", pk.PAULI_C128, H), ("f32_kahan", pk.PAULI_C64K, H),
-                         ("f64_reversed_H", pk.PAULI_C128, Hr)):
+                         ("f64_reversed_H", pk.PAULI_C128, Hr),
+                         ("f64_perturbed_H", pk.PAULI_C128, Hp)):
         H = Hn
         O0 = pk.PauliOp.from_host(O0_host, dtype=dt, ws=ws)
         trunc = pk.Trunc(max_strings=M)
@@ -124,9 +130,11 @@ def run_lanczos_split(args):
         res[name] = {"b": bs, "strings": sizes, "seconds": wall, "ms_per_step": 1e3 * wall / len(bs),
                      "pairs_per_s": pairs / wall, "emitted_per_s": emitted / wall}
     b64, b32, b64r = res["f64"]["b"], res["f32_kahan"]["b"], res["f64_reversed_H"]["b"]
-    m = min(len(b64), len(b32), len(b64r))
+    b64p = res["f64_perturbed_H"]["b"]
+    m = min(len(b64), len(b32), len(b64r), len(b64p))
     rel = [abs(b32[k] - b64[k]) / abs(b64[k]) for k in range(m)]
     rel_r = [abs(b64r[k] - b64[k]) / abs(b64[k]) for k in range(m)]
+    rel_p = [abs(b64p[k] - b64[k]) / abs(b64[k]) for k in range(m)]
     full = [k for k in range(m) if res["f64"]["strings"][k] < M]  # steps before the cut binds
     print(json.dumps({"workload": "lanczos precision split: N=128 XXZ(0.5) + 0.3 r_i Z_i, "
                                   "O0 = sum X_i/sqrt(N)", "steps": steps, "max_strings": M,
@@ -134,6 +142,10 @@ def run_lanczos_split(args):
                       "max_b_rel_err_untruncated_steps": max([rel[k] for k in full], default=None),
                       "f64_order_sensitivity": rel_r,
                       "max_f64_order_sensitivity": max(rel_r) if rel_r else None,
+                      "f64_h_perturbation_2m24_sensitivity": rel_p,
+                      "max_f64_h_perturbation_sensitivity": max(rel_p) if rel_p else None,
+                      "max_h_perturbation_sensitivity_untruncated_steps":
+                          max([rel_p[k] for k in full], default=None),
                       **res}), flush=True)
 
 

@@ -18,8 +18,8 @@ namespace pauli {
 constexpr int NBINS_LOG = 14;
 constexpr int NBINS = 1 << NBINS_LOG;   // hash bins of the emit passes
 constexpr int MERGE_CAP = 1984;         // max records of one merge bucket (LDS: two
-                                        // 1024-thread merge blocks per CU at W = 1)
-constexpr int MERGE_THREADS = 1024;
+                                        // merge blocks per CU at W = 1)
+constexpr int MERGE_THREADS = 512;
 constexpr int DIGIT_BITS = 11;          // in-bucket counting-sort digit
 constexpr int NDIGITS = 1 << DIGIT_BITS;
 constexpr int EMIT_THREADS = 512;

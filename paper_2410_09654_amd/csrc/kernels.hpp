@@ -491,7 +491,7 @@ DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, in
 
 template <int W, bool F32>
 __global__ __launch_bounds__(MERGE_THREADS)
-__attribute__((amdgpu_waves_per_eu(W == 1 ? 8 : 4))) void k_merge(MergeArgs a) {
+__attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   using V = RecV<F32>;
   constexpr int PER = (MERGE_CAP + MERGE_THREADS - 1) / MERGE_THREADS;
   constexpr int DPT = NDIGITS / MERGE_THREADS;
