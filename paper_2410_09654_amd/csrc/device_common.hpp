@@ -22,11 +22,11 @@ constexpr int MERGE_CAP = 1984;         // max records of one merge bucket (LDS:
 constexpr int MERGE_THREADS = 512;
 constexpr int DIGIT_BITS = 11;          // in-bucket counting-sort digit
 constexpr int NDIGITS = 1 << DIGIT_BITS;
-constexpr int EMIT_THREADS = 512;
+constexpr int EMIT_THREADS = 1024;
 constexpr int SEL0_BINS = 2048;         // exponent bins of |c|^2
 constexpr int SEL_BINS = 4096;          // 12-bit digits of later select levels
 constexpr int FINISH_CAP = 2048;
-constexpr int HREP = 64;                // replicas of the select histograms
+constexpr int HREP = 16;                // replicas of the select histograms
                                         // (blocks add into replica blockIdx % HREP)
 constexpr uint32_t GROUP_SHIFT = 28;    // record source id = group << 28 | index
 

@@ -367,7 +367,10 @@ int Engine::run(Call& c) {
     ea.pass_id = pass_id;
     LAUNCH("k_emit_count", (k_emit<W, F32, false>), rows, EMIT_THREADS, ea);
     LAUNCH("k_scan_cols", k_scan_cols, NBINS / 256, 256, counts, rows, bin_total, dctl);
-    LAUNCH("k_scan_bins", k_scan_bins, 1, 1024, bin_total, bin_base, dctl);
+    // the first count pass of a merge sequence also clears the exponent histogram
+    LAUNCH("k_scan_bins", k_scan_bins, 1, 1024, bin_total, bin_base, dctl,
+           pass_id == 0 ? hist0 : (uint32_t*)nullptr,
+           pass_id == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u);
     return read_ctl();
   };
   TRY(count_pass(0, 0));
@@ -463,7 +466,6 @@ int Engine::run(Call& c) {
     nbk = 0;
     unsigned long long u_off = 0;  // U slots reserved by earlier passes
     npass = 1 << pass_bits;
-    TRY(zero_u32(hist0, (size_t)HREP * SEL0_BINS));
     for (int p = 0; p < npass; p++) {
       if (pass_bits) TRY(count_pass(pass_bits, (uint32_t)p));
       const unsigned long long pe = hctl->pe_total;
@@ -574,7 +576,6 @@ int Engine::run(Call& c) {
     s2.listf = cand[0];
     s2.listfb = cand[2];
     s2.hist1 = histL[1];
-    LAUNCH("k_hist_reduce", k_hist_reduce, SEL0_BINS / 256, 256, hist0, SEL0_BINS, hsum);
   }
   PlanArgs pa;
   memset(&pa, 0, sizeof(pa));
@@ -585,14 +586,13 @@ int Engine::run(Call& c) {
   pa.nbk = nbk;
   pa.want_select = want_select ? 1 : 0;
   pa.max_strings = want_select ? (long long)tr->max_strings : 0;
-  pa.hsum0 = hsum;
+  pa.hist0 = hist0;
+  pa.hist1 = want_select ? histL[1] : nullptr;
   pa.ctl = dctl;
   LAUNCH("k_sel_plan", k_sel_plan, 1, 1024, pa);
   if (want_select) {
-    TRY(zero_u32(histL[1], (size_t)HREP * SEL_BINS));
     LAUNCH("k_sel_pass1", (k_sel_pass1<W>), nchunk, 256, s2);
-    LAUNCH("k_hist_reduce", k_hist_reduce, SEL_BINS / 256, 256, histL[1], SEL_BINS, hsum);
-    LAUNCH("k_sel_pick1", k_sel_pick1, 1, 1024, hsum, dctl);
+    LAUNCH("k_sel_pick1", k_sel_pick1, 1, 1024, histL[1], dctl);
     LAUNCH("k_sel_narrow", (k_sel_narrow<W>), nchunk, 256, s2);
     LAUNCH("k_sel_finish", (k_sel_finish<W>), 1, 1024, s2);
   }

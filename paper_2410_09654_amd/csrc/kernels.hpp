@@ -307,21 +307,29 @@ __global__ void k_scan_cols(uint32_t* counts, int rows, uint32_t* bin_total, Ctl
   bin_total[b] = (uint32_t)run;
 }
 
-// Exclusive scan of the bin totals (one block of 1024 threads, NBINS/1024 bins each)
-// and the largest total over aligned groups of 1, 2, 4, 8, 16 bins.
+// Exclusive scan of the bin totals (one block of 1024 threads, NBINS/1024
+// bins each, staged through LDS for coalesced loads and stores) and the
+// largest total over aligned groups of 1, 2, 4, 8, 16 bins.  Also clears
+// `zero` (nzero words) when given: the exponent histogram of the merges that
+// follow this count pass.
 __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, uint32_t* bin_base,
-                                                    Ctl* ctl) {
-  __shared__ unsigned long long tmp[1024 / 64 + 1];
-  __shared__ unsigned int gmax[5];
+                                                    Ctl* ctl, uint32_t* zero, uint32_t nzero) {
   constexpr int BPT = NBINS / 1024;
   static_assert(BPT >= 16 && BPT * 1024 == NBINS, "k_scan_bins covers NBINS with 1024 threads");
+  __shared__ uint32_t tile[NBINS];
+  __shared__ unsigned long long tmp[1024 / 64 + 1];
+  __shared__ unsigned int gmax[5];
   const int t = threadIdx.x;
   if (t < 5) gmax[t] = 0;
+  for (uint32_t i = t; i < nzero; i += 1024) zero[i] = 0u;
+#pragma unroll
+  for (int k = 0; k < BPT; k++) tile[k * 1024 + t] = bin_total[k * 1024 + t];
+  __syncthreads();
   uint32_t v[BPT];
   unsigned long long s = 0;
 #pragma unroll
   for (int k = 0; k < BPT; k++) {
-    v[k] = bin_total[t * BPT + k];
+    v[k] = tile[t * BPT + k];
     s += v[k];
   }
   unsigned int lm[5];
@@ -346,29 +354,29 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   }
   if (lane == 63) tmp[wv] = x;
   __syncthreads();
-  if (t == 0) {
-    unsigned long long run = 0;
-    for (int i = 0; i < 16; i++) {
-      unsigned long long q = tmp[i];
-      tmp[i] = run;
-      run += q;
-    }
-    tmp[16] = run;
+  unsigned long long w = lane < 16 ? tmp[lane] : 0ull;
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) {
+    unsigned long long y = __shfl_up(w, d, 64);
+    if (lane >= d) w += y;
   }
-  __syncthreads();
+  const unsigned long long before = wv > 0 ? __shfl(w, wv - 1, 64) : 0ull;
+  const unsigned long long total = __shfl(w, 15, 64);
 #pragma unroll
   for (int lg = 0; lg < 5; lg++) atomicMax(&gmax[lg], lm[lg]);
-  unsigned long long pre = tmp[wv] + x - s;
+  unsigned long long pre = before + x - s;
 #pragma unroll
   for (int k = 0; k < BPT; k++) {
-    bin_base[t * BPT + k] = (uint32_t)pre;
+    tile[t * BPT + k] = (uint32_t)pre;
     pre += v[k];
   }
   __syncthreads();
+#pragma unroll
+  for (int k = 0; k < BPT; k++) bin_base[k * 1024 + t] = tile[k * 1024 + t];
   if (t == 0) {
-    bin_base[NBINS] = (uint32_t)tmp[16];
-    ctl->pe_total = tmp[16];
-    if (tmp[16] > 0xFFFFFFFFull) ctl->overflow |= 2u;
+    bin_base[NBINS] = (uint32_t)total;
+    ctl->pe_total = total;
+    if (total > 0xFFFFFFFFull) ctl->overflow |= 2u;
     for (int lg = 0; lg < 5; lg++) ctl->maxg[lg] = gmax[lg];
   }
 }

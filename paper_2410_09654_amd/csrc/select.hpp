@@ -11,8 +11,7 @@
 // kept strings in bucket order.
 //
 // Flow (one stream, no host synchronisation in between):
-//   k_hist_reduce(hist0)  k_sel_plan  k_fill(hist1)  k_sel_pass1
-//   k_hist_reduce(hist1)  k_sel_pick1  k_sel_narrow  k_sel_finish
+//   k_sel_plan  k_sel_pass1  k_sel_pick1  k_sel_narrow  k_sel_finish
 //   k_scan_out  k_write_out
 // Candidate lists live per bucket in the bucket's own U slot range, so no
 // pass appends through a single global counter except the final list of at
@@ -89,21 +88,39 @@ struct PlanArgs {
   uint32_t nbk;
   int want_select;
   long long max_strings;
-  const uint32_t* hsum0;     // summed exponent histogram (SEL0_BINS)
+  const uint32_t* hist0;     // HREP replicas of the exponent histogram (SEL0_BINS each)
+  uint32_t* hist1;           // digit-1 histogram replicas, cleared here (nullable)
   Ctl* ctl;
 };
 
 // Totals of the per-bucket counters, the select mode, and the exponent bin of
-// the threshold (one block of 1024 threads).
+// the threshold (one block of 1024 threads).  Clears the digit-1 histogram
+// for k_sel_pass1.
 __global__ __launch_bounds__(1024) void k_sel_plan(PlanArgs a) {
   __shared__ unsigned long long red[4][16];
   __shared__ unsigned long long tmp[19];
+  __shared__ uint32_t hs[SEL0_BINS];
   __shared__ unsigned long long s_K;
   __shared__ int s_mode;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  if (a.hist1)
+    for (int i = t; i < HREP * SEL_BINS; i += 1024) a.hist1[i] = 0u;
   unsigned long long v[4] = {0, 0, 0, 0};
-#pragma unroll 4
-  for (uint32_t b = t; b < a.nbk; b += 1024) {
+  // four buckets per thread and step (16-byte loads; the arena aligns the tables)
+  const uint32_t nb4 = a.nbk / 4;
+  for (uint32_t q = t; q < nb4; q += 1024) {
+    const uint4 s0 = reinterpret_cast<const uint4*>(a.b_slots)[q];
+    const uint4 s1 = reinterpret_cast<const uint4*>(a.b_surv)[q];
+    const uint4 s2 = reinterpret_cast<const uint4*>(a.b_keep)[q];
+    v[0] += (unsigned long long)s0.x + s0.y + s0.z + s0.w;
+    v[1] += (unsigned long long)s1.x + s1.y + s1.z + s1.w;
+    v[2] += (unsigned long long)s2.x + s2.y + s2.z + s2.w;
+    if (a.b_unique) {
+      const uint4 s3 = reinterpret_cast<const uint4*>(a.b_unique)[q];
+      v[3] += (unsigned long long)s3.x + s3.y + s3.z + s3.w;
+    }
+  }
+  for (uint32_t b = nb4 * 4 + t; b < a.nbk; b += 1024) {
     v[0] += a.b_slots[b];
     v[1] += a.b_surv[b];
     v[2] += a.b_keep[b];
@@ -143,9 +160,16 @@ __global__ __launch_bounds__(1024) void k_sel_plan(PlanArgs a) {
   }
   __syncthreads();
   if (s_mode != S_THRESHOLD) return;
+  for (int b = t; b < SEL0_BINS; b += 1024) {
+    uint32_t h = 0;
+#pragma unroll
+    for (int r = 0; r < HREP; r++) h += a.hist0[(size_t)r * SEL0_BINS + b];
+    hs[b] = h;
+  }
+  __syncthreads();
   unsigned int d0;
   unsigned long long krem, cnt;
-  pick_bin(a.hsum0, SEL0_BINS, s_K, tmp, &d0, &krem, &cnt);
+  pick_bin(hs, SEL0_BINS, s_K, tmp, &d0, &krem, &cnt);
   if (t == 0) {
     a.ctl->sel_d0 = d0;
     a.ctl->sel_K = krem;
@@ -245,14 +269,22 @@ __global__ __launch_bounds__(256) void k_sel_pass1(Sel2Args a) {
   }
 }
 
-// Digit-1 bin of the threshold (one block), from the summed histogram.
-__global__ __launch_bounds__(1024) void k_sel_pick1(const uint32_t* hsum1, Ctl* ctl) {
+// Digit-1 bin of the threshold (one block), from the HREP histogram replicas.
+__global__ __launch_bounds__(1024) void k_sel_pick1(const uint32_t* hist1, Ctl* ctl) {
   __shared__ unsigned long long tmp[19];
+  __shared__ uint32_t hs[SEL_BINS];
   if (ctl->sel_mode != S_THRESHOLD || ctl->fin_level != 1u) return;
   const unsigned long long K = ctl->sel_K;
+  for (int b = threadIdx.x; b < SEL_BINS; b += 1024) {
+    uint32_t h = 0;
+#pragma unroll
+    for (int r = 0; r < HREP; r++) h += hist1[(size_t)r * SEL_BINS + b];
+    hs[b] = h;
+  }
+  __syncthreads();
   unsigned int d1;
   unsigned long long krem, cnt;
-  pick_bin(hsum1, SEL_BINS, K, tmp, &d1, &krem, &cnt);
+  pick_bin(hs, SEL_BINS, K, tmp, &d1, &krem, &cnt);
   if (threadIdx.x == 0) {
     ctl->sel_d1 = d1;
     ctl->sel_K = krem;
