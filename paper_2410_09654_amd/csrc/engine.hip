@@ -291,6 +291,9 @@ int Engine::run(Call& c) {
 
   dctl = (Ctl*)ar->take(sizeof(Ctl));
   uint64_t* Hk = comm ? (uint64_t*)ar->take((size_t)c.H.n * KB) : nullptr;
+  uint32_t* Hidx = comm ? (uint32_t*)ar->take((size_t)c.H.n * 4) : nullptr;
+  uint32_t* hstart = comm ? (uint32_t*)ar->take((size_t)(64 * W + 2) * 4) : nullptr;
+  int* hspan = comm ? (int*)ar->take(4) : nullptr;
   Key<W>* keep_mk = n_keep ? (Key<W>*)ar->take((size_t)n_keep * KB) : nullptr;
   uint32_t* counts = (uint32_t*)ar->take((size_t)std::max(rows, 1) * NBINS * 4);
   uint32_t* bin_total = (uint32_t*)ar->take(NBINS * 4);
@@ -323,8 +326,8 @@ int Engine::run(Call& c) {
     return write_empty();
   }
   if (comm) {
-    LAUNCH("k_pack_keys", (k_pack_keys<W>), (c.H.n + 255) / 256, 256, c.H.x, c.H.z, c.H.cap,
-           c.H.n, Hk);
+    LAUNCH("k_prep_h", (k_prep_h<W>), 1, 1024, c.H.x, c.H.z, c.H.cap, (int)c.H.n, Hk, Hidx,
+           hstart, hspan);
   }
   if (n_keep) {
     LAUNCH("k_mix_keys", (k_mix_keys<W>), (n_keep + 255) / 256, 256, keep->x, keep->z,
@@ -334,6 +337,9 @@ int Engine::run(Call& c) {
   EmitArgs ea;
   memset(&ea, 0, sizeof(ea));
   ea.Hk = Hk;
+  ea.Hidx = Hidx;
+  ea.hstart = hstart;
+  ea.hspan = hspan;
   ea.Hc = comm ? (const double2*)c.H.c : nullptr;
   ea.nH = comm ? (int)c.H.n : 0;
   ea.has_comm = comm ? 1 : 0;

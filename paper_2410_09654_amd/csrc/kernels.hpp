@@ -58,8 +58,14 @@ struct Ctl {
 };
 
 struct EmitArgs {
-  // commutator group: H packed [nH][2W] raw words, O word-major
+  // commutator group: H packed [nH][2W] raw words in ascending order of their
+  // lowest site (k_prep_h), with each entry's index in the caller's H and the
+  // first entry whose lowest site is >= s (hstart[s], s = 0 .. 64W + 1);
+  // O word-major
   const uint64_t* Hk;
+  const uint32_t* Hidx;
+  const uint32_t* hstart;
+  const int* hspan;    // largest highest-minus-lowest site over H (device)
   const double2* Hc;
   int nH;
   int has_comm;
@@ -119,7 +125,7 @@ __device__ __forceinline__ uint32_t layout_row(uint32_t b, uint32_t n) {
 }
 
 template <int W, bool F32, bool SCATTER>
-__global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
+__global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_emit(EmitArgs a) {
   using V = RecV<F32>;
   __shared__ uint32_t hist[NBINS];
   __shared__ uint32_t queue[EMIT_THREADS / 64][128];
@@ -159,10 +165,64 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
   };
 
   if (a.has_comm && row < a.comm_rows) {
+    // Each tile of EMIT_THREADS strings is put in ascending order of lowest
+    // site, so a wave holds strings of nearby support and loops only over the
+    // H strings whose sites can overlap its window [wlo, whi].  A pair whose
+    // supports do not overlap commutes, so skipping it changes nothing.
+    constexpr int SITES = 64 * W;
+    __shared__ uint32_t scnt[SITES + 2];
+    __shared__ uint16_t sperm[EMIT_THREADS];
     const V* Oc = reinterpret_cast<const V*>(a.Oc);
     const int64_t ntiles = (a.nO + EMIT_THREADS - 1) / EMIT_THREADS;
     for (int64_t tile = row; tile < ntiles; tile += a.comm_rows) {
-      const int64_t i = tile * EMIT_THREADS + tid;
+      // lowest and highest site of this thread's string (empty or padding
+      // strings sort last, with site SITES)
+      int lo = SITES, hi = -1;
+      {
+        const int64_t i0 = tile * EMIT_THREADS + tid;
+        if (i0 < a.nO) {
+#pragma unroll
+          for (int w = W - 1; w >= 0; w--) {
+            const uint64_t s = a.Ox[(size_t)w * a.Ocap + i0] | a.Oz[(size_t)w * a.Ocap + i0];
+            if (s) {
+              lo = 64 * w + __builtin_ctzll(s);
+              if (hi < 0) hi = 64 * w + 63 - __builtin_clzll(s);
+            }
+          }
+        }
+      }
+      for (int q = tid; q < SITES + 2; q += EMIT_THREADS) scnt[q] = 0u;
+      __syncthreads();
+      const uint32_t rk = atomicAdd(&scnt[lo], 1u);
+      __syncthreads();
+      if (tid < 64) {  // exclusive scan of the SITES + 1 site counts (one wave)
+        constexpr int PERL = (SITES + 1 + 63) / 64;
+        uint32_t c[PERL], sum = 0;
+#pragma unroll
+        for (int q = 0; q < PERL; q++) {
+          const int sidx = tid * PERL + q;
+          c[q] = sidx <= SITES ? scnt[sidx] : 0u;
+          sum += c[q];
+        }
+        uint32_t x = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t y = __shfl_up(x, d, 64);
+          if (tid >= d) x += y;
+        }
+        uint32_t pre = x - sum;
+#pragma unroll
+        for (int q = 0; q < PERL; q++) {
+          const int sidx = tid * PERL + q;
+          if (sidx <= SITES) scnt[sidx] = pre;
+          pre += c[q];
+        }
+      }
+      __syncthreads();
+      sperm[scnt[lo] + rk] = (uint16_t)tid;
+      __syncthreads();
+      const int64_t i = tile * EMIT_THREADS + sperm[tid];
+      __syncthreads();  // scnt / sperm are rewritten by the next tile
       const bool valid = i < a.nO;
       uint64_t xb[W], zb[W];
       V cb;
@@ -173,8 +233,27 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
       }
       if (valid) cb = Oc[i];
       else { cb.x = 0; cb.y = 0; }
+      // the wave's site window
+      int slo = SITES, shi = -1;
+#pragma unroll
+      for (int w = W - 1; w >= 0; w--) {
+        const uint64_t s = xb[w] | zb[w];
+        if (s) {
+          slo = 64 * w + __builtin_ctzll(s);
+          if (shi < 0) shi = 64 * w + 63 - __builtin_clzll(s);
+        }
+      }
+      int wlo = slo, whi = shi;
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        wlo = min(wlo, __shfl_xor(wlo, d, 64));
+        whi = max(whi, __shfl_xor(whi, d, 64));
+      }
+      if (whi < 0) continue;  // nothing but empty strings: all commute
+      const int hfirst = (int)a.hstart[max(wlo - *a.hspan, 0)];
+      const int hend = (int)a.hstart[whi + 1];
 
-      // Handle one queued (lane, H index) pair per lane.
+      // Handle one queued (lane, H position) pair per lane.
       auto process = [&](uint32_t entry, bool active) {
         const int src_lane = (int)(entry & 63u);
         const int h = (int)(entry >> 6);
@@ -204,18 +283,19 @@ __global__ __launch_bounds__(EMIT_THREADS) void k_emit(EmitArgs a) {
         // P_a P_b = i^(pa + pb + 2 pop(z_a & x_b) - pc) P_c; anticommuting
         // pairs contribute 2 i^e h_a c_b to [P_a, P_b] h_a c_b.
         const int e = (pa + pb + 2 * pz - pc) & 3;
-        const double2 hd = a.Hc[h];
+        const uint32_t horig = a.Hidx[h];
+        const double2 hd = a.Hc[horig];
         V hc;
         hc.x = hd.x;
         hc.y = hd.y;
         V prod;
         if constexpr (F32) prod = cmulf(hc, bc);
         else prod = cmul(hc, bc);
-        deposit(c, times_2ie(prod, e), a.comm_group, (uint32_t)h);
+        deposit(c, times_2ie(prod, e), a.comm_group, horig);
       };
 
       uint32_t qn = 0;  // wave-uniform queue fill
-      for (int h = 0; h < a.nH; ++h) {
+      for (int h = hfirst; h < hend; ++h) {
         const uint64_t* hk = a.Hk + (size_t)h * (2 * W);
         uint32_t par = 0;
 #pragma unroll
@@ -1406,16 +1486,67 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
 // ---------------------------------------------------------------------------
 // Small helpers
 // ---------------------------------------------------------------------------
+// H for the commutator emission (one block of 1024 threads, n <= 2047):
+// packed raw words [n][2W] in ascending order of lowest site, the index of
+// each entry in the caller's H, hstart[s] = first entry with lowest site >= s
+// (s = 0 .. 64W + 1; the empty string sorts as site 64W) and the largest
+// highest-minus-lowest site.  The order among entries of one lowest site is
+// not fixed: every entry carries its own index.
 template <int W>
-__global__ void k_pack_keys(const uint64_t* x, const uint64_t* z, int64_t cap, int64_t n,
-                            uint64_t* packed) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+__global__ __launch_bounds__(1024) void k_prep_h(const uint64_t* x, const uint64_t* z, int64_t cap,
+                                                 int n, uint64_t* packed, uint32_t* hidx,
+                                                 uint32_t* hstart, int* hspan) {
+  constexpr int SITES = 64 * W;
+  __shared__ uint32_t cnt[SITES + 2];
+  __shared__ int span;
+  const int t = threadIdx.x;
+  for (int q = t; q < SITES + 2; q += 1024) cnt[q] = 0u;
+  if (t == 0) span = 0;
+  __syncthreads();
+  int lo[2], rk[2];
+  for (int k = 0; k < 2; k++) {
+    const int i = t + k * 1024;
+    lo[k] = SITES;
+    rk[k] = 0;
+    if (i < n) {
+      int hi = -1;
 #pragma unroll
-  for (int w = 0; w < W; w++) {
-    packed[i * 2 * W + w] = x[(size_t)w * cap + i];
-    packed[i * 2 * W + W + w] = z[(size_t)w * cap + i];
+      for (int w = W - 1; w >= 0; w--) {
+        const uint64_t s = x[(size_t)w * cap + i] | z[(size_t)w * cap + i];
+        if (s) {
+          lo[k] = 64 * w + __builtin_ctzll(s);
+          if (hi < 0) hi = 64 * w + 63 - __builtin_clzll(s);
+        }
+      }
+      if (hi >= 0) atomicMax(&span, hi - lo[k]);
+      rk[k] = (int)atomicAdd(&cnt[lo[k]], 1u);
+    }
   }
+  __syncthreads();
+  if (t == 0) {
+    uint32_t run = 0;
+    for (int q = 0; q <= SITES; q++) {
+      const uint32_t c = cnt[q];
+      cnt[q] = run;
+      run += c;
+    }
+    cnt[SITES + 1] = run;
+  }
+  __syncthreads();
+  for (int k = 0; k < 2; k++) {
+    const int i = t + k * 1024;
+    if (i < n) {
+      const int p = (int)cnt[lo[k]] + rk[k];
+#pragma unroll
+      for (int w = 0; w < W; w++) {
+        packed[(size_t)p * 2 * W + w] = x[(size_t)w * cap + i];
+        packed[(size_t)p * 2 * W + W + w] = z[(size_t)w * cap + i];
+      }
+      hidx[p] = (uint32_t)i;
+    }
+  }
+  for (int q = t; q < SITES + 2; q += 1024) hstart[q] = cnt[q];
+  if (t == 0) *hspan = span;
 }
 
 // Mixed keys of a canonical operator; flags a violation of ascending order.
