@@ -16,7 +16,9 @@
 namespace pauli {
 
 constexpr int NBINS_LOG = 14;
-constexpr int NBINS = 1 << NBINS_LOG;   // hash bins of the emit passes
+constexpr int NBINS = 1 << NBINS_LOG;   // hash bins of a call that fits one pass
+constexpr int NBINS_LOG_MP = 15;        // hash bins per pass of a call that needs
+constexpr int NBINS_MP = 1 << NBINS_LOG_MP;  // several (twice the records per pass)
 constexpr int MERGE_CAP = 1984;         // max records of one merge bucket (LDS: two
                                         // merge blocks per CU at W = 1)
 constexpr int MERGE_THREADS = 512;

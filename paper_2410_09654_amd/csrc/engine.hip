@@ -295,9 +295,9 @@ int Engine::run(Call& c) {
   uint32_t* hstart = comm ? (uint32_t*)ar->take((size_t)(64 * W + 2) * 4) : nullptr;
   int* hspan = comm ? (int*)ar->take(4) : nullptr;
   Key<W>* keep_mk = n_keep ? (Key<W>*)ar->take((size_t)n_keep * KB) : nullptr;
-  uint32_t* counts = (uint32_t*)ar->take((size_t)std::max(rows, 1) * NBINS * 4);
-  uint32_t* bin_total = (uint32_t*)ar->take(NBINS * 4);
-  uint32_t* bin_base = (uint32_t*)ar->take((NBINS + 1) * 4);
+  uint32_t* counts = (uint32_t*)ar->take((size_t)std::max(rows, 1) * NBINS_MP * 4);
+  uint32_t* bin_total = (uint32_t*)ar->take(NBINS_MP * 4);
+  uint32_t* bin_base = (uint32_t*)ar->take((NBINS_MP + 1) * 4);
   uint32_t* hist0 = (uint32_t*)ar->take((size_t)HREP * SEL0_BINS * 4);
   uint32_t* histL[2];
   histL[0] = (uint32_t*)ar->take((size_t)HREP * SEL_BINS * 4);
@@ -368,15 +368,27 @@ int Engine::run(Call& c) {
   ea.bin_base = bin_base;
   ea.max_len = (c.mode == M_PLAIN && tr) ? tr->max_len : 0;
 
+  // 2^nbl hash bins per pass: NBINS_LOG while the call fits one pass,
+  // NBINS_LOG_MP (twice the records per pass) when it needs several
+  int nbl = NBINS_LOG;
   auto count_pass = [&](int pass_bits, uint32_t pass_id) -> int {
     ea.pass_bits = pass_bits;
     ea.pass_id = pass_id;
-    LAUNCH("k_emit_count", (k_emit<W, F32, false>), rows, EMIT_THREADS, ea);
-    LAUNCH("k_scan_cols", k_scan_cols, NBINS / 256, 256, counts, rows, bin_total, dctl);
     // the first count pass of a merge sequence also clears the exponent histogram
-    LAUNCH("k_scan_bins", k_scan_bins, 1, 1024, bin_total, bin_base, dctl,
-           pass_id == 0 ? hist0 : (uint32_t*)nullptr,
-           pass_id == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u);
+    uint32_t* zero = pass_id == 0 ? hist0 : (uint32_t*)nullptr;
+    const uint32_t nzero = pass_id == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
+    if (nbl == NBINS_LOG) {
+      LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG>), rows, EMIT_THREADS, ea);
+      LAUNCH("k_scan_cols", k_scan_cols, NBINS / 256, 256, counts, rows, bin_total, dctl, NBINS);
+      LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG>, 1, 1024, bin_total, bin_base, dctl, zero,
+             nzero);
+    } else {
+      LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);
+      LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / 256, 256, counts, rows, bin_total, dctl,
+             NBINS_MP);
+      LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
+             nzero);
+    }
     return read_ctl();
   };
   TRY(count_pass(0, 0));
@@ -392,18 +404,22 @@ int Engine::run(Call& c) {
   // loop with one more pass bit
   int pass_bits = 0;
   {
-    // the count pass measured every bin exactly: one pass when they all fit
+    // the count pass measured every bin exactly: one pass when they all fit;
+    // otherwise twice the bins, whose largest holds about half as many
     unsigned long long mx = hctl->maxg[0];
-    if (mx > (unsigned long long)MERGE_CAP)
+    if (mx > (unsigned long long)MERGE_CAP) {
+      nbl = NBINS_LOG_MP;
+      mx = (mx + 1) / 2;
       while (mx > (unsigned long long)(MERGE_CAP * 3 / 4) && pass_bits < 10) {
         pass_bits++;
         mx = (mx + 1) / 2;
       }
+    }
   }
   constexpr int MAX_PASS_BITS = 12;
   const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
   const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
-  const uint32_t max_buckets = (uint32_t)NBINS << table_bits;
+  const uint32_t max_buckets = (uint32_t)(1u << nbl) << table_bits;
   // ----- records, U, bucket tables, candidate lists -------------------------
   // source ids fold into the key bits implied by the bin unless an index
   // needs more than 11 bits (H above 2047 strings, canonicalisation lists)
@@ -473,7 +489,8 @@ int Engine::run(Call& c) {
     unsigned long long u_off = 0;  // U slots reserved by earlier passes
     npass = 1 << pass_bits;
     for (int p = 0; p < npass; p++) {
-      if (pass_bits) TRY(count_pass(pass_bits, (uint32_t)p));
+      // the first count pass (single pass, NBINS_LOG bins) already counted
+      if (pass_bits || nbl != NBINS_LOG) TRY(count_pass(pass_bits, (uint32_t)p));
       const unsigned long long pe = hctl->pe_total;
       if (hctl->maxg[0] > (unsigned int)MERGE_CAP) {
         if (pass_bits >= table_bits) {
@@ -492,14 +509,18 @@ int Engine::run(Call& c) {
       int g_log = 4;
       while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)MERGE_CAP) g_log--;
       if (pe == 0) continue;
-      LAUNCH("k_emit_scatter", (k_emit<W, F32, true>), rows, EMIT_THREADS, ea);
+      if (nbl == NBINS_LOG)
+        LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG>), rows, EMIT_THREADS, ea);
+      else
+        LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);
       ma.g_log = g_log;
-      ma.digit_shift = pass_bits + NBINS_LOG - g_log;
+      ma.nbins_log = nbl;
+      ma.digit_shift = pass_bits + nbl - g_log;
       ma.pass_bits = pass_bits;
       ma.pass_id = (uint32_t)p;
       ma.u_off = u_off;
       ma.bucket_off = nbk;
-      const uint32_t nb_pass = (uint32_t)(NBINS >> g_log);
+      const uint32_t nb_pass = (uint32_t)((1u << nbl) >> g_log);
       LAUNCH("k_merge", (k_merge<W, F32>), nb_pass, MERGE_THREADS, ma);
       nbk += nb_pass;
       u_off += pe;

@@ -124,24 +124,25 @@ __device__ __forceinline__ uint32_t layout_row(uint32_t b, uint32_t n) {
   return b < n8 ? (b & 7u) * (n8 >> 3) + (b >> 3) : b;
 }
 
-template <int W, bool F32, bool SCATTER>
+template <int W, bool F32, bool SCATTER, int NBL>
 __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_emit(EmitArgs a) {
+  constexpr int NB = 1 << NBL;  // hash bins of this call
   using V = RecV<F32>;
-  __shared__ uint32_t hist[NBINS];
+  __shared__ uint32_t hist[NB];
   __shared__ uint32_t queue[EMIT_THREADS / 64][128];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int row = blockIdx.x;
   const uint32_t lrow = layout_row(blockIdx.x, gridDim.x);
   if (SCATTER) {
-    const uint32_t* crow = a.counts + (size_t)lrow * NBINS;
-    for (int i = tid; i < NBINS; i += EMIT_THREADS) hist[i] = a.bin_base[i] + crow[i];
+    const uint32_t* crow = a.counts + (size_t)lrow * NB;
+    for (int i = tid; i < NB; i += EMIT_THREADS) hist[i] = a.bin_base[i] + crow[i];
   } else {
-    for (int i = tid; i < NBINS; i += EMIT_THREADS) hist[i] = 0u;
+    for (int i = tid; i < NB; i += EMIT_THREADS) hist[i] = 0u;
   }
   __syncthreads();
   Rec<W, F32>* recs = reinterpret_cast<Rec<W, F32>*>(a.recs);
-  const int F = NBINS_LOG + a.pass_bits;
+  const int F = NBL + a.pass_bits;
 
   auto deposit = [&](const Key<W>& raw, V val, uint32_t group, uint32_t index) {
     if (a.max_len > 0 && key_length<W>(raw) > a.max_len) return;
@@ -151,7 +152,7 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
       if ((uint32_t)(top >> (64 - a.pass_bits)) != a.pass_id) return;
       top <<= a.pass_bits;
     }
-    const uint32_t bin = (uint32_t)(top >> (64 - NBINS_LOG));
+    const uint32_t bin = (uint32_t)(top >> (64 - NBL));
     const uint32_t pos = atomicAdd(&hist[bin], 1u);
     if (SCATTER) {
       const uint64_t small = a.wide ? 0ull : (((uint64_t)group << (F - 3)) | index);
@@ -356,29 +357,29 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
   }
   __syncthreads();
   if (!SCATTER) {
-    uint32_t* crow = a.counts + (size_t)lrow * NBINS;
-    for (int i = tid; i < NBINS; i += EMIT_THREADS) crow[i] = hist[i];
+    uint32_t* crow = a.counts + (size_t)lrow * NB;
+    for (int i = tid; i < NB; i += EMIT_THREADS) crow[i] = hist[i];
   }
 }
 
 // Column-wise exclusive prefix of the counts matrix; bin totals.
-__global__ void k_scan_cols(uint32_t* counts, int rows, uint32_t* bin_total, Ctl* ctl) {
+__global__ void k_scan_cols(uint32_t* counts, int rows, uint32_t* bin_total, Ctl* ctl, int nbins) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= NBINS) return;
+  if (b >= nbins) return;
   unsigned long long run = 0;
   int r = 0;
   for (; r + 8 <= rows; r += 8) {
     uint32_t c[8];
 #pragma unroll
-    for (int q = 0; q < 8; q++) c[q] = counts[(size_t)(r + q) * NBINS + b];
+    for (int q = 0; q < 8; q++) c[q] = counts[(size_t)(r + q) * nbins + b];
 #pragma unroll
     for (int q = 0; q < 8; q++) {
-      counts[(size_t)(r + q) * NBINS + b] = (uint32_t)run;
+      counts[(size_t)(r + q) * nbins + b] = (uint32_t)run;
       run += c[q];
     }
   }
   for (; r < rows; ++r) {
-    const size_t idx = (size_t)r * NBINS + b;
+    const size_t idx = (size_t)r * nbins + b;
     const uint32_t c = counts[idx];
     counts[idx] = (uint32_t)run;
     run += c;
@@ -392,11 +393,13 @@ __global__ void k_scan_cols(uint32_t* counts, int rows, uint32_t* bin_total, Ctl
 // largest total over aligned groups of 1, 2, 4, 8, 16 bins.  Also clears
 // `zero` (nzero words) when given: the exponent histogram of the merges that
 // follow this count pass.
+template <int NBL>
 __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, uint32_t* bin_base,
                                                     Ctl* ctl, uint32_t* zero, uint32_t nzero) {
-  constexpr int BPT = NBINS / 1024;
-  static_assert(BPT >= 16 && BPT * 1024 == NBINS, "k_scan_bins covers NBINS with 1024 threads");
-  __shared__ uint32_t tile[NBINS];
+  constexpr int NB = 1 << NBL;
+  constexpr int BPT = NB / 1024;
+  static_assert(BPT >= 16 && BPT * 1024 == NB, "k_scan_bins covers the bins with 1024 threads");
+  __shared__ uint32_t tile[NB];
   __shared__ unsigned long long tmp[1024 / 64 + 1];
   __shared__ unsigned int gmax[5];
   const int t = threadIdx.x;
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
 #pragma unroll
   for (int k = 0; k < BPT; k++) bin_base[k * 1024 + t] = tile[k * 1024 + t];
   if (t == 0) {
-    bin_base[NBINS] = (uint32_t)total;
+    bin_base[NB] = (uint32_t)total;
     ctl->pe_total = total;
     if (total > 0xFFFFFFFFull) ctl->overflow |= 2u;
     for (int lg = 0; lg < 5; lg++) ctl->maxg[lg] = gmax[lg];
@@ -463,6 +466,7 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
 
 struct MergeArgs {
   const uint32_t* bin_base;
+  int nbins_log;  // hash bins of the call: 2^nbins_log per pass
   int g_log;
   int digit_shift;
   int pass_bits;
@@ -637,7 +641,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   __syncthreads();
 
   const Rec<W, F32>* recs = reinterpret_cast<const Rec<W, F32>*>(a.recs);
-  const int F = NBINS_LOG + a.pass_bits;
+  const int F = a.nbins_log + a.pass_bits;
   const uint32_t ibits = (uint32_t)(F - 3);
   uint32_t dig[PER], rnk[PER], rsx[PER];
   Key<W> rkey[PER];
@@ -656,7 +660,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
       const Rec<W, F32> r = recs[pos];
       int kb = 0;
       while (kb + 1 < G && sbb[kb + 1] <= pos) kb++;
-      const uint64_t T = ((uint64_t)a.pass_id << NBINS_LOG) | (uint64_t)((j << a.g_log) + kb);
+      const uint64_t T = ((uint64_t)a.pass_id << a.nbins_log) | (uint64_t)((j << a.g_log) + kb);
       const uint32_t small = (uint32_t)(r.k.w[0] >> (64 - F));
       Key<W> m = r.k;
       m.w[0] = (T << (64 - F)) | (r.k.w[0] & (~0ull >> F));
@@ -826,12 +830,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
     return !is_zero(acc);
   };
 
-  // Sorted positions in rounds of MERGE_THREADS: the lane at the head of a run
-  // folds it, applies the filters (plain mode) and the survivors of a round
-  // are written in order at the running offset.
+  // Head bits of the sorted positions (a position starts a run of equal keys).
   Key<W>* uk = reinterpret_cast<Key<W>*>(a.uk) + ub;
   double2* uc = a.uc + ub;
-  uint32_t base = 0, kc = 0, nzu = 0;
+  uint32_t kc = 0, nzu = 0;
   const uint32_t nround = (n + MERGE_THREADS - 1) / MERGE_THREADS;
   const uint32_t nwords = (n + 63) / 64;
   for (uint32_t r = 0; r < nround; r++) {
@@ -861,51 +863,65 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
     }
     __syncthreads();
   }
-  for (uint32_t r = 0; r < nround; r++) {
-    const uint32_t p = r * MERGE_THREADS + tid;
-    bool surv = false;
-    double2 v = make_double2(0.0, 0.0);
-    Key<W> raw;
+  // Thread t owns the PER consecutive sorted positions [PER t, PER t + PER):
+  // it folds the runs that start there (a run may reach into the next
+  // threads' positions), applies the filters (plain mode), and one block scan
+  // places every survivor in sorted order.
+  static_assert(PER * MERGE_THREADS >= MERGE_CAP, "every position has an owner");
+  double2 fv[PER];
+  uint32_t smask = 0;
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const uint32_t p = tid * PER + k;
+    fv[k] = make_double2(0.0, 0.0);
     if (p < n && ((hmask[p >> 6] >> (p & 63)) & 1ull)) {
-      const Key<W> kp = mk[p];
-      {
-        // end of the run: the next head bit after p (or n)
-        uint32_t q = n;
-        const uint32_t w = p >> 6, bp = p & 63;
-        const uint64_t rest = bp == 63 ? 0ull : (hmask[w] >> (bp + 1));
-        if (rest) {
-          q = p + 1 + (uint32_t)__builtin_ctzll(rest);
-        } else {
-          for (uint32_t ww = w + 1; ww < nwords; ww++)
-            if (hmask[ww]) {
-              q = ww * 64 + (uint32_t)__builtin_ctzll(hmask[ww]);
-              break;
-            }
-        }
-        if (q > n) q = n;
-        if (fold(p, q, v)) {
-          nzu++;
-          raw = kp;  // U keeps order keys; raw strings are restored where needed
-          surv = true;
-          if (a.mode != M_LANCZOS) {
-            // the length cap was applied when the records were emitted
-            if (a.use_eps && !(weight2(v) >= a.eps2)) surv = false;
-            if (surv) {
-              const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, kp) : false;
-              if (isk) kc++;
-              else atomicAdd(&h0[(uint32_t)(__double_as_longlong(weight2(v)) >> 52)], 1u);
-            }
+      // end of the run: the next head bit after p (or n)
+      uint32_t q = n;
+      const uint32_t w = p >> 6, bp = p & 63;
+      const uint64_t rest = bp == 63 ? 0ull : (hmask[w] >> (bp + 1));
+      if (rest) {
+        q = p + 1 + (uint32_t)__builtin_ctzll(rest);
+      } else {
+        for (uint32_t ww = w + 1; ww < nwords; ww++)
+          if (hmask[ww]) {
+            q = ww * 64 + (uint32_t)__builtin_ctzll(hmask[ww]);
+            break;
           }
+      }
+      if (q > n) q = n;
+      double2 v;
+      if (fold(p, q, v)) {
+        nzu++;
+        bool surv = true;
+        if (a.mode != M_LANCZOS) {
+          // the length cap was applied when the records were emitted
+          if (a.use_eps && !(weight2(v) >= a.eps2)) surv = false;
+          if (surv) {
+            const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mk[p]) : false;
+            if (isk) kc++;
+            else atomicAdd(&h0[(uint32_t)(__double_as_longlong(weight2(v)) >> 52)], 1u);
+          }
+        }
+        if (surv) {
+          fv[k] = v;
+          smask |= 1u << k;
         }
       }
     }
+  }
+  uint32_t base;
+  {
     uint32_t tot;
-    const uint32_t pos = block_exclusive_scan(surv ? 1u : 0u, scan_tmp, &tot);
-    if (surv) {
-      uk[base + pos] = raw;
-      uc[base + pos] = v;
-    }
-    base += tot;
+    uint32_t o = block_exclusive_scan((uint32_t)__popc(smask), scan_tmp, &tot);
+    base = tot;
+    // U keeps order keys; raw strings are restored where needed
+#pragma unroll
+    for (int k = 0; k < PER; k++)
+      if ((smask >> k) & 1u) {
+        uk[o] = mk[tid * PER + k];
+        uc[o] = fv[k];
+        o++;
+      }
   }
   uint32_t tot_pk;  // kc and nzu are <= MERGE_CAP: one scan of the packed pair
   (void)block_exclusive_scan((kc << 16) | nzu, scan_tmp, &tot_pk);
