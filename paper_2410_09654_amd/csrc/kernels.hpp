@@ -537,7 +537,7 @@ DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, in
   constexpr int PER = (MERGE_CAP + MERGE_THREADS - 1) / MERGE_THREADS;
   Key<W> k[PER];
   uint32_t x[PER], pos[PER];
-  RecV<F32> v[PER];
+  typename std::conditional<F32, float, double>::type vx[PER], vy[PER];
 #pragma unroll
   for (int q = 0; q < PER; q++) {
     const uint32_t p = threadIdx.x + q * MERGE_THREADS;
@@ -545,7 +545,8 @@ DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, in
     if (p < n) {
       k[q] = mk[p];
       x[q] = sx[p];
-      v[q] = sv[p];
+      vx[q] = sv[p].x;
+      vy[q] = sv[p].y;
       const uint32_t d = (uint32_t)(key_window<W>(k[q], shift) >> 32);
       // digit group [s0, s1): binary searches on the (ascending) digits
       uint32_t lo = 0, hi = p;
@@ -575,7 +576,8 @@ DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, in
     if (p < n) {
       mk[pos[q]] = k[q];
       sx[pos[q]] = x[q];
-      sv[pos[q]] = v[q];
+      sv[pos[q]].x = vx[q];
+      sv[pos[q]].y = vy[q];
     }
   }
   __syncthreads();
@@ -644,6 +646,9 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   const int F = a.nbins_log + a.pass_bits;
   const uint32_t ibits = (uint32_t)(F - 3);
   uint32_t dig[PER], rnk[PER], rsx[PER];
+  // record values (as plain components, so they stay in registers), kept
+  // until they are written in sorted order
+  typename std::conditional<F32, float, double>::type rvx[PER], rvy[PER];
   Key<W> rkey[PER];
   // sort word of record k (recomputed where needed to spare registers)
   auto sort_word = [&](int k) -> uint64_t {
@@ -658,6 +663,8 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
     if (i < n) {
       const uint32_t pos = b0 + i;
       const Rec<W, F32> r = recs[pos];
+      rvx[k] = r.v.x;
+      rvy[k] = r.v.y;
       int kb = 0;
       while (kb + 1 < G && sbb[kb + 1] <= pos) kb++;
       const uint64_t T = ((uint64_t)a.pass_id << a.nbins_log) | (uint64_t)((j << a.g_log) + kb);
@@ -735,7 +742,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
     if (i < n) {
       mk[fpos[k]] = rkey[k];
       sx[fpos[k]] = rsx[k];
-      sv[fpos[k]] = recs[b0 + i].v;  // second read of the record, from cache
+      V vk;
+      vk.x = rvx[k];
+      vk.y = rvy[k];
+      sv[fpos[k]] = vk;
     }
   }
   __syncthreads();
