@@ -352,43 +352,44 @@ def test_sort_bit_collisions(pk, ws, n, seed):
     assert_same_operator(got, want, rtol=0.0, what="collisions add")
 
 
-def _top_m_reference(x, z, c, M):
-    """Indices of the top M strings by |c|^2 = fl(re^2) + fl(im^2), ties by the
-    smaller key (x, then z, unsigned): the truncation rule."""
-    m2 = c.real * c.real + c.imag * c.imag
-    kth = np.partition(m2, len(m2) - M)[len(m2) - M]
-    above = np.nonzero(m2 > kth)[0]
-    tied = np.nonzero(m2 == kth)[0]
-    tied = tied[np.lexsort((z[tied], x[tied]))][:M - len(above)]
-    return np.concatenate([above, tied])
-
-
-@pytest.mark.parametrize("count", [34_000_000, 50_000_000])
-def test_multi_pass_truncate(pk, count):
+@pytest.mark.parametrize("n,count", [(64, 34_000_000), (64, 50_000_000), (128, 52_000_000)])
+def test_multi_pass_truncate(pk, n, count):
     """More records than one pass of hash bins holds: the engine switches to
-    the larger bin count and, at 50 M, to two hash-range passes.  Every string
-    must be merged exactly once and the top 2^20 must equal the reference."""
+    the larger bin count and, at 50 M and more, to several hash-range passes.
+    Every string must be merged exactly once and the top 2^20 must equal the
+    reference."""
     import torch
-    say(f"multi-pass truncate count={count}")
-    rng = np.random.default_rng(count % 1000)
-    x = rng.integers(0, 2**63, size=count, dtype=np.uint64) * np.uint64(2) + \
-        rng.integers(0, 2, size=count, dtype=np.uint64)
-    z = rng.integers(0, 2**63, size=count, dtype=np.uint64) * np.uint64(2) + \
-        rng.integers(0, 2, size=count, dtype=np.uint64)
+    say(f"multi-pass truncate n={n} count={count}")
+    rng = np.random.default_rng(count % 1000 + n)
+    W = n // 64
+
+    def words():
+        return (rng.integers(0, 2**63, size=(count, W), dtype=np.uint64) * np.uint64(2) +
+                rng.integers(0, 2, size=(count, W), dtype=np.uint64))
+    x, z = words(), words()
     c = rng.standard_normal(count) + 1j * rng.standard_normal(count)
-    O = pk.PauliOp.from_raw(64, x.reshape(count, 1), z.reshape(count, 1), c)
+    O = pk.PauliOp.from_raw(n, x, z, c)
     M = 1 << 20
     ws = pk.Workspace(1 << 30)
     got = pk.truncate(O, pk.Trunc(max_strings=M), ws=ws)
     st = pk.last_stats()
     assert st["emitted"] == count and st["unique"] == count, st
+    assert st["passes"] >= (2 if count > 49_000_000 else 1)
     assert got.size == M
-    sel = _top_m_reference(x, z, c, M)
+    # key order for ties: x words from high to low, then z words from high to low
+    cols = [x[:, w] for w in range(W - 1, -1, -1)] + [z[:, w] for w in range(W - 1, -1, -1)]
+    m2 = c.real * c.real + c.imag * c.imag
+    kth = np.partition(m2, count - M)[count - M]
+    above = np.nonzero(m2 > kth)[0]
+    tied = np.nonzero(m2 == kth)[0]
+    tied = tied[np.lexsort([col[tied] for col in cols[::-1]])][:M - len(above)]
+    sel = np.concatenate([above, tied])
     h = got.to_host()
-    gx, gz = h.x[:, 0], h.z[:, 0]
-    go = np.lexsort((gz, gx))
-    ro = sel[np.lexsort((z[sel], x[sel]))]
-    assert np.array_equal(gx[go], x[ro]) and np.array_equal(gz[go], z[ro])
+    hcols = [h.x[:, w] for w in range(W - 1, -1, -1)] + [h.z[:, w] for w in range(W - 1, -1, -1)]
+    go = np.lexsort(hcols[::-1])
+    ro = sel[np.lexsort([col[sel] for col in cols[::-1]])]
+    for a, b in zip(hcols, cols):
+        assert np.array_equal(a[go], b[ro])
     assert np.array_equal(h.coef[go], c[ro])
     k = pk.order_keys(got).cpu().numpy().view(np.uint64)
     assert (np.lexsort(k.T[::-1]) == np.arange(len(k))).all()
