@@ -295,7 +295,8 @@ int Engine::run(Call& c) {
   uint32_t* hstart = comm ? (uint32_t*)ar->take((size_t)(64 * W + 2) * 4) : nullptr;
   int* hspan = comm ? (int*)ar->take(4) : nullptr;
   Key<W>* keep_mk = n_keep ? (Key<W>*)ar->take((size_t)n_keep * KB) : nullptr;
-  uint32_t* counts = (uint32_t*)ar->take((size_t)std::max(rows, 1) * NBINS_MP * 4);
+  // rows of the emission, or of the partition binning (256 blocks)
+  uint32_t* counts = (uint32_t*)ar->take((size_t)std::max(rows, 256) * NBINS_MP * 4);
   uint32_t* bin_total = (uint32_t*)ar->take(NBINS_MP * 4);
   uint32_t* bin_base = (uint32_t*)ar->take((NBINS_MP + 1) * 4);
   uint32_t* hist0 = (uint32_t*)ar->take((size_t)HREP * SEL0_BINS * 4);
@@ -427,6 +428,14 @@ int Engine::run(Call& c) {
   for (int t = 0; t < c.n_terms; t++) wide = wide || c.tlist[t];
   void* recs = ar->take(ptot * RB);
   uint32_t* rsrc_wide = wide ? (uint32_t*)ar->take(ptot * 4) : nullptr;
+  // several passes: every record is emitted once into 2^pass_bits partitions
+  // (full order keys, source ids aside); each pass bins one partition
+  constexpr int PART_NBL = 12;  // at most 2^12 partitions (MAX_PASS_BITS)
+  constexpr int SPLIT_ROWS = 256;  // blocks binning one partition
+  const bool partitioned = nbl == NBINS_LOG_MP;
+  void* precs = partitioned ? ar->take(ptot * RB) : nullptr;
+  uint32_t* psrc = partitioned ? (uint32_t*)ar->take(ptot * 4) : nullptr;
+  uint32_t* pbase = partitioned ? (uint32_t*)ar->take(((1u << PART_NBL) + 1) * 4) : nullptr;
   void* uk = ar->take(ptot * KB);
   double2* uc = (double2*)ar->take(ptot * sizeof(double2));
   uint32_t* b_ubase = (uint32_t*)ar->take((size_t)max_buckets * 4);
@@ -488,9 +497,51 @@ int Engine::run(Call& c) {
     nbk = 0;
     unsigned long long u_off = 0;  // U slots reserved by earlier passes
     npass = 1 << pass_bits;
+    SplitArgs sp;
+    memset(&sp, 0, sizeof(sp));
+    if (pass_bits > 0) {
+      // emit every record once, into the partitions of its top pass_bits bits
+      ea.part = 1;
+      ea.pass_bits = pass_bits;
+      ea.pass_id = 0;
+      ea.recs = precs;
+      ea.psrc = psrc;
+      ea.bin_base = pbase;
+      LAUNCH("k_emit_part_count", (k_emit<W, F32, false, PART_NBL>), rows, EMIT_THREADS, ea);
+      LAUNCH("k_scan_cols", k_scan_cols, (1 << PART_NBL) / 256, 256, counts, rows, bin_total, dctl,
+             1 << PART_NBL);
+      LAUNCH("k_scan_part", k_scan_part, 1, 1024, bin_total, npass, pbase, (1 << PART_NBL) + 1,
+             dctl);
+      LAUNCH("k_emit_part_scatter", (k_emit<W, F32, true, PART_NBL>), rows, EMIT_THREADS, ea);
+      ea.part = 0;
+      ea.recs = recs;
+      ea.bin_base = bin_base;
+      sp.precs = precs;
+      sp.psrc = psrc;
+      sp.pbase = pbase;
+      sp.pass_bits = pass_bits;
+      sp.wide = wide ? 1 : 0;
+      sp.counts = counts;
+      sp.bin_base = bin_base;
+      sp.recs = recs;
+      sp.rsrc_wide = rsrc_wide;
+    }
     for (int p = 0; p < npass; p++) {
-      // the first count pass (single pass, NBINS_LOG bins) already counted
-      if (pass_bits || nbl != NBINS_LOG) TRY(count_pass(pass_bits, (uint32_t)p));
+      if (pass_bits > 0) {
+        // bin partition p: histogram, scans (and the host check below)
+        sp.part = (uint32_t)p;
+        uint32_t* zero = p == 0 ? hist0 : (uint32_t*)nullptr;
+        const uint32_t nzero = p == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
+        LAUNCH("k_split_count", (k_split<W, F32, false, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
+        LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / 256, 256, counts, SPLIT_ROWS, bin_total,
+               dctl, NBINS_MP);
+        LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
+               nzero);
+        TRY(read_ctl());
+      } else if (nbl != NBINS_LOG) {
+        // one pass at NBINS_LOG_MP bins: count again at that bin count
+        TRY(count_pass(pass_bits, (uint32_t)p));
+      }
       const unsigned long long pe = hctl->pe_total;
       if (hctl->maxg[0] > (unsigned int)MERGE_CAP) {
         if (pass_bits >= table_bits) {
@@ -509,7 +560,9 @@ int Engine::run(Call& c) {
       int g_log = 4;
       while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)MERGE_CAP) g_log--;
       if (pe == 0) continue;
-      if (nbl == NBINS_LOG)
+      if (pass_bits > 0)
+        LAUNCH("k_split_scatter", (k_split<W, F32, true, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
+      else if (nbl == NBINS_LOG)
         LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG>), rows, EMIT_THREADS, ea);
       else
         LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);

@@ -90,6 +90,11 @@ struct EmitArgs {
   // strings longer than this are not emitted (plain mode; 0: no cap): the
   // length cap depends on the key alone, so it can act before the merge
   int max_len;
+  // partition mode: the bin is the top pass_bits bits of the order key
+  // (2^pass_bits partitions), records keep their full order key and the
+  // source ids go to psrc
+  int part;
+  uint32_t* psrc;
   // binning
   int pass_bits;
   uint32_t pass_id;
@@ -147,6 +152,18 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
   auto deposit = [&](const Key<W>& raw, V val, uint32_t group, uint32_t index) {
     if (a.max_len > 0 && key_length<W>(raw) > a.max_len) return;
     Key<W> mk = mix_key<W>(raw);
+    if (a.part) {
+      const uint32_t pid = (uint32_t)(mk.w[0] >> (64 - a.pass_bits));
+      const uint32_t pos = atomicAdd(&hist[pid], 1u);
+      if (SCATTER) {
+        Rec<W, F32> r;
+        r.k = mk;
+        r.v = val;
+        recs[pos] = r;
+        a.psrc[pos] = (group << GROUP_SHIFT) | index;
+      }
+      return;
+    }
     uint64_t top = mk.w[0];
     if (a.pass_bits) {
       if ((uint32_t)(top >> (64 - a.pass_bits)) != a.pass_id) return;
@@ -360,6 +377,95 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
     uint32_t* crow = a.counts + (size_t)lrow * NB;
     for (int i = tid; i < NB; i += EMIT_THREADS) crow[i] = hist[i];
   }
+}
+
+// One partition of a several-pass call, binned for the merge: block r of the
+// grid takes the r-th contiguous share of partition `part` (records with
+// full order keys from the partition-mode emission), histograms the NBL key
+// bits after the pass bits (COUNT: into row r of the counts matrix) or writes
+// each record at its bin cursor with the source id folded into the key bits
+// the bin and pass imply (SCATTER), exactly as the emission's scatter does.
+struct SplitArgs {
+  const void* precs;
+  const uint32_t* psrc;
+  const uint32_t* pbase;  // partition starts [2^pass_bits + 1]
+  uint32_t part;
+  int pass_bits;
+  int wide;
+  uint32_t* counts;        // [gridDim.x][2^NBL]
+  const uint32_t* bin_base;
+  void* recs;
+  uint32_t* rsrc_wide;
+};
+
+template <int W, bool F32, bool SCATTER, int NBL>
+__global__ __launch_bounds__(1024) void k_split(SplitArgs a) {
+  constexpr int NB = 1 << NBL;
+  __shared__ uint32_t hist[NB];
+  const int tid = threadIdx.x;
+  const uint32_t* crow = a.counts + (size_t)blockIdx.x * NB;
+  if (SCATTER)
+    for (int i = tid; i < NB; i += 1024) hist[i] = a.bin_base[i] + crow[i];
+  else
+    for (int i = tid; i < NB; i += 1024) hist[i] = 0u;
+  __syncthreads();
+  const uint32_t lo = a.pbase[a.part], n = a.pbase[a.part + 1] - lo;
+  const uint32_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const uint32_t r0 = lo + min(n, blockIdx.x * chunk);
+  const uint32_t r1 = lo + min(n, (blockIdx.x + 1) * chunk);
+  // records moved as 64-bit words (word 0 is the key's leading word)
+  constexpr int RW = (int)(sizeof(Rec<W, F32>) / 8);
+  static_assert(sizeof(Rec<W, F32>) % 8 == 0, "records are whole 64-bit words");
+  const uint64_t* in = reinterpret_cast<const uint64_t*>(a.precs);
+  uint64_t* out = reinterpret_cast<uint64_t*>(a.recs);
+  const int F = NBL + a.pass_bits;
+  for (uint32_t i = r0 + tid; i < r1; i += 1024) {
+    uint64_t rw[RW];
+#pragma unroll
+    for (int q = 0; q < RW; q++) rw[q] = in[(size_t)i * RW + q];
+    const uint32_t bin = (uint32_t)((rw[0] << a.pass_bits) >> (64 - NBL));
+    const uint32_t pos = atomicAdd(&hist[bin], 1u);
+    if (SCATTER) {
+      const uint32_t src = a.psrc[i];
+      const uint64_t small =
+          a.wide ? 0ull
+                 : (((uint64_t)(src >> GROUP_SHIFT) << (F - 3)) | (src & ((1u << GROUP_SHIFT) - 1u)));
+      rw[0] = (small << (64 - F)) | (rw[0] & (~0ull >> F));
+#pragma unroll
+      for (int q = 0; q < RW; q++) out[(size_t)pos * RW + q] = rw[q];
+      if (a.wide) a.rsrc_wide[pos] = src;
+    }
+  }
+  if (!SCATTER) {
+    __syncthreads();
+    uint32_t* w = a.counts + (size_t)blockIdx.x * NB;
+    for (int i = tid; i < NB; i += 1024) w[i] = hist[i];
+  }
+}
+
+// Exclusive scan of the partition totals (one block of 1024 threads, at most
+// 4096 partitions): pbase[p] for p < np, pbase[p] = total beyond.
+__global__ __launch_bounds__(1024) void k_scan_part(const uint32_t* total, int np, uint32_t* pbase,
+                                                    int nbase, Ctl* ctl) {
+  __shared__ uint32_t scan_tmp[1024 / 64 + 1];
+  const int t = threadIdx.x;
+  uint32_t v[4], s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int p = t * 4 + k;
+    v[k] = p < np ? total[p] : 0u;
+    s += v[k];
+  }
+  uint32_t tot;
+  uint32_t pre = block_exclusive_scan(s, scan_tmp, &tot);
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int p = t * 4 + k;
+    if (p < np) pbase[p] = pre;
+    pre += v[k];
+  }
+  for (int p = np + t; p < nbase; p += 1024) pbase[p] = tot;
+  if (t == 0) ctl->pe_total = tot;
 }
 
 // Column-wise exclusive prefix of the counts matrix; bin totals.
