@@ -21,6 +21,10 @@ constexpr int NBINS_LOG_MP = 15;        // hash bins per pass of a call that nee
 constexpr int NBINS_MP = 1 << NBINS_LOG_MP;  // several (twice the records per pass)
 constexpr int MERGE_CAP = 1984;         // max records of one merge bucket (LDS: two
                                         // merge blocks per CU at W = 1)
+// The bucket capacity per key width: two merge blocks per CU in LDS at
+// W = 2 too (52 bytes per record in FP64).
+template <int W>
+constexpr int merge_cap() { return W == 1 ? MERGE_CAP : 1344; }
 constexpr int MERGE_THREADS = 512;
 constexpr int DIGIT_BITS = 11;          // in-bucket counting-sort digit
 constexpr int NDIGITS = 1 << DIGIT_BITS;

@@ -279,7 +279,7 @@ int Engine::run(Call& c) {
   if (keep && words_of(keep->n_qubits) != W) return PAULI_EINVAL;
 
   // every string's contributions must fit one merge bucket
-  if (comm && c.H.n + c.n_terms + 8 > MERGE_CAP) {
+  if (comm && c.H.n + c.n_terms + 8 > merge_cap<W>()) {
     g_last_error = "H has more strings than one merge bucket holds";
     return PAULI_EINVAL;
   }
@@ -399,7 +399,7 @@ int Engine::run(Call& c) {
     return PAULI_EINTERNAL;
   }
   const unsigned long long pe_all = hctl->pe_total;
-  // passes over disjoint hash ranges keep every bucket within MERGE_CAP; the
+  // passes over disjoint hash ranges keep every bucket within the merge capacity; the
   // largest bin does not always halve with each extra pass bit (all records
   // of one string share a bin), so a pass that still overflows restarts the
   // loop with one more pass bit
@@ -408,10 +408,10 @@ int Engine::run(Call& c) {
     // the count pass measured every bin exactly: one pass when they all fit;
     // otherwise twice the bins, whose largest holds about half as many
     unsigned long long mx = hctl->maxg[0];
-    if (mx > (unsigned long long)MERGE_CAP) {
+    if (mx > (unsigned long long)merge_cap<W>()) {
       nbl = NBINS_LOG_MP;
       mx = (mx + 1) / 2;
-      while (mx > (unsigned long long)(MERGE_CAP * 3 / 4) && pass_bits < 10) {
+      while (mx > (unsigned long long)(merge_cap<W>() * 3 / 4) && pass_bits < 10) {
         pass_bits++;
         mx = (mx + 1) / 2;
       }
@@ -543,7 +543,7 @@ int Engine::run(Call& c) {
         TRY(count_pass(pass_bits, (uint32_t)p));
       }
       const unsigned long long pe = hctl->pe_total;
-      if (hctl->maxg[0] > (unsigned int)MERGE_CAP) {
+      if (hctl->maxg[0] > (unsigned int)merge_cap<W>()) {
         if (pass_bits >= table_bits) {
           char msg[256];
           snprintf(msg, sizeof(msg),
@@ -558,7 +558,7 @@ int Engine::run(Call& c) {
         break;
       }
       int g_log = 4;
-      while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)MERGE_CAP) g_log--;
+      while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)merge_cap<W>()) g_log--;
       if (pe == 0) continue;
       if (pass_bits > 0)
         LAUNCH("k_split_scatter", (k_split<W, F32, true, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);

@@ -640,7 +640,8 @@ DEV uint64_t key_window(const Key<W>& m, int shift) {
 // digit (ascending); on return they are in (key, source id) order.
 template <int W, bool F32>
 DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, int shift) {
-  constexpr int PER = (MERGE_CAP + MERGE_THREADS - 1) / MERGE_THREADS;
+  constexpr int CAP = merge_cap<W>();
+  constexpr int PER = (CAP + MERGE_THREADS - 1) / MERGE_THREADS;
   Key<W> k[PER];
   uint32_t x[PER], pos[PER];
   typename std::conditional<F32, float, double>::type vx[PER], vy[PER];
@@ -693,7 +694,8 @@ template <int W, bool F32>
 __global__ __launch_bounds__(MERGE_THREADS)
 __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   using V = RecV<F32>;
-  constexpr int PER = (MERGE_CAP + MERGE_THREADS - 1) / MERGE_THREADS;
+  constexpr int CAP = merge_cap<W>();
+  constexpr int PER = (CAP + MERGE_THREADS - 1) / MERGE_THREADS;
   constexpr int DPT = NDIGITS / MERGE_THREADS;
   static_assert(SEL0_BINS == NDIGITS, "digit counts and |c|^2 histogram share LDS");
   // Sort: a counting sort on the DIGIT_BITS key bits after the bucket bits,
@@ -704,11 +706,11 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   // exponent histogram of |c|^2.  Two distinct keys of one digit group with
   // equal sort bits show up as adjacent entries with equal windows but
   // different keys; the block then ranks by full keys (merge_full_rank).
-  __shared__ Key<W> mk[MERGE_CAP];
-  __shared__ __align__(16) V sv[MERGE_CAP];
+  __shared__ Key<W> mk[CAP];
+  __shared__ __align__(16) V sv[CAP];
   static_assert(sizeof(V) >= sizeof(uint64_t), "sort words alias the values");
   uint64_t* const swd = reinterpret_cast<uint64_t*>(sv);
-  __shared__ uint32_t sx[MERGE_CAP];
+  __shared__ uint32_t sx[CAP];
   __shared__ int s_collide;
   __shared__ uint32_t dh[NDIGITS];
   uint32_t* const h0 = dh;
@@ -716,7 +718,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   __shared__ int s_gk[MAX_GROUPS], s_ak[MAX_GROUPS];
   __shared__ double2 s_al[MAX_GROUPS];
   __shared__ uint32_t sbb[17];
-  constexpr int NHW = (MERGE_CAP + 63) / 64;
+  constexpr int NHW = (CAP + 63) / 64;
   __shared__ uint64_t hmask[NHW];  // bit p: sorted position p starts a run of equal keys
 
   const int tid = threadIdx.x;
@@ -726,7 +728,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   const uint32_t b1 = a.bin_base[(j + 1) << a.g_log];
   const uint32_t n = b1 - b0;
   const unsigned long long ub = a.u_off + b0;
-  if (n > (uint32_t)MERGE_CAP) {
+  if (n > (uint32_t)CAP) {
     if (tid == 0) {
       atomicOr(&a.ctl->overflow, 1u);
       a.b_ubase[gb] = (uint32_t)ub;
@@ -755,10 +757,17 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   // record values (as plain components, so they stay in registers), kept
   // until they are written in sorted order
   typename std::conditional<F32, float, double>::type rvx[PER], rvy[PER];
-  Key<W> rkey[PER];
+  // the records' order keys as plain words (so they stay in registers)
+  uint64_t rkw[2 * W][PER];
+  auto rkey = [&](int k) -> Key<W> {
+    Key<W> m;
+#pragma unroll
+    for (int q = 0; q < 2 * W; q++) m.w[q] = rkw[q][k];
+    return m;
+  };
   // sort word of record k (recomputed where needed to spare registers)
   auto sort_word = [&](int k) -> uint64_t {
-    return (key_window<W>(rkey[k], a.digit_shift) << 32) | rsx[k];
+    return (key_window<W>(rkey(k), a.digit_shift) << 32) | rsx[k];
   };
 #pragma unroll
   for (int k = 0; k < PER; k++) {
@@ -777,7 +786,8 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
       const uint32_t small = (uint32_t)(r.k.w[0] >> (64 - F));
       Key<W> m = r.k;
       m.w[0] = (T << (64 - F)) | (r.k.w[0] & (~0ull >> F));
-      rkey[k] = m;
+#pragma unroll
+      for (int q = 0; q < 2 * W; q++) rkw[q][k] = m.w[q];
       rsx[k] = a.wide ? a.rsrc_wide[pos]
                       : (((small >> ibits) << GROUP_SHIFT) | (small & ((1u << ibits) - 1u)));
       dig[k] = (uint32_t)(key_window<W>(m, a.digit_shift) >> 32);
@@ -846,7 +856,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
     if (i < n) {
-      mk[fpos[k]] = rkey[k];
+      mk[fpos[k]] = rkey(k);
       sx[fpos[k]] = rsx[k];
       V vk;
       vk.x = rvx[k];
@@ -983,7 +993,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   // it folds the runs that start there (a run may reach into the next
   // threads' positions), applies the filters (plain mode), and one block scan
   // places every survivor in sorted order.
-  static_assert(PER * MERGE_THREADS >= MERGE_CAP, "every position has an owner");
+  static_assert(PER * MERGE_THREADS >= CAP, "every position has an owner");
   double2 fv[PER];
   uint32_t smask = 0;
 #pragma unroll
@@ -1039,7 +1049,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
         o++;
       }
   }
-  uint32_t tot_pk;  // kc and nzu are <= MERGE_CAP: one scan of the packed pair
+  uint32_t tot_pk;  // kc and nzu are <= CAP: one scan of the packed pair
   (void)block_exclusive_scan((kc << 16) | nzu, scan_tmp, &tot_pk);
   const uint32_t tot_kc = tot_pk >> 16, tot_nzu = tot_pk & 0xFFFFu;
   const uint32_t tot_cnt = base;
