@@ -352,14 +352,15 @@ def test_sort_bit_collisions(pk, ws, n, seed):
     assert_same_operator(got, want, rtol=0.0, what="collisions add")
 
 
-@pytest.mark.parametrize("n,count", [(64, 34_000_000), (64, 50_000_000), (128, 52_000_000)])
-def test_multi_pass_truncate(pk, n, count):
+@pytest.mark.parametrize("n,count,f32", [(64, 34_000_000, False), (64, 50_000_000, False),
+                                         (128, 52_000_000, False), (128, 40_000_000, True)])
+def test_multi_pass_truncate(pk, n, count, f32):
     """More records than one pass of hash bins holds: the engine switches to
     the larger bin count and, at 50 M and more, to several hash-range passes.
     Every string must be merged exactly once and the top 2^20 must equal the
     reference."""
     import torch
-    say(f"multi-pass truncate n={n} count={count}")
+    say(f"multi-pass truncate n={n} count={count} f32={f32}")
     rng = np.random.default_rng(count % 1000 + n)
     W = n // 64
 
@@ -368,7 +369,9 @@ def test_multi_pass_truncate(pk, n, count):
                 rng.integers(0, 2, size=(count, W), dtype=np.uint64))
     x, z = words(), words()
     c = rng.standard_normal(count) + 1j * rng.standard_normal(count)
-    O = pk.PauliOp.from_raw(n, x, z, c)
+    if f32:  # FP32 coefficients (PAULI_C64K): |c|^2 from the stored floats
+        c = c.astype(np.complex64).astype(np.complex128)
+    O = pk.PauliOp.from_raw(n, x, z, c, dtype=pk.PAULI_C64K if f32 else pk.PAULI_C128)
     M = 1 << 20
     ws = pk.Workspace(1 << 30)
     got = pk.truncate(O, pk.Trunc(max_strings=M), ws=ws)
