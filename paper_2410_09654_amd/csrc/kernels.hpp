@@ -712,6 +712,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   uint64_t* const swd = reinterpret_cast<uint64_t*>(sv);
   __shared__ uint32_t sx[CAP];
   __shared__ int s_collide;
+  __shared__ uint32_t s_pk;
   __shared__ uint32_t dh[NDIGITS];
   uint32_t* const h0 = dh;
   __shared__ uint32_t scan_tmp[MERGE_THREADS / 64 + 1];
@@ -747,7 +748,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
   }
   const int G = 1 << a.g_log;
   if (tid <= G) sbb[tid] = a.bin_base[(j << a.g_log) + tid];
-  if (tid == 0) s_collide = 0;
+  if (tid == 0) {
+    s_collide = 0;
+    s_pk = 0u;
+  }
   __syncthreads();
 
   const Rec<W, F32>* recs = reinterpret_cast<const Rec<W, F32>*>(a.recs);
@@ -989,18 +993,20 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
     }
     __syncthreads();
   }
-  // Thread t owns the PER consecutive sorted positions [PER t, PER t + PER):
-  // it folds the runs that start there (a run may reach into the next
-  // threads' positions), applies the filters (plain mode), and one block scan
-  // places every survivor in sorted order.
+  // Thread t owns the `per` consecutive sorted positions [per t, per t + per)
+  // (per = ceil(n / threads) <= PER, so the work spreads over all waves): it
+  // folds the runs that start there (a run may reach into the next threads'
+  // positions), applies the filters (plain mode), and one block scan places
+  // every survivor in sorted order.
   static_assert(PER * MERGE_THREADS >= CAP, "every position has an owner");
+  const uint32_t per = (n + MERGE_THREADS - 1) / MERGE_THREADS;
   double2 fv[PER];
   uint32_t smask = 0;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const uint32_t p = tid * PER + k;
+    const uint32_t p = tid * per + k;
     fv[k] = make_double2(0.0, 0.0);
-    if (p < n && ((hmask[p >> 6] >> (p & 63)) & 1ull)) {
+    if ((uint32_t)k < per && p < n && ((hmask[p >> 6] >> (p & 63)) & 1ull)) {
       // end of the run: the next head bit after p (or n)
       uint32_t q = n;
       const uint32_t w = p >> 6, bp = p & 63;
@@ -1035,25 +1041,27 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
       }
     }
   }
-  uint32_t base;
+  // block totals of the keep count and the nonzero count (both <= CAP: one
+  // packed word), added per wave before the scan's barriers
   {
-    uint32_t tot;
-    uint32_t o = block_exclusive_scan((uint32_t)__popc(smask), scan_tmp, &tot);
-    base = tot;
+    uint32_t pk = (kc << 16) | nzu;
+    for (int d = 32; d >= 1; d >>= 1) pk += __shfl_down(pk, d, 64);
+    if ((tid & 63) == 0) atomicAdd(&s_pk, pk);
+  }
+  uint32_t tot_cnt;
+  {
+    uint32_t o = block_exclusive_scan((uint32_t)__popc(smask), scan_tmp, &tot_cnt);
     // U keeps order keys; raw strings are restored where needed
 #pragma unroll
     for (int k = 0; k < PER; k++)
       if ((smask >> k) & 1u) {
-        uk[o] = mk[tid * PER + k];
+        uk[o] = mk[tid * per + k];
         uc[o] = fv[k];
         o++;
       }
   }
-  uint32_t tot_pk;  // kc and nzu are <= CAP: one scan of the packed pair
-  (void)block_exclusive_scan((kc << 16) | nzu, scan_tmp, &tot_pk);
-  const uint32_t tot_kc = tot_pk >> 16, tot_nzu = tot_pk & 0xFFFFu;
-  const uint32_t tot_cnt = base;
-  __syncthreads();
+  // the scan's barriers have ordered every histogram and s_pk update
+  const uint32_t tot_kc = s_pk >> 16, tot_nzu = s_pk & 0xFFFFu;
   if (a.mode == M_PLAIN) {
     uint32_t* hrep = a.hist0 + (size_t)(j % HREP) * SEL0_BINS;
     for (int i = tid; i < SEL0_BINS; i += MERGE_THREADS)
