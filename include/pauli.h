@@ -231,8 +231,12 @@ const char *pauli_last_error(void);
 /* Optional per-kernel timing with HIP events on the caller's stream.
  * pauli_profile_enable(1) clears the log and starts recording;
  * pauli_profile_read fills `buf` with one line per kernel name:
- * "name count total_ms\n" and returns the number of bytes needed. */
+ * "name count total_ms\n" and returns the number of bytes needed.
+ * pauli_profile_only("k_a,k_b") limits the events to the named kernels (each
+ * timed kernel costs two event records on the stream); NULL or "" times every
+ * kernel.  The filter stays until the next pauli_profile_only call. */
 void pauli_profile_enable(int on);
+void pauli_profile_only(const char *names);
 size_t pauli_profile_read(char *buf, size_t len);
 
 #ifdef __cplusplus

@@ -13,7 +13,7 @@ PAULI_C128, PAULI_C64K = 0, 1
 
 EXPORTS = ["pauli_commutator", "pauli_add", "pauli_truncate", "pauli_canonicalize",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
-           "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_read",
+           "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_only", "pauli_profile_read",
            "pauli_last_stats", "pauli_order_keys", "pauli_strings_from_order_keys",
            "pauli_mlp_num_params", "pauli_mlp_sync", "pauli_mlp_forward",
            "pauli_mlp_loss_grad", "pauli_mlp_adam", "pauli_gemm_bf16"]
@@ -75,6 +75,7 @@ def load():
     L.pauli_last_error.argtypes = []
     L.pauli_last_error.restype = ctypes.c_char_p
     L.pauli_profile_enable.argtypes = [ctypes.c_int]
+    L.pauli_profile_only.argtypes = [ctypes.c_char_p]
     L.pauli_profile_read.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
     L.pauli_profile_read.restype = ctypes.c_size_t
     L.pauli_last_stats.argtypes = [P(PauliStatsC)]
@@ -90,7 +91,8 @@ def load():
         if name == "pauli_mlp_num_params":
             L[name].restype = ctypes.c_int64
             continue
-        L[name].restype = None if name == "pauli_profile_enable" else ctypes.c_int
+        L[name].restype = (None if name in ("pauli_profile_enable", "pauli_profile_only")
+                            else ctypes.c_int)
     _lib = L
     return L
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -35,6 +36,7 @@ thread_local pauli_stats g_stats;
 struct Prof {
   std::mutex mu;
   bool on = false;
+  std::set<std::string> only;  // kernel names to time; empty: every kernel
   struct Pending {
     const char* name;
     hipEvent_t a, b;
@@ -77,6 +79,7 @@ struct ProfScope {
   ProfScope(const char* n, hipStream_t st) : name(n), s(st) {
     if (!g_prof.on) return;
     std::lock_guard<std::mutex> g(g_prof.mu);
+    if (!g_prof.only.empty() && !g_prof.only.count(n)) return;
     a = g_prof.get();
     b = g_prof.get();
     if (a) (void)hipEventRecord(a, s);
@@ -905,6 +908,22 @@ void pauli_profile_enable(int on) {
   std::lock_guard<std::mutex> g(g_prof.mu);
   g_prof.on = on != 0;
   g_prof.acc.clear();
+}
+
+void pauli_profile_only(const char* names) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  g_prof.only.clear();
+  if (!names) return;
+  std::string cur;
+  for (const char* q = names;; q++) {
+    if (*q == ',' || *q == 0) {
+      if (!cur.empty()) g_prof.only.insert(cur);
+      cur.clear();
+      if (*q == 0) break;
+    } else {
+      cur += *q;
+    }
+  }
 }
 
 size_t pauli_profile_read(char* buf, size_t len) {

@@ -494,47 +494,60 @@ __global__ void k_scan_cols(uint32_t* counts, int rows, uint32_t* bin_total, Ctl
   bin_total[b] = (uint32_t)run;
 }
 
-// Exclusive scan of the bin totals (one block of 1024 threads, NBINS/1024
-// bins each, staged through LDS for coalesced loads and stores) and the
-// largest total over aligned groups of 1, 2, 4, 8, 16 bins.  Also clears
-// `zero` (nzero words) when given: the exponent histogram of the merges that
-// follow this count pass.
+// Exclusive scan of the bin totals (one block of 1024 threads; thread t owns
+// the NB/1024 consecutive bins from t NB/1024, read and written as 16-byte
+// vectors) and the largest total over aligned groups of 1, 2, 4, 8, 16 bins.
+// Also clears `zero` (nzero words) when given: the exponent histogram of the
+// merges that follow this count pass.
 template <int NBL>
 __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, uint32_t* bin_base,
                                                     Ctl* ctl, uint32_t* zero, uint32_t nzero) {
   constexpr int NB = 1 << NBL;
   constexpr int BPT = NB / 1024;
-  static_assert(BPT >= 16 && BPT * 1024 == NB, "k_scan_bins covers the bins with 1024 threads");
-  __shared__ uint32_t tile[NB];
+  static_assert(BPT >= 16 && BPT * 1024 == NB && BPT % 4 == 0,
+                "k_scan_bins covers the bins with 1024 threads");
   __shared__ unsigned long long tmp[1024 / 64 + 1];
-  __shared__ unsigned int gmax[5];
-  const int t = threadIdx.x;
-  if (t < 5) gmax[t] = 0;
+  __shared__ unsigned int gmax[16][5];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   for (uint32_t i = t; i < nzero; i += 1024) zero[i] = 0u;
-#pragma unroll
-  for (int k = 0; k < BPT; k++) tile[k * 1024 + t] = bin_total[k * 1024 + t];
-  __syncthreads();
   uint32_t v[BPT];
+  const uint4* src = reinterpret_cast<const uint4*>(bin_total) + (size_t)t * (BPT / 4);
+#pragma unroll
+  for (int q = 0; q < BPT / 4; q++) {
+    const uint4 c = src[q];
+    v[4 * q] = c.x;
+    v[4 * q + 1] = c.y;
+    v[4 * q + 2] = c.z;
+    v[4 * q + 3] = c.w;
+  }
   unsigned long long s = 0;
 #pragma unroll
-  for (int k = 0; k < BPT; k++) {
-    v[k] = tile[t * BPT + k];
-    s += v[k];
-  }
+  for (int k = 0; k < BPT; k++) s += v[k];
   unsigned int lm[5];
 #pragma unroll
   for (int lg = 0; lg < 5; lg++) {
     const int g = 1 << lg;
     unsigned int best = 0;
+#pragma unroll
     for (int k = 0; k < BPT; k += g) {
       unsigned long long acc = 0;
+#pragma unroll
       for (int q = 0; q < g; q++) acc += v[k + q];
-      if (acc > best) best = acc > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned int)acc;
+      const unsigned int a = acc > 0xFFFFFFFFull ? 0xFFFFFFFFu : (unsigned int)acc;
+      best = a > best ? a : best;
+    }
+    // wave maximum, then one entry per wave
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const unsigned int o = __shfl_xor(best, d, 64);
+      best = o > best ? o : best;
     }
     lm[lg] = best;
   }
+  if (lane == 0)
+#pragma unroll
+    for (int lg = 0; lg < 5; lg++) gmax[wv][lg] = lm[lg];
   // block exclusive scan (u64)
-  const int lane = t & 63, wv = t >> 6;
   unsigned long long x = s;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -551,22 +564,30 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   }
   const unsigned long long before = wv > 0 ? __shfl(w, wv - 1, 64) : 0ull;
   const unsigned long long total = __shfl(w, 15, 64);
-#pragma unroll
-  for (int lg = 0; lg < 5; lg++) atomicMax(&gmax[lg], lm[lg]);
   unsigned long long pre = before + x - s;
+  uint4* dst = reinterpret_cast<uint4*>(bin_base) + (size_t)t * (BPT / 4);
 #pragma unroll
-  for (int k = 0; k < BPT; k++) {
-    tile[t * BPT + k] = (uint32_t)pre;
-    pre += v[k];
+  for (int q = 0; q < BPT / 4; q++) {
+    uint4 o;
+    o.x = (uint32_t)pre;
+    pre += v[4 * q];
+    o.y = (uint32_t)pre;
+    pre += v[4 * q + 1];
+    o.z = (uint32_t)pre;
+    pre += v[4 * q + 2];
+    o.w = (uint32_t)pre;
+    pre += v[4 * q + 3];
+    dst[q] = o;
   }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < BPT; k++) bin_base[k * 1024 + t] = tile[k * 1024 + t];
   if (t == 0) {
     bin_base[NB] = (uint32_t)total;
     ctl->pe_total = total;
     if (total > 0xFFFFFFFFull) ctl->overflow |= 2u;
-    for (int lg = 0; lg < 5; lg++) ctl->maxg[lg] = gmax[lg];
+    for (int lg = 0; lg < 5; lg++) {
+      unsigned int m = 0;
+      for (int q = 0; q < 16; q++) m = gmax[q][lg] > m ? gmax[q][lg] : m;
+      ctl->maxg[lg] = m;
+    }
   }
 }
 

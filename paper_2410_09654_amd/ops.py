@@ -366,8 +366,13 @@ def strings_from_order_keys(n_qubits: int, keys: torch.Tensor):
 
 # -- kernel timing -------------------------------------------------------------
 
-def profile_enable(on: bool = True):
-    _lib.load().pauli_profile_enable(1 if on else 0)
+def profile_enable(on: bool = True, only=None):
+    """Start (or stop) per-kernel event timing and clear the log.  `only`: the
+    kernel names to time (each costs two event records per launch); None
+    times every kernel."""
+    L = _lib.load()
+    L.pauli_profile_only(",".join(only).encode() if only else None)
+    L.pauli_profile_enable(1 if on else 0)
 
 
 def profile_read() -> dict:
