@@ -25,7 +25,7 @@ constexpr int MERGE_CAP = 1984;         // max records of one merge bucket (LDS:
 // W = 2 too (52 bytes per record in FP64).
 template <int W>
 constexpr int merge_cap() { return W == 1 ? MERGE_CAP : 1344; }
-constexpr int MERGE_THREADS = 512;
+constexpr int MERGE_THREADS = 1024;   // 16 waves; two merge blocks per CU (8 waves/SIMD)
 constexpr int DIGIT_BITS = 11;          // in-bucket counting-sort digit
 constexpr int NDIGITS = 1 << DIGIT_BITS;
 constexpr int EMIT_THREADS = 1024;

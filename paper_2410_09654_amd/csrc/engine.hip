@@ -309,7 +309,8 @@ int Engine::run(Call& c) {
   uint32_t* hsum = (uint32_t*)ar->take(SEL_BINS * 4);
   if (ar->short_) return PAULI_EWORKSPACE;
   TRY(host_ctl(&hctl));
-  TRY(zero_u32(dctl, sizeof(Ctl) / 4));
+  // the control block starts at zero (cleared by k_prep_h when there is one)
+  if (!comm || rows == 0) TRY(zero_u32(dctl, sizeof(Ctl) / 4));
 
   auto write_empty = [&]() -> int {
     if (c.out.to_arena) {
@@ -331,7 +332,7 @@ int Engine::run(Call& c) {
   }
   if (comm) {
     LAUNCH("k_prep_h", (k_prep_h<W>), 1, 1024, c.H.x, c.H.z, c.H.cap, (int)c.H.n, Hk, Hidx,
-           hstart, hspan);
+           hstart, hspan, (uint32_t*)dctl, (uint32_t)(sizeof(Ctl) / 4));
   }
   if (n_keep) {
     LAUNCH("k_mix_keys", (k_mix_keys<W>), (n_keep + 255) / 256, 256, keep->x, keep->z,

@@ -713,7 +713,7 @@ DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, in
 
 template <int W, bool F32>
 __global__ __launch_bounds__(MERGE_THREADS)
-__attribute__((amdgpu_waves_per_eu(4))) void k_merge(MergeArgs a) {
+__attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   using V = RecV<F32>;
   constexpr int CAP = merge_cap<W>();
   constexpr int PER = (CAP + MERGE_THREADS - 1) / MERGE_THREADS;
@@ -1666,11 +1666,14 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
 template <int W>
 __global__ __launch_bounds__(1024) void k_prep_h(const uint64_t* x, const uint64_t* z, int64_t cap,
                                                  int n, uint64_t* packed, uint32_t* hidx,
-                                                 uint32_t* hstart, int* hspan) {
+                                                 uint32_t* hstart, int* hspan, uint32_t* zero,
+                                                 uint32_t nzero) {
   constexpr int SITES = 64 * W;
   __shared__ uint32_t cnt[SITES + 2];
   __shared__ int span;
   const int t = threadIdx.x;
+  // also clears `zero` (nzero words: the call's control block)
+  for (uint32_t q = t; q < nzero; q += 1024) zero[q] = 0u;
   for (int q = t; q < SITES + 2; q += 1024) cnt[q] = 0u;
   if (t == 0) span = 0;
   __syncthreads();

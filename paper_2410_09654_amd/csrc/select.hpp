@@ -248,9 +248,10 @@ __global__ __launch_bounds__(256) void k_sel_pass1(Sel2Args a) {
             } else if (d0 == D0) {
               cand = true;
               if (lvl1) {
-                if (!a.n_keep) mk = ukb[ub + i];
-                uint64_t c[NW];
-                composite<W>(v, unmix_key<W>(mk), c);
+                // digit 1: the 12 bits of |c|^2 after the exponent (the
+                // string words of the composite do not reach it)
+                uint64_t c[NW] = {};
+                c[0] = (uint64_t)__double_as_longlong(weight2(v));
                 atomicAdd(&hrep[comp_digit<W>(c, 1)], 1u);
               }
             }
@@ -303,7 +304,6 @@ __global__ __launch_bounds__(256) void k_sel_narrow(Sel2Args a) {
   if (a.ctl->sel_mode != S_THRESHOLD || a.ctl->deep) return;
   const bool l1 = a.ctl->fin_level == 1u;
   const uint32_t D1 = a.ctl->sel_d1;
-  const Key<W>* ukb = reinterpret_cast<const Key<W>*>(a.uk);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int q = 0; q < SEL_CHUNK / 4; q++) {
     const uint32_t b = blockIdx.x * SEL_CHUNK + q * 4 + wv;
@@ -318,8 +318,10 @@ __global__ __launch_bounds__(256) void k_sel_narrow(Sel2Args a) {
         ui = a.list0[ub + i];
         take = true;
         if (l1) {
-          uint64_t c[NW];
-          composite<W>(a.uc[ui], unmix_key<W>(ukb[ui]), c);
+          // the digit-1 bin holds the 12 bits of |c|^2 after the exponent:
+          // the string words of the composite do not reach it
+          uint64_t c[NW] = {};
+          c[0] = (uint64_t)__double_as_longlong(weight2(a.uc[ui]));
           const uint32_t d1 = comp_digit<W>(c, 1);
           take = d1 == D1;
           above += d1 > D1 ? 1u : 0u;
