@@ -103,11 +103,24 @@ __global__ __launch_bounds__(1024) void k_sel_plan(PlanArgs a) {
   __shared__ unsigned long long s_K;
   __shared__ int s_mode;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  if (a.hist1)
-    for (int i = t; i < HREP * SEL_BINS; i += 1024) a.hist1[i] = 0u;
+  // the exponent histogram (its HREP replicas summed), loaded up front
+  constexpr int BPT0 = SEL0_BINS / 1024;
+  uint32_t h0[BPT0];
+#pragma unroll
+  for (int k = 0; k < BPT0; k++) {
+    h0[k] = 0;
+#pragma unroll
+    for (int r = 0; r < HREP; r++) h0[k] += a.hist0[(size_t)r * SEL0_BINS + k * 1024 + t];
+  }
+  if (a.hist1) {
+    uint4* z = reinterpret_cast<uint4*>(a.hist1);
+#pragma unroll 4
+    for (int i = t; i < HREP * SEL_BINS / 4; i += 1024) z[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
   unsigned long long v[4] = {0, 0, 0, 0};
   // four buckets per thread and step (16-byte loads; the arena aligns the tables)
   const uint32_t nb4 = a.nbk / 4;
+#pragma unroll 4
   for (uint32_t q = t; q < nb4; q += 1024) {
     const uint4 s0 = reinterpret_cast<const uint4*>(a.b_slots)[q];
     const uint4 s1 = reinterpret_cast<const uint4*>(a.b_surv)[q];
@@ -158,15 +171,10 @@ __global__ __launch_bounds__(1024) void k_sel_plan(PlanArgs a) {
     s_K = K;
     a.ctl->sel_mode = mode;
   }
+#pragma unroll
+  for (int k = 0; k < BPT0; k++) hs[k * 1024 + t] = h0[k];
   __syncthreads();
   if (s_mode != S_THRESHOLD) return;
-  for (int b = t; b < SEL0_BINS; b += 1024) {
-    uint32_t h = 0;
-#pragma unroll
-    for (int r = 0; r < HREP; r++) h += a.hist0[(size_t)r * SEL0_BINS + b];
-    hs[b] = h;
-  }
-  __syncthreads();
   unsigned int d0;
   unsigned long long krem, cnt;
   pick_bin(hs, SEL0_BINS, s_K, tmp, &d0, &krem, &cnt);
@@ -276,12 +284,17 @@ __global__ __launch_bounds__(1024) void k_sel_pick1(const uint32_t* hist1, Ctl* 
   __shared__ uint32_t hs[SEL_BINS];
   if (ctl->sel_mode != S_THRESHOLD || ctl->fin_level != 1u) return;
   const unsigned long long K = ctl->sel_K;
-  for (int b = threadIdx.x; b < SEL_BINS; b += 1024) {
-    uint32_t h = 0;
+  // every load of the replicas issued before the first use
+  constexpr int BPT = SEL_BINS / 1024;
+  uint32_t h[BPT];
 #pragma unroll
-    for (int r = 0; r < HREP; r++) h += hist1[(size_t)r * SEL_BINS + b];
-    hs[b] = h;
+  for (int k = 0; k < BPT; k++) {
+    h[k] = 0;
+#pragma unroll
+    for (int r = 0; r < HREP; r++) h[k] += hist1[(size_t)r * SEL_BINS + k * 1024 + threadIdx.x];
   }
+#pragma unroll
+  for (int k = 0; k < BPT; k++) hs[k * 1024 + threadIdx.x] = h[k];
   __syncthreads();
   unsigned int d1;
   unsigned long long krem, cnt;
@@ -417,37 +430,51 @@ __global__ __launch_bounds__(1024) void k_sel_finish(Sel2Args a) {
   }
 }
 
+// Eight consecutive words p[b0 .. b0 + 8) (zero past nb), as two 16-byte
+// loads when the eight lie inside the array (b0 is a multiple of 8 and the
+// arena aligns the tables to 256 bytes).
+DEV void load8(const uint32_t* p, uint32_t b0, uint32_t nb, uint32_t* v) {
+  if (b0 + 8 <= nb) {
+    const uint4 a = *reinterpret_cast<const uint4*>(p + b0);
+    const uint4 c = *reinterpret_cast<const uint4*>(p + b0 + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; k++) v[k] = b0 + k < nb ? p[b0 + k] : 0u;
+  }
+}
+
 // Output bases: survivors kept per bucket (by the select mode), exclusive
-// scan over the buckets in tiles of 8192 (one block, coalesced loads).
+// scan over the buckets in tiles of 8192 (one block; thread t owns eight
+// consecutive buckets, read and written as 16-byte vectors).
 __global__ __launch_bounds__(1024) void k_scan_out(const uint32_t* b_surv, const uint32_t* b_keep,
                                                    const uint32_t* b_abv, const uint32_t* b_bcnt,
                                                    uint32_t nb, uint32_t* b_obase, Ctl* ctl) {
   constexpr int PER = 8, TILE = 1024 * PER;
-  __shared__ uint32_t tile[TILE];
   __shared__ unsigned long long tmp[17];
   if (ctl->deep) return;
   const int mode = ctl->sel_mode;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   unsigned long long carry = 0;
   for (uint32_t base = 0; base < nb; base += TILE) {
-#pragma unroll
-    for (int k = 0; k < PER; k++) {
-      const uint32_t b = base + k * 1024 + t;
-      uint32_t c = 0;
-      if (b < nb)
-        c = mode == S_ALL ? b_surv[b]
-            : mode == S_KEEP_ONLY ? b_keep[b]
-                                  : b_keep[b] + b_abv[b] + b_bcnt[b];
-      tile[k * 1024 + t] = c;
-    }
-    __syncthreads();
+    const uint32_t b0 = base + (uint32_t)t * PER;
     uint32_t loc[PER];
+    if (mode == S_ALL) {
+      load8(b_surv, b0, nb, loc);
+    } else if (mode == S_KEEP_ONLY) {
+      load8(b_keep, b0, nb, loc);
+    } else {
+      uint32_t a[PER], c[PER];
+      load8(b_keep, b0, nb, loc);
+      load8(b_abv, b0, nb, a);
+      load8(b_bcnt, b0, nb, c);
+#pragma unroll
+      for (int k = 0; k < PER; k++) loc[k] += a[k] + c[k];
+    }
     unsigned long long s = 0;
 #pragma unroll
-    for (int k = 0; k < PER; k++) {
-      loc[k] = tile[t * PER + k];
-      s += loc[k];
-    }
+    for (int k = 0; k < PER; k++) s += loc[k];
     unsigned long long x = s;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -465,19 +492,22 @@ __global__ __launch_bounds__(1024) void k_scan_out(const uint32_t* b_surv, const
     const unsigned long long before = wv > 0 ? __shfl(w, wv - 1, 64) : 0ull;
     const unsigned long long tile_total = __shfl(w, 15, 64);
     unsigned long long pre = carry + before + x - s;
+    uint32_t o[PER];
 #pragma unroll
     for (int k = 0; k < PER; k++) {
-      tile[t * PER + k] = (uint32_t)pre;
+      o[k] = (uint32_t)pre;
       pre += loc[k];
     }
-    __syncthreads();
+    if (b0 + PER <= nb) {
+      *reinterpret_cast<uint4*>(b_obase + b0) = make_uint4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<uint4*>(b_obase + b0 + 4) = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
 #pragma unroll
-    for (int k = 0; k < PER; k++) {
-      const uint32_t b = base + k * 1024 + t;
-      if (b < nb) b_obase[b] = tile[k * 1024 + t];
+      for (int k = 0; k < PER; k++)
+        if (b0 + k < nb) b_obase[b0 + k] = o[k];
     }
     carry += tile_total;
-    __syncthreads();
+    __syncthreads();  // tmp is rewritten by the next tile
   }
   if (t == 0) ctl->out_total = carry;
 }
