@@ -288,6 +288,7 @@ int Engine::run(Call& c) {
   }
   // at most 2^18 (commutator) and 2^17 (operator terms) threads of emit rows
   constexpr int64_t COMM_ROWS_MAX = (1 << 18) / EMIT_THREADS, TERM_ROWS_MAX = (1 << 17) / EMIT_THREADS;
+  static_assert(COMM_ROWS_MAX + TERM_ROWS_MAX <= SC_ROWS_MAX, "k_scan_cols covers every count row");
   int comm_rows = comm ? (int)std::min<int64_t>((c.O.n + EMIT_THREADS - 1) / EMIT_THREADS, COMM_ROWS_MAX) : 0;
   int term_rows = nterm_rec > 0 ? (int)std::min<int64_t>((nterm_rec + EMIT_THREADS - 1) / EMIT_THREADS, TERM_ROWS_MAX) : 0;
   const int rows = comm_rows + term_rows;
@@ -384,12 +385,12 @@ int Engine::run(Call& c) {
     const uint32_t nzero = pass_id == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
     if (nbl == NBINS_LOG) {
       LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG>), rows, EMIT_THREADS, ea);
-      LAUNCH("k_scan_cols", k_scan_cols, NBINS / 256, 256, counts, rows, bin_total, dctl, NBINS);
+      LAUNCH("k_scan_cols", k_scan_cols, NBINS / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl, NBINS);
       LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG>, 1, 1024, bin_total, bin_base, dctl, zero,
              nzero);
     } else {
       LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);
-      LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / 256, 256, counts, rows, bin_total, dctl,
+      LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl,
              NBINS_MP);
       LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
              nzero);
@@ -436,6 +437,7 @@ int Engine::run(Call& c) {
   // (full order keys, source ids aside); each pass bins one partition
   constexpr int PART_NBL = 12;  // at most 2^12 partitions (MAX_PASS_BITS)
   constexpr int SPLIT_ROWS = 256;  // blocks binning one partition
+  static_assert(SPLIT_ROWS <= SC_ROWS_MAX, "k_scan_cols covers every split row");
   const bool partitioned = nbl == NBINS_LOG_MP;
   void* precs = partitioned ? ar->take(ptot * RB) : nullptr;
   uint32_t* psrc = partitioned ? (uint32_t*)ar->take(ptot * 4) : nullptr;
@@ -512,7 +514,7 @@ int Engine::run(Call& c) {
       ea.psrc = psrc;
       ea.bin_base = pbase;
       LAUNCH("k_emit_part_count", (k_emit<W, F32, false, PART_NBL>), rows, EMIT_THREADS, ea);
-      LAUNCH("k_scan_cols", k_scan_cols, (1 << PART_NBL) / 256, 256, counts, rows, bin_total, dctl,
+      LAUNCH("k_scan_cols", k_scan_cols, (1 << PART_NBL) / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl,
              1 << PART_NBL);
       LAUNCH("k_scan_part", k_scan_part, 1, 1024, bin_total, npass, pbase, (1 << PART_NBL) + 1,
              dctl);
@@ -537,7 +539,7 @@ int Engine::run(Call& c) {
         uint32_t* zero = p == 0 ? hist0 : (uint32_t*)nullptr;
         const uint32_t nzero = p == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
         LAUNCH("k_split_count", (k_split<W, F32, false, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
-        LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / 256, 256, counts, SPLIT_ROWS, bin_total,
+        LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, counts, SPLIT_ROWS, bin_total,
                dctl, NBINS_MP);
         LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
                nzero);

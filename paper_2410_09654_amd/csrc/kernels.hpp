@@ -468,30 +468,42 @@ __global__ __launch_bounds__(1024) void k_scan_part(const uint32_t* total, int n
   if (t == 0) ctl->pe_total = tot;
 }
 
-// Column-wise exclusive prefix of the counts matrix; bin totals.
-__global__ void k_scan_cols(uint32_t* counts, int rows, uint32_t* bin_total, Ctl* ctl, int nbins) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nbins) return;
+// Column-wise exclusive prefix of the counts matrix (rows x nbins, row
+// major) and the bin totals.  A block of SC_NSEG x SC_COLS threads covers
+// SC_COLS columns: thread (segment g, column b) loads rows
+// [SC_SEG g, SC_SEG g + SC_SEG) of column b all at once, the segment sums of
+// a column are combined in LDS, and each thread writes its rows' prefixes.
+// rows <= SC_NSEG * SC_SEG.
+constexpr int SC_COLS = 32, SC_SEG = 32, SC_NSEG = 16;
+constexpr int SC_ROWS_MAX = SC_SEG * SC_NSEG;
+__global__ __launch_bounds__(SC_COLS * SC_NSEG) void k_scan_cols(uint32_t* counts, int rows,
+                                                                 uint32_t* bin_total, Ctl* ctl,
+                                                                 int nbins) {
+  __shared__ unsigned long long ssum[SC_NSEG][SC_COLS];
+  const int col = threadIdx.x % SC_COLS, seg = threadIdx.x / SC_COLS;
+  const int b = blockIdx.x * SC_COLS + col;
+  const int r0 = seg * SC_SEG;
+  const bool on = b < nbins;
+  uint32_t c[SC_SEG];
+#pragma unroll
+  for (int q = 0; q < SC_SEG; q++)
+    c[q] = (on && r0 + q < rows) ? counts[(size_t)(r0 + q) * nbins + b] : 0u;
+  unsigned long long s = 0;
+#pragma unroll
+  for (int q = 0; q < SC_SEG; q++) s += c[q];
+  ssum[seg][col] = s;
+  __syncthreads();
   unsigned long long run = 0;
-  int r = 0;
-  for (; r + 8 <= rows; r += 8) {
-    uint32_t c[8];
+  for (int g = 0; g < seg; g++) run += ssum[g][col];
 #pragma unroll
-    for (int q = 0; q < 8; q++) c[q] = counts[(size_t)(r + q) * nbins + b];
-#pragma unroll
-    for (int q = 0; q < 8; q++) {
-      counts[(size_t)(r + q) * nbins + b] = (uint32_t)run;
-      run += c[q];
-    }
+  for (int q = 0; q < SC_SEG; q++) {
+    if (on && r0 + q < rows) counts[(size_t)(r0 + q) * nbins + b] = (uint32_t)run;
+    run += c[q];
   }
-  for (; r < rows; ++r) {
-    const size_t idx = (size_t)r * nbins + b;
-    const uint32_t c = counts[idx];
-    counts[idx] = (uint32_t)run;
-    run += c;
+  if (on && seg == SC_NSEG - 1) {  // the last segment's running sum is the column total
+    if (run > 0xFFFFFFFFull) atomicOr(&ctl->overflow, 2u);
+    bin_total[b] = (uint32_t)run;
   }
-  if (run > 0xFFFFFFFFull) atomicOr(&ctl->overflow, 2u);
-  bin_total[b] = (uint32_t)run;
 }
 
 // Exclusive scan of the bin totals (one block of 1024 threads; thread t owns
