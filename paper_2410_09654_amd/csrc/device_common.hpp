@@ -29,7 +29,8 @@ constexpr int MERGE_THREADS = 1024;   // 16 waves; two merge blocks per CU (8 wa
 constexpr int DIGIT_BITS = 11;          // in-bucket counting-sort digit
 constexpr int NDIGITS = 1 << DIGIT_BITS;
 constexpr int EMIT_THREADS = 1024;
-constexpr int SEL0_BINS = 2048;         // exponent bins of |c|^2
+constexpr int SEL0_SHIFT = 51;          // level-0 select bin of |c|^2: its bits >> 51
+constexpr int SEL0_BINS = 4096;         // (exponent and first mantissa bit; |c|^2 >= 0)
 constexpr int SEL_BINS = 4096;          // 12-bit digits of later select levels
 constexpr int FINISH_CAP = 2048;
 constexpr int HREP = 16;                // replicas of the select histograms

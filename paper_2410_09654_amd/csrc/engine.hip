@@ -380,7 +380,7 @@ int Engine::run(Call& c) {
   auto count_pass = [&](int pass_bits, uint32_t pass_id) -> int {
     ea.pass_bits = pass_bits;
     ea.pass_id = pass_id;
-    // the first count pass of a merge sequence also clears the exponent histogram
+    // the first count pass of a merge sequence also clears the level-0 |c|^2 histogram
     uint32_t* zero = pass_id == 0 ? hist0 : (uint32_t*)nullptr;
     const uint32_t nzero = pass_id == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
     if (nbl == NBINS_LOG) {

@@ -14,7 +14,7 @@
 //                   sort on the next 11 key bits + insertion sort per thread
 //                   range, then every run of equal keys is folded in ascending
 //                   source id (the canonical summation order), filtered, and
-//                   written compactly; exponent histogram of |c|^2 for top-M
+//                   written compactly; level-0 histogram of |c|^2 for top-M
 //   k_select / k_level1 / k_cand_level / k_finish / k_count_boundary
 //                   exact radix select of the M-th largest (|c|^2, key) pair
 //   k_scan_buckets / k_write
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(SC_COLS * SC_NSEG) void k_scan_cols(uint32_t* count
 // Exclusive scan of the bin totals (one block of 1024 threads; thread t owns
 // the NB/1024 consecutive bins from t NB/1024, read and written as 16-byte
 // vectors) and the largest total over aligned groups of 1, 2, 4, 8, 16 bins.
-// Also clears `zero` (nzero words) when given: the exponent histogram of the
+// Also clears `zero` (nzero words) when given: the level-0 |c|^2 histogram of the
 // merges that follow this count pass.
 template <int NBL>
 __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, uint32_t* bin_base,
@@ -521,7 +521,9 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   __shared__ unsigned long long tmp[1024 / 64 + 1];
   __shared__ unsigned int gmax[16][5];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  for (uint32_t i = t; i < nzero; i += 1024) zero[i] = 0u;
+  // nzero is a multiple of 4 and `zero` 16-byte aligned (histogram replicas)
+  for (uint32_t i = t; i < nzero / 4; i += 1024)
+    reinterpret_cast<uint4*>(zero)[i] = make_uint4(0u, 0u, 0u, 0u);
   uint32_t v[BPT];
   const uint4* src = reinterpret_cast<const uint4*>(bin_total) + (size_t)t * (BPT / 4);
 #pragma unroll
@@ -730,13 +732,14 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   constexpr int CAP = merge_cap<W>();
   constexpr int PER = (CAP + MERGE_THREADS - 1) / MERGE_THREADS;
   constexpr int DPT = NDIGITS / MERGE_THREADS;
-  static_assert(SEL0_BINS == NDIGITS, "digit counts and |c|^2 histogram share LDS");
+  static_assert(SEL0_BINS == 2 * NDIGITS,
+                "digit counts and the |c|^2 histogram (16-bit counters, two per word) share LDS");
   // Sort: a counting sort on the DIGIT_BITS key bits after the bucket bits,
   // then the rank of every record inside its digit group by a 64-bit sort
   // word (the next 32 key bits, then the source id), read from `swd` (which
   // aliases sv until the values are written).  mk / sx / sv then hold the
   // records in sorted order; dh holds the digit counts and starts, then the
-  // exponent histogram of |c|^2.  Two distinct keys of one digit group with
+  // level-0 histogram of |c|^2.  Two distinct keys of one digit group with
   // equal sort bits show up as adjacent entries with equal windows but
   // different keys; the block then ranks by full keys (merge_full_rank).
   __shared__ Key<W> mk[CAP];
@@ -886,9 +889,9 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   }
   __syncthreads();
   // keys, sources and values in sorted order; the digit counts become the
-  // exponent histogram
+  // level-0 |c|^2 histogram (16-bit counters, two per word)
   if (a.mode == M_PLAIN)
-    for (int i = tid; i < SEL0_BINS; i += MERGE_THREADS) h0[i] = 0u;
+    for (int i = tid; i < NDIGITS; i += MERGE_THREADS) h0[i] = 0u;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
@@ -1064,7 +1067,11 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
           if (surv) {
             const bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mk[p]) : false;
             if (isk) kc++;
-            else atomicAdd(&h0[(uint32_t)(__double_as_longlong(weight2(v)) >> 52)], 1u);
+            else {
+              // 16-bit counters (a bucket holds < 2^16 records), two per word
+              const uint32_t hb = (uint32_t)((uint64_t)__double_as_longlong(weight2(v)) >> SEL0_SHIFT);
+              atomicAdd(&h0[hb >> 1], 1u << ((hb & 1u) << 4));
+            }
           }
         }
         if (surv) {
@@ -1096,9 +1103,13 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   // the scan's barriers have ordered every histogram and s_pk update
   const uint32_t tot_kc = s_pk >> 16, tot_nzu = s_pk & 0xFFFFu;
   if (a.mode == M_PLAIN) {
+    // word i of the LDS histogram holds bins 2i (low half) and 2i + 1
     uint32_t* hrep = a.hist0 + (size_t)(j % HREP) * SEL0_BINS;
-    for (int i = tid; i < SEL0_BINS; i += MERGE_THREADS)
-      if (h0[i]) atomicAdd(&hrep[i], h0[i]);
+    for (int i = tid; i < NDIGITS; i += MERGE_THREADS) {
+      const uint32_t w = h0[i];
+      if (w & 0xFFFFu) atomicAdd(&hrep[2 * i], w & 0xFFFFu);
+      if (w >> 16) atomicAdd(&hrep[2 * i + 1], w >> 16);
+    }
   }
   if (tid == 0) {
     a.b_ubase[gb] = (uint32_t)ub;
@@ -1242,7 +1253,7 @@ __global__ __launch_bounds__(256) void k_scale_filter(ScaleArgs a) {
       surv++;
       bool isk = a.n_keep ? keep_lookup<W>(keep, a.n_keep, mk) : false;
       if (isk) kc++;
-      else atomicAdd(&h0[(uint32_t)(__double_as_longlong(weight2(v)) >> 52)], 1u);
+      else atomicAdd(&h0[(uint32_t)((uint64_t)__double_as_longlong(weight2(v)) >> SEL0_SHIFT)], 1u);
     } else {
       v = make_double2(0.0, 0.0);
     }
@@ -1269,8 +1280,9 @@ __global__ __launch_bounds__(256) void k_scale_filter(ScaleArgs a) {
 // ---------------------------------------------------------------------------
 // Top-M selection: exact radix select over the composite ordering key
 // (|c|^2 bits, then the complemented key words x[W-1]..x[0], z[W-1]..z[0]):
-// larger composite = kept first.  Digit 0 = the 11 exponent bits of |c|^2,
-// digit L >= 1 = the 12 bits at position 12L of the composite bit string.
+// larger composite = kept first.  Digit 0 = the top 13 bits of |c|^2 (sign,
+// always 0, the 11 exponent bits and the first mantissa bit: 4096 bins),
+// digit L >= 1 = the 12 bits at position 12L + 1 of the composite bit string.
 // ---------------------------------------------------------------------------
 template <int W>
 DEV void composite(double2 v, const Key<W>& raw, uint64_t* c) {
@@ -1284,8 +1296,8 @@ DEV void composite(double2 v, const Key<W>& raw, uint64_t* c) {
 
 template <int W>
 DEV uint32_t comp_digit(const uint64_t* c, int level) {
-  if (level == 0) return (uint32_t)(c[0] >> 52);
-  const int p = 12 * level;
+  if (level == 0) return (uint32_t)(c[0] >> SEL0_SHIFT);
+  const int p = 12 * level + (64 - SEL0_SHIFT - 12);  // 12-bit digits after the level-0 bits
   const int wi = p >> 6, off = p & 63;
   constexpr int NW = 1 + 2 * W;
   const uint64_t hi = wi < NW ? c[wi] : 0ull;

@@ -3,7 +3,7 @@
 // After the merge every bucket b holds its surviving strings (length cap and
 // coefficient threshold applied; keys as order keys) at U slots
 // [b_ubase[b], b_ubase[b] + b_slots[b]), with per-bucket counts of survivors and keep-set survivors and
-// a replicated exponent histogram of |c|^2 over the non-keep survivors.  The
+// a replicated level-0 histogram of |c|^2 (its top 13 bits) over the non-keep survivors.  The
 // kernels below decide, without a host round trip, whether a threshold is
 // needed (the keep set is always kept and counts toward M; ties are broken by
 // ascending key), find it by a two-level radix select over the composite
@@ -88,12 +88,12 @@ struct PlanArgs {
   uint32_t nbk;
   int want_select;
   long long max_strings;
-  const uint32_t* hist0;     // HREP replicas of the exponent histogram (SEL0_BINS each)
+  const uint32_t* hist0;     // HREP replicas of the level-0 |c|^2 histogram (SEL0_BINS each)
   uint32_t* hist1;           // digit-1 histogram replicas, cleared here (nullable)
   Ctl* ctl;
 };
 
-// Totals of the per-bucket counters, the select mode, and the exponent bin of
+// Totals of the per-bucket counters, the select mode, and the level-0 bin of
 // the threshold (one block of 1024 threads).  Clears the digit-1 histogram
 // for k_sel_pass1.
 __global__ __launch_bounds__(1024) void k_sel_plan(PlanArgs a) {
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(1024) void k_sel_plan(PlanArgs a) {
   __shared__ unsigned long long s_K;
   __shared__ int s_mode;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  // the exponent histogram (its HREP replicas summed), loaded up front
+  // the level-0 histogram (its HREP replicas summed), loaded up front
   constexpr int BPT0 = SEL0_BINS / 1024;
   uint32_t h0[BPT0];
 #pragma unroll
@@ -217,7 +217,7 @@ DEV uint32_t wave_append(bool take, unsigned long long* counter) {
 }
 
 // Level 1 over all survivors, one wave per bucket: counts per bucket the
-// non-keep survivors whose exponent digit is above the threshold bin, lists
+// non-keep survivors whose level-0 digit is above the threshold bin, lists
 // those inside it and histograms their digit 1 (when the bin is too large to
 // finish directly).
 template <int W>
@@ -250,13 +250,13 @@ __global__ __launch_bounds__(256) void k_sel_pass1(Sel2Args a) {
             isk = keep_lookup<W>(keep, a.n_keep, mk);
           }
           if (!isk) {
-            const uint32_t d0 = (uint32_t)((uint64_t)__double_as_longlong(weight2(v)) >> 52);
+            const uint32_t d0 = (uint32_t)((uint64_t)__double_as_longlong(weight2(v)) >> SEL0_SHIFT);
             if (d0 > D0) {
               abv++;
             } else if (d0 == D0) {
               cand = true;
               if (lvl1) {
-                // digit 1: the 12 bits of |c|^2 after the exponent (the
+                // digit 1: the 12 bits of |c|^2 after the level-0 bits (the
                 // string words of the composite do not reach it)
                 uint64_t c[NW] = {};
                 c[0] = (uint64_t)__double_as_longlong(weight2(v));
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(1024) void k_sel_pick1(const uint32_t* hist1, Ctl* 
 }
 
 // The final candidates, gathered into one list: the level-1 candidates
-// inside the digit-1 bin, or all of them when the exponent bin is small.
+// inside the digit-1 bin, or all of them when the level-0 bin is small.
 // Also counts per bucket the candidates above the digit-1 bin.  One wave per
 // bucket.
 template <int W>
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_sel_narrow(Sel2Args a) {
         ui = a.list0[ub + i];
         take = true;
         if (l1) {
-          // the digit-1 bin holds the 12 bits of |c|^2 after the exponent:
+          // the digit-1 bin holds the 12 bits of |c|^2 after the level-0 bits:
           // the string words of the composite do not reach it
           uint64_t c[NW] = {};
           c[0] = (uint64_t)__double_as_longlong(weight2(a.uc[ui]));
