@@ -794,9 +794,6 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   const int F = a.nbins_log + a.pass_bits;
   const uint32_t ibits = (uint32_t)(F - 3);
   uint32_t dig[PER], rnk[PER], rsx[PER];
-  // record values (as plain components, so they stay in registers), kept
-  // until they are written in sorted order
-  typename std::conditional<F32, float, double>::type rvx[PER], rvy[PER];
   // the records' order keys as plain words (so they stay in registers)
   uint64_t rkw[2 * W][PER];
   auto rkey = [&](int k) -> Key<W> {
@@ -818,8 +815,6 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
     if (i < n) {
       const uint32_t pos = b0 + i;
       const Rec<W, F32> r = recs[pos];
-      rvx[k] = r.v.x;
-      rvy[k] = r.v.y;
       int kb = 0;
       while (kb + 1 < G && sbb[kb + 1] <= pos) kb++;
       const uint64_t T = ((uint64_t)a.pass_id << a.nbins_log) | (uint64_t)((j << a.g_log) + kb);
@@ -898,10 +893,9 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
     if (i < n) {
       mk[fpos[k]] = rkey(k);
       sx[fpos[k]] = rsx[k];
-      V vk;
-      vk.x = rvx[k];
-      vk.y = rvy[k];
-      sv[fpos[k]] = vk;
+      // values are read a second time (from cache) rather than held in
+      // registers through the sort: spill-free at 8 waves per SIMD
+      sv[fpos[k]] = recs[b0 + i].v;
     }
   }
   __syncthreads();
