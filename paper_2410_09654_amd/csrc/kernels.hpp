@@ -793,39 +793,45 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   const Rec<W, F32>* recs = reinterpret_cast<const Rec<W, F32>*>(a.recs);
   const int F = a.nbins_log + a.pass_bits;
   const uint32_t ibits = (uint32_t)(F - 3);
-  uint32_t dig[PER], rnk[PER], rsx[PER];
-  // the records' order keys as plain words (so they stay in registers)
-  uint64_t rkw[2 * W][PER];
-  auto rkey = [&](int k) -> Key<W> {
-    Key<W> m;
-#pragma unroll
-    for (int q = 0; q < 2 * W; q++) m.w[q] = rkw[q][k];
+  // Per record the digit, its rank among the digit's records, the source id
+  // and the 32 sort bits stay in registers, and at W = 1 the order key; the
+  // value (and a wider key) is read a second time, from cache, for the
+  // sorted write, which keeps the kernel spill-free at 8 waves per SIMD.
+  constexpr bool HOLD_KEY = W == 1;
+  uint32_t dig[PER], rnk[PER], rsx[PER], swl[PER];
+  uint64_t rkw[HOLD_KEY ? 2 * W : 1][PER];
+  // the record's order key: the bin bits that the source id displaced restored
+  auto order_key = [&](uint32_t pos, const Key<W>& rk) -> Key<W> {
+    int kb = 0;
+    while (kb + 1 < G && sbb[kb + 1] <= pos) kb++;
+    const uint64_t T = ((uint64_t)a.pass_id << a.nbins_log) | (uint64_t)((j << a.g_log) + kb);
+    Key<W> m = rk;
+    m.w[0] = (T << (64 - F)) | (rk.w[0] & (~0ull >> F));
     return m;
   };
-  // sort word of record k (recomputed where needed to spare registers)
-  auto sort_word = [&](int k) -> uint64_t {
-    return (key_window<W>(rkey(k), a.digit_shift) << 32) | rsx[k];
-  };
+  // sort word of record k: the 32 key bits after the digit, then the source id
+  auto sort_word = [&](int k) -> uint64_t { return ((uint64_t)swl[k] << 32) | rsx[k]; };
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
     dig[k] = 0;
     rnk[k] = 0;
     rsx[k] = 0;
+    swl[k] = 0;
     if (i < n) {
       const uint32_t pos = b0 + i;
-      const Rec<W, F32> r = recs[pos];
-      int kb = 0;
-      while (kb + 1 < G && sbb[kb + 1] <= pos) kb++;
-      const uint64_t T = ((uint64_t)a.pass_id << a.nbins_log) | (uint64_t)((j << a.g_log) + kb);
-      const uint32_t small = (uint32_t)(r.k.w[0] >> (64 - F));
-      Key<W> m = r.k;
-      m.w[0] = (T << (64 - F)) | (r.k.w[0] & (~0ull >> F));
+      const Key<W> rk = recs[pos].k;
+      const uint32_t small = (uint32_t)(rk.w[0] >> (64 - F));
+      const Key<W> m = order_key(pos, rk);
+      if constexpr (HOLD_KEY) {
 #pragma unroll
-      for (int q = 0; q < 2 * W; q++) rkw[q][k] = m.w[q];
+        for (int q = 0; q < 2 * W; q++) rkw[q][k] = m.w[q];
+      }
+      const uint64_t win = key_window<W>(m, a.digit_shift);
       rsx[k] = a.wide ? a.rsrc_wide[pos]
                       : (((small >> ibits) << GROUP_SHIFT) | (small & ((1u << ibits) - 1u)));
-      dig[k] = (uint32_t)(key_window<W>(m, a.digit_shift) >> 32);
+      dig[k] = (uint32_t)(win >> 32);
+      swl[k] = (uint32_t)win;
       rnk[k] = atomicAdd(&dh[dig[k]], 1u);
     }
   }
@@ -891,11 +897,18 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   for (int k = 0; k < PER; k++) {
     const uint32_t i = tid + k * MERGE_THREADS;
     if (i < n) {
-      mk[fpos[k]] = rkey(k);
+      if constexpr (HOLD_KEY) {
+        Key<W> m;
+#pragma unroll
+        for (int q = 0; q < 2 * W; q++) m.w[q] = rkw[q][k];
+        mk[fpos[k]] = m;
+        sv[fpos[k]] = recs[b0 + i].v;  // second read (cache)
+      } else {
+        const Rec<W, F32> r = recs[b0 + i];  // second read (cache)
+        mk[fpos[k]] = order_key(b0 + i, r.k);
+        sv[fpos[k]] = r.v;
+      }
       sx[fpos[k]] = rsx[k];
-      // values are read a second time (from cache) rather than held in
-      // registers through the sort: spill-free at 8 waves per SIMD
-      sv[fpos[k]] = recs[b0 + i].v;
     }
   }
   __syncthreads();
