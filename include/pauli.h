@@ -111,6 +111,19 @@ typedef struct pauli_ws {
 int pauli_commutator(const pauli_op *H, const pauli_op *O, const pauli_trunc *t,
                      pauli_op *out, pauli_ws *ws, void *stream);
 
+/* out = trunc(A B) = sum_{a,b} a_a b_b P_a P_b (Alg. 1 as written: every pair,
+ * the string product and phase of the single-site multiplication table),
+ * summed per string in ascending index of A.  A must be PAULI_C128 with fewer
+ * strings than one merge bucket holds (as H of pauli_commutator); B and out
+ * share a dtype.  Pairs are not filtered, so the records number |A| |B|. */
+int pauli_multiply(const pauli_op *A, const pauli_op *B, const pauli_trunc *t,
+                   pauli_op *out, pauli_ws *ws, void *stream);
+
+/* out[0] + i out[1] (host) = Tr(A)/2^N: the coefficient of the identity string
+ * (0 when A has none).  A's strings must be distinct.  With pauli_multiply it
+ * gives the moments Tr(H^k)/2^N of the Conclusion's spectral outlook. */
+int pauli_trace(const pauli_op *A, double out[2], pauli_ws *ws, void *stream);
+
 /* out = trunc(alpha A + beta B) over the union of strings (the operator sum
  * used by both the Lanczos recursion and the Runge-Kutta stages). */
 int pauli_add(const pauli_op *A, double alpha_re, double alpha_im, const pauli_op *B,

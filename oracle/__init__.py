@@ -164,6 +164,27 @@ def product(A: HostOp, B: HostOp) -> HostOp:
     return _take(out, A.n_qubits)
 
 
+def trace(O: HostOp) -> complex:
+    """Tr(O)/2^N: every Pauli string but the identity is traceless, so this is
+    the identity string's coefficient (0 when O has none)."""
+    if O.n == 0:
+        return 0j
+    ident = np.all(O.x == 0, axis=1) & np.all(O.z == 0, axis=1)
+    idx = np.nonzero(ident)[0]
+    return complex(O.coef[idx[0]]) if len(idx) else 0j
+
+
+def moments(H: HostOp, kmax: int) -> list:
+    """mu_k = Tr(H^k)/2^N, k = 1..kmax (the spectral moments of the
+    Conclusion), from the powers H^k = H H^(k-1) by exact string products."""
+    mus, cur = [], H
+    for k in range(1, kmax + 1):
+        if k > 1:
+            cur = product(H, cur)
+        mus.append(trace(cur))
+    return mus
+
+
 def add(A: HostOp, alpha: complex, B: HostOp, beta: complex) -> HostOp:
     a, b, out = _Marshalled(A), _Marshalled(B), _OrOp()
     alpha, beta = complex(alpha), complex(beta)

@@ -7,11 +7,11 @@ Python binding over torch device memory.
 """
 from ._lib import PAULI_C128, PAULI_C64K, PauliError
 from .ops import (PauliOp, Trunc, Workspace, add, canonicalize, commutator, inner,
-                  lanczos_step, last_stats, norm2, order_keys, profile_enable, profile_read,
-                  rk4_step, strings_from_order_keys, truncate)
-from .algorithms import evolve, lanczos
+                  lanczos_step, last_stats, multiply, norm2, order_keys, profile_enable,
+                  profile_read, rk4_step, strings_from_order_keys, trace, truncate)
+from .algorithms import evolve, lanczos, moments
 
 __all__ = ["PAULI_C128", "PAULI_C64K", "PauliError", "PauliOp", "Trunc", "Workspace", "add",
            "canonicalize", "commutator", "inner", "lanczos_step", "norm2", "rk4_step",
            "truncate", "lanczos", "evolve", "profile_enable", "profile_read", "last_stats",
-           "order_keys", "strings_from_order_keys"]
+           "order_keys", "strings_from_order_keys", "multiply", "trace", "moments"]

@@ -44,3 +44,17 @@ def evolve(H: PauliOp, O0: PauliOp, dt: float, steps: int, trunc: Trunc | None =
         if observe is not None:
             observe(cur)
     return cur, S
+
+
+def moments(H: PauliOp, kmax: int, trunc: Trunc | None = None, ws: Workspace | None = None):
+    """Moments mu_k = Tr(H^k)/2^N for k = 1..kmax (the spectral moments the
+    Conclusion proposes): H^k = H H^(k-1) by string products, mu_k = the
+    identity coefficient of H^k.  Exact without truncation; with `trunc`
+    every power is truncated before the next product."""
+    ws = ws or ops.default_workspace(H.device)
+    mus, cur = [], H
+    for k in range(1, kmax + 1):
+        if k > 1:
+            cur = ops.multiply(H, cur, trunc, ws=ws)
+        mus.append(ops.trace(cur, ws=ws))
+    return mus

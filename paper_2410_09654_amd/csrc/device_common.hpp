@@ -187,6 +187,27 @@ DEV float2 times_2ie(float2 v, int e) {
   }
   return r;
 }
+// i^e v, exact.
+DEV double2 times_ie(double2 v, int e) {
+  double2 r;
+  switch (e & 3) {
+    case 0: r = v; break;
+    case 1: r = make_double2(-v.y, v.x); break;
+    case 2: r = make_double2(-v.x, -v.y); break;
+    default: r = make_double2(v.y, -v.x); break;
+  }
+  return r;
+}
+DEV float2 times_ie(float2 v, int e) {
+  float2 r;
+  switch (e & 3) {
+    case 0: r = v; break;
+    case 1: r = make_float2(-v.y, v.x); break;
+    case 2: r = make_float2(-v.x, -v.y); break;
+    default: r = make_float2(v.y, -v.x); break;
+  }
+  return r;
+}
 DEV double weight2(double2 v) {
   double a = v.x * v.x;
   double b = v.y * v.y;

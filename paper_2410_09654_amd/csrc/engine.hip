@@ -206,6 +206,7 @@ struct Call {
   int W = 1;
   bool f32rec = false;  // FP32 record values (precision split)
   bool has_comm = false;
+  bool product = false;  // A B instead of [A, B] (H = A, O = B)
   OpV H, O;
   int comm_group = 0;
   int n_terms = 0;
@@ -349,6 +350,7 @@ int Engine::run(Call& c) {
   ea.Hc = comm ? (const double2*)c.H.c : nullptr;
   ea.nH = comm ? (int)c.H.n : 0;
   ea.has_comm = comm ? 1 : 0;
+  ea.product = c.product ? 1 : 0;
   ea.comm_rows = comm_rows;
   ea.comm_group = (uint32_t)c.comm_group;
   if (comm) {
@@ -966,6 +968,52 @@ int pauli_commutator(const pauli_op* H, const pauli_op* O, const pauli_trunc* t,
   c.out.f32 = out->dtype == PAULI_C64K;
   c.round32 = c.out.f32;
   return run_call(ar, ws, stream, c);
+}
+
+int pauli_multiply(const pauli_op* A, const pauli_op* B, const pauli_trunc* t, pauli_op* out,
+                   pauli_ws* ws, void* stream) {
+  if (!ws || check_op(A, false) || check_op(B, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (A->n_qubits != B->n_qubits || out->n_qubits != B->n_qubits) return PAULI_EINVAL;
+  if (A->dtype != PAULI_C128 || out->dtype != B->dtype) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  Call c;
+  c.W = words_of(B->n_qubits);
+  c.f32rec = B->dtype == PAULI_C64K;
+  c.has_comm = true;
+  c.product = true;
+  c.H = view(A);
+  c.O = view(B);
+  c.comm_group = 0;
+  c.n_groups = 1;
+  c.groups[0].kind = c.f32rec ? G_SUM_KAHAN32 : G_SUM;
+  c.trunc = t;
+  c.out.user = out;
+  c.out.f32 = out->dtype == PAULI_C64K;
+  c.round32 = c.out.f32;
+  return run_call(ar, ws, stream, c);
+}
+
+int pauli_trace(const pauli_op* A, double out[2], pauli_ws* ws, void* stream_) {
+  if (!ws || !out || check_op(A, false)) return PAULI_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  Arena ar = make_arena(ws);
+  double* res = (double*)ar.take(16);
+  if (ar.short_) return ws_short(ar, ws);
+  out[0] = 0.0;
+  out[1] = 0.0;
+  if (A->size == 0) return PAULI_OK;
+  const int W = words_of(A->n_qubits);
+  LAUNCH("k_fill_u32", k_fill_u32, 1, 256, (uint32_t*)res, 0u, (size_t)4);
+  const int blocks = (int)std::min<int64_t>((A->size + 255) / 256, 4096);
+  LAUNCH("k_trace", k_trace, blocks, 256, A->x, A->z, A->capacity, A->size, W,
+         A->coef, A->dtype == PAULI_C64K ? 1 : 0, res);
+  double h[2];
+  HIP_TRY(hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  out[0] = h[0];
+  out[1] = h[1];
+  return PAULI_OK;
 }
 
 int pauli_add(const pauli_op* A, double ar_, double ai, const pauli_op* B, double br, double bi,

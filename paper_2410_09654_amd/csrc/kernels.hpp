@@ -69,6 +69,7 @@ struct EmitArgs {
   const double2* Hc;
   int nH;
   int has_comm;
+  int product;  // plain product A B (every pair, i^e h_a c_b) instead of [A, B]
   int comm_rows;
   uint32_t comm_group;
   const uint64_t* Ox;
@@ -267,9 +268,11 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
         wlo = min(wlo, __shfl_xor(wlo, d, 64));
         whi = max(whi, __shfl_xor(whi, d, 64));
       }
-      if (whi < 0) continue;  // nothing but empty strings: all commute
-      const int hfirst = (int)a.hstart[max(wlo - *a.hspan, 0)];
-      const int hend = (int)a.hstart[whi + 1];
+      // the product keeps every pair (identity strings included); the
+      // commutator only pairs that can overlap
+      if (whi < 0 && !a.product) continue;  // nothing but empty strings: all commute
+      const int hfirst = a.product ? 0 : (int)a.hstart[max(wlo - *a.hspan, 0)];
+      const int hend = a.product ? a.nH : (int)a.hstart[whi + 1];
 
       // Handle one queued (lane, H position) pair per lane.
       auto process = [&](uint32_t entry, bool active) {
@@ -299,7 +302,8 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
           pc += __popcll(c.w[w] & c.w[W + w]);
         }
         // P_a P_b = i^(pa + pb + 2 pop(z_a & x_b) - pc) P_c; anticommuting
-        // pairs contribute 2 i^e h_a c_b to [P_a, P_b] h_a c_b.
+        // pairs contribute 2 i^e h_a c_b to [P_a, P_b] h_a c_b, every pair
+        // i^e h_a c_b to the product.
         const int e = (pa + pb + 2 * pz - pc) & 3;
         const uint32_t horig = a.Hidx[h];
         const double2 hd = a.Hc[horig];
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
         V prod;
         if constexpr (F32) prod = cmulf(hc, bc);
         else prod = cmul(hc, bc);
-        deposit(c, times_2ie(prod, e), a.comm_group, horig);
+        deposit(c, a.product ? times_ie(prod, e) : times_2ie(prod, e), a.comm_group, horig);
       };
 
       uint32_t qn = 0;  // wave-uniform queue fill
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
         uint32_t par = 0;
 #pragma unroll
         for (int w = 0; w < W; w++) par += __popcll((hk[w] & zb[w]) ^ (hk[W + w] & xb[w]));
-        const bool emit = valid && (par & 1u);
+        const bool emit = valid && (a.product || (par & 1u));
         const uint64_t m = __ballot(emit);
         if (m) {
           const uint32_t pos = qn + mbcnt64(m);
@@ -1124,6 +1128,29 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
     a.b_surv[gb] = tot_cnt;
     a.b_keep[gb] = tot_kc;
     a.b_unique[gb] = tot_nzu;
+  }
+}
+
+// Coefficient of the identity string (all mask words zero) of an operator
+// with distinct strings: Tr(A)/2^N.  `res` (two doubles) starts at zero; at
+// most one thread writes it.
+__global__ __launch_bounds__(256) void k_trace(const uint64_t* x, const uint64_t* z, int64_t cap,
+                                               int64_t n, int W, const void* coef, int f32,
+                                               double* res) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint64_t s = 0;
+    for (int w = 0; w < W; w++) s |= x[(size_t)w * cap + i] | z[(size_t)w * cap + i];
+    if (s == 0) {
+      if (f32) {
+        const float2 v = reinterpret_cast<const float2*>(coef)[i];
+        res[0] = (double)v.x;
+        res[1] = (double)v.y;
+      } else {
+        const double2 v = reinterpret_cast<const double2*>(coef)[i];
+        res[0] = v.x;
+        res[1] = v.y;
+      }
+    }
   }
 }
 

@@ -197,6 +197,43 @@ def commutator(H: PauliOp, O: PauliOp, trunc: Trunc | None = None, out: PauliOp 
     return out
 
 
+def multiply(A: PauliOp, B: PauliOp, trunc: Trunc | None = None, out: PauliOp | None = None,
+             ws: Workspace | None = None) -> PauliOp:
+    """A B (then truncated), on the GPU: every pair of strings, no filter."""
+    L = _lib.load()
+    ws = ws or default_workspace(B.device)
+    if out is None:
+        b = trunc.bound() if trunc else None
+        guess = b if b is not None else min(A.size * B.size, 16 * B.size + 1024)
+        out = _out_like(B.n_qubits, guess, B.dtype, B.device)
+    As, Bs = A.c_struct(), B.c_struct()
+    keep_s, ts = trunc.c_struct() if trunc else (None, None)
+
+    def fn(wss):
+        outs = out.c_struct()
+        st = L.pauli_multiply(ctypes.byref(As), ctypes.byref(Bs),
+                              ctypes.byref(ts) if ts is not None else None,
+                              ctypes.byref(outs), ctypes.byref(wss), _stream_handle())
+        return st, outs
+
+    _call("pauli_multiply", fn, ws, out)
+    return out
+
+
+def trace(A: PauliOp, ws: Workspace | None = None) -> complex:
+    """Tr(A)/2^N: the coefficient of the identity string."""
+    L = _lib.load()
+    ws = ws or default_workspace(A.device)
+    As = A.c_struct()
+    r = (ctypes.c_double * 2)()
+
+    def fn(wss):
+        return L.pauli_trace(ctypes.byref(As), r, ctypes.byref(wss), _stream_handle()), None
+
+    _call("pauli_trace", fn, ws, None)
+    return complex(r[0], r[1])
+
+
 def add(A: PauliOp, alpha: complex, B: PauliOp, beta: complex, trunc: Trunc | None = None,
         out: PauliOp | None = None, ws: Workspace | None = None) -> PauliOp:
     L = _lib.load()

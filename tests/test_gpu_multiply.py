@@ -1,0 +1,118 @@
+"""GPU parity of the plain operator product A B (Alg. 1 with every pair kept),
+the trace Tr(A)/2^N and the spectral moments Tr(H^k)/2^N, through the C ABI,
+against the CPU oracle.  Keys bit-exact; coefficients within 1e-12 relative
+(the product sums each string's contributions in ascending index of A, as the
+oracle does, so they agree exactly up to the sign of zero)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from helpers import assert_canonical_unique, assert_same_operator, exact_fraction, gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2410_09654_amd as pk
+    pk._lib.load()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ws(pk):
+    return pk.Workspace(256 << 20)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def up(pk, host, ws, dtype=0):
+    return pk.PauliOp.from_host(host, dtype=dtype, ws=ws)
+
+
+def upa(pk, host):
+    """The left factor keeps its given order (the summation order)."""
+    return pk.PauliOp.from_raw(host.n_qubits, host.x, host.z, host.coef)
+
+
+def with_identity(op: wl.HostOp, c: complex) -> wl.HostOp:
+    W = op.x.shape[1]
+    I = wl.HostOp(op.n_qubits, np.zeros((1, W), np.uint64), np.zeros((1, W), np.uint64),
+                  np.array([c]))
+    return oracle.add(op, 1.0, I, 1.0)
+
+
+@pytest.mark.parametrize("n,na,nb,seed", [(6, 7, 40, 1), (10, 25, 900, 2), (64, 191, 2000, 3),
+                                          (100, 30, 600, 4), (128, 17, 300, 5), (1, 1, 1, 6)])
+def test_multiply_random(pk, ws, n, na, nb, seed):
+    say(f"multiply n={n} na={na} nb={nb} seed={seed}")
+    A = wl.random_operator(n, na, seed=seed, density=min(1.0, 3.0 / n + 0.05))
+    B = with_identity(wl.random_operator(n, nb, seed=seed + 100,
+                                         density=min(1.0, 6.0 / n + 0.05)), 0.5 + 0.25j)
+    want = oracle.product(A, B)
+    got = pk.multiply(upa(pk, A), up(pk, B, ws), ws=ws).to_host()
+    assert_canonical_unique(got)
+    assert_same_operator(got, want, what="product")
+    assert exact_fraction(got, want) == 1.0
+    st = pk.last_stats()
+    assert st["emitted"] == A.n * B.n  # every pair is a record
+
+
+def test_multiply_truncated_and_fp32(pk, ws):
+    say("multiply chain N=64, 4000 local strings, L=10, M=20000; FP32 operand")
+    H = wl.ising_chain(64)
+    B = wl.random_local_strings(64, 4000, 8, seed=9)
+    t = oracle.Trunc(max_len=10, max_strings=20000)
+    want = oracle.truncate(oracle.product(H, B), t)
+    got = pk.multiply(upa(pk, H), up(pk, B, ws), pk.Trunc(max_len=10, max_strings=20000),
+                      ws=ws).to_host()
+    assert got.n == want.n == 20000
+    assert_same_operator(got, want, what="truncated product")
+    # FP32 right factor: keys exact, values within FP32 rounding of the products
+    want32 = oracle.product(H, B)
+    got32 = pk.multiply(upa(pk, H), up(pk, B, ws, dtype=pk.PAULI_C64K), ws=ws).to_host()
+    assert_same_operator(got32, want32, rtol=2e-6, what="FP32 product")
+
+
+def test_multiply_identity_and_empty(pk, ws):
+    say("multiply identity / empty")
+    n = 40
+    A = wl.random_operator(n, 12, seed=31, density=0.2)
+    I = with_identity(wl.HostOp(n, np.zeros((0, 1), np.uint64), np.zeros((0, 1), np.uint64),
+                                np.zeros(0, complex)), 2.0)
+    got = pk.multiply(upa(pk, A), up(pk, I, ws), ws=ws).to_host()
+    assert_same_operator(got, oracle.product(A, I), what="A * 2I")
+    E = wl.HostOp(n, np.zeros((0, 1), np.uint64), np.zeros((0, 1), np.uint64),
+                  np.zeros(0, complex))
+    got = pk.multiply(upa(pk, A), up(pk, E, ws), ws=ws).to_host()
+    assert got.n == 0
+
+
+@pytest.mark.parametrize("n,seed", [(8, 41), (64, 42), (128, 43)])
+def test_trace(pk, ws, n, seed):
+    say(f"trace n={n}")
+    O = wl.random_operator(n, 500, seed=seed, density=0.3)
+    assert pk.trace(up(pk, O, ws), ws=ws) == oracle.trace(O)
+    OI = with_identity(O, -1.5 + 0.125j)
+    assert pk.trace(up(pk, OI, ws), ws=ws) == oracle.trace(OI) == -1.5 + 0.125j
+    assert pk.trace(up(pk, OI, ws, dtype=pk.PAULI_C64K), ws=ws) == -1.5 + 0.125j
+
+
+@pytest.mark.parametrize("n,kmax", [(12, 6), (64, 3)])
+def test_moments_chain(pk, ws, n, kmax):
+    """mu_k = Tr(H^k)/2^N of the chaotic Ising chain, untruncated."""
+    say(f"moments n={n} kmax={kmax}")
+    H = wl.ising_chain(n, hx=1.05, hz=0.5)
+    want = oracle.moments(H, kmax)
+    got = pk.moments(upa(pk, H), kmax, ws=ws)
+    for k, (g, w) in enumerate(zip(got, want), 1):
+        assert abs(g - w) <= 1e-12 * max(1.0, abs(w)), (k, g, w)
+    assert got[0] == 0
+    assert abs(got[1] - float(np.sum(np.abs(H.coef) ** 2))) < 1e-12

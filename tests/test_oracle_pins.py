@@ -122,6 +122,33 @@ def test_product_vs_dense(n, seed):
     assert np.abs(dense(oracle.product(A, B)) - dense(A) @ dense(B)).max() < 1e-12
 
 
+@pytest.mark.parametrize("n,seed", [(2, 21), (4, 22), (6, 23)])
+def test_trace_vs_dense(n, seed):
+    """Tr(O)/2^N from the matrix, for operators with and without the identity."""
+    O = wl.random_operator(n, 9, seed=seed, density=0.6)
+    assert abs(oracle.trace(O) - np.trace(dense(O)) / 2 ** n) < 1e-13
+    I = wl.HostOp(n, np.zeros((1, O.x.shape[1]), np.uint64), np.zeros((1, O.x.shape[1]), np.uint64),
+                  np.array([0.25 - 0.5j]))
+    OI = oracle.add(O, 1.0, I, 1.0)
+    assert abs(oracle.trace(OI) - np.trace(dense(OI)) / 2 ** n) < 1e-13
+
+
+@pytest.mark.parametrize("n", [4, 6])
+def test_moments_vs_dense_matrix_powers(n):
+    """mu_k = Tr(H^k)/2^N of the chaotic Ising chain against matrix powers;
+    mu_1 = 0 (traceless) and mu_2 = sum of squared coefficients (Hermitian H)."""
+    H = wl.ising_chain(n, hx=1.05, hz=0.5)
+    mus = oracle.moments(H, 6)
+    dH = dense(H)
+    P = np.eye(2 ** n, dtype=complex)
+    for k in range(1, 7):
+        P = P @ dH
+        want = np.trace(P) / 2 ** n
+        assert abs(mus[k - 1] - want) <= 1e-12 * max(1.0, abs(want)), k
+    assert abs(mus[0]) == 0.0
+    assert abs(mus[1] - float(np.sum(np.abs(H.coef) ** 2))) < 1e-12
+
+
 def test_add_norm_inner_vs_dense():
     n = 5
     A = wl.random_operator(n, 20, seed=11)
