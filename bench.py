@@ -38,11 +38,11 @@ def parse():
                     help="O strings given to the CPU oracle (0: skip the CPU baseline)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--workload", default="commutator",
-                    choices=["commutator", "lanczos-split", "rk4-tfim", "lanczos-small",
+                    choices=["commutator", "lanczos-split", "rk4-tfim", "lanczos-small", "moments",
                              "surrogate"],
                     help="commutator: the benchmark line (default); the others run the "
-                         "Lanczos precision-split, RK4, small-Lanczos and b_n-surrogate "
-                         "configurations and print their own result line")
+                         "Lanczos precision-split, RK4, small-Lanczos, spectral-moment and "
+                         "b_n-surrogate configurations and print their own result line")
     ap.add_argument("--max-strings", type=int, default=0,
                     help="truncation M for lanczos-split / rk4-tfim (0: the configuration's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -193,6 +193,60 @@ def run_lanczos_small(args):
                       "strings": counts, "strings_above_1e-12": small}), flush=True)
 
 
+def run_moments(args):
+    """Spectral moments mu_k = Tr(H^k)/2^N, k = 1..4, of the N=64 chaotic Ising
+    chain (|H| = 191) by untruncated string products H^k = H H^(k-1) and the
+    identity coefficient; the last product pairs 191 x |H^3| = 2.0e8 strings.
+    The oracle computes mu_1..mu_3 beside it (mu_4 needs 2e8 records)."""
+    import torch
+    import workloads as wl
+    import paper_2410_09654_amd as pk
+    H_host = wl.ising_chain(64, hx=1.05, hz=0.5)
+    H = pk.PauliOp.from_raw(64, H_host.x, H_host.z, H_host.coef)
+    ws = pk.Workspace(1 << 30)
+    kmax = 4
+    for _ in range(max(args.warmup, 1)):
+        pk.moments(H, kmax, ws=ws)
+    steps = args.steps or 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mus = pk.moments(H, kmax, ws=ws)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    # the last product alone
+    P = H
+    for _ in range(kmax - 2):
+        P = pk.multiply(H, P, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        pk.multiply(H, P, ws=ws)
+    torch.cuda.synchronize()
+    t_last = (time.perf_counter() - t1) / steps
+    st = pk.last_stats()
+    pairs = H.size * P.size
+    line = {"workload": "spectral moments Tr(H^k)/2^N, N=64 chaotic Ising chain (hx=1.05, hz=0.5), "
+                        "k=1..4, untruncated products",
+            "mu": [[m.real, m.imag] for m in mus], "ms_per_moments_call": wall * 1e3,
+            "last_product": {"pairs": pairs, "ms": t_last * 1e3, "pairs_per_s": pairs / t_last,
+                             "emitted": st["emitted"], "unique": st["unique"],
+                             "passes": st["passes"]}}
+    if args.cpu_sample > 0:
+        import oracle
+        tc = time.perf_counter()
+        want = oracle.moments(H_host, 3)
+        t_o = time.perf_counter() - tc
+        # mu_4 = Tr(H^2 H^2)/2^N = ||H^2||^2 for Hermitian H
+        mu4 = oracle.norm2(oracle.product(H_host, H_host))
+        line["oracle"] = {"mu_1_3": [[m.real, m.imag] for m in want],
+                          "seconds_mu_1_3": t_o, "cores": 1,
+                          "max_abs_diff_mu_1_3": max(abs(a - b) for a, b in zip(mus[:3], want)),
+                          "mu_4_as_norm2_of_H2": mu4,
+                          "rel_diff_mu_4": abs(mus[3] - mu4) / abs(mu4)}
+    print(json.dumps(line), flush=True)
+
+
 MLP_FWD_FLOP = 2 * (16 * 256 + 256 * 256 + 256 * 16)  # per window
 MLP_TRAIN_FLOP = 3 * MLP_FWD_FLOP  # forward, input gradient, weight gradient
 
@@ -277,7 +331,8 @@ def main():
         globals()["np"] = np
         torch.cuda.set_device(0)
         {"lanczos-split": run_lanczos_split, "rk4-tfim": run_rk4_tfim,
-         "lanczos-small": run_lanczos_small, "surrogate": run_surrogate}[args.workload](args)
+         "lanczos-small": run_lanczos_small, "surrogate": run_surrogate,
+         "moments": run_moments}[args.workload](args)
         return
     import torch
     import workloads as wl

@@ -116,3 +116,21 @@ def test_moments_chain(pk, ws, n, kmax):
         assert abs(g - w) <= 1e-12 * max(1.0, abs(w)), (k, g, w)
     assert got[0] == 0
     assert abs(got[1] - float(np.sum(np.abs(H.coef) ** 2))) < 1e-12
+
+
+def test_fourth_moment_full_size_equals_norm_of_square(pk):
+    """N=64 chain: mu_4 from the 2.0e8-pair product H H^3 (several hash-range
+    passes) equals ||H^2||^2 = Tr(H^2 H^2)/2^N (H Hermitian), and
+    mu_3 = <H, H^2>, both from the oracle's small products."""
+    say("mu_4 at N=64 (2e8 pairs)")
+    import torch
+    H = wl.ising_chain(64, hx=1.05, hz=0.5)
+    wsb = pk.Workspace(1 << 30)
+    mus = pk.moments(upa(pk, H), 4, ws=wsb)
+    assert pk.last_stats()["passes"] >= 2
+    H2 = oracle.product(H, H)
+    mu4 = oracle.norm2(H2)
+    assert abs(mus[3] - mu4) <= 1e-12 * mu4
+    assert abs(mus[2] - oracle.inner(H, H2)) <= 1e-12 * max(1.0, abs(mus[2]))
+    del wsb
+    torch.cuda.empty_cache()
