@@ -138,6 +138,25 @@ int pauli_truncate(const pauli_op *in, const pauli_trunc *t, pauli_op *out, paul
  * zeros dropped, library order.  Duplicates allowed; up to 2^28 strings. */
 int pauli_canonicalize(const pauli_op *in, pauli_op *out, pauli_ws *ws, void *stream);
 
+/* Depolarizing noise in place (Heisenberg time evolution section: a string
+ * of length w is transmitted with rate exp(-eps w); one step of the noisy
+ * evolution applies lambda = eps dt): every coefficient is multiplied by
+ * f[w] = exp(-lambda w), the table computed on the host in double, w =
+ * sites with x or z set.  FP32 coefficients are scaled in double and rounded
+ * once.  A coefficient that underflows becomes an exact zero in place (the
+ * next pauli_truncate drops it).  lambda >= 0, else PAULI_EINVAL.
+ * Asynchronous on `stream`. */
+int pauli_add_noise(pauli_op *A, double lambda, void *stream);
+
+/* out[2q] + i out[2q+1] (host, 2 Q->size doubles) = the coefficient in A of the
+ * string q of Q, 0 when A lacks it.  A must be canonical (distinct strings in
+ * canonical order, as every call of this library leaves it); Q's strings are
+ * any.  With Q = {Z_j} and A = Z_i(t) this reads the two-point correlators
+ * S_{i-j}(t) = Tr[Z_i(t) Z_j(0)]/2^N of the noisy-evolution results.
+ * Synchronous at return. */
+int pauli_coefficients(const pauli_op *A, const pauli_op *Q, double *out, pauli_ws *ws,
+                       void *stream);
+
 /* Order keys: for every string of A its 2W-word key whose ascending
  * lexicographic order (word 0 most significant, unsigned) is the library's
  * canonical storage order.  The key is a bijective mix of the string's x and

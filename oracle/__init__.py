@@ -66,6 +66,7 @@ def lib():
                              ctypes.c_double, ctypes.c_double, P(_OrOp)]
         L.or_truncate.argtypes = [P(_OrOp), P(_OrTrunc), P(_OrOp)]
         L.or_divide.argtypes = [P(_OrOp), ctypes.c_double, P(_OrOp)]
+        L.or_add_noise.argtypes = [P(_OrOp), ctypes.c_double, P(_OrOp)]
         L.or_norm2.argtypes = [P(_OrOp)]
         L.or_norm2.restype = ctypes.c_double
         L.or_inner.argtypes = [P(_OrOp), P(_OrOp), P(ctypes.c_double), P(ctypes.c_double)]
@@ -205,6 +206,42 @@ def divide(O: HostOp, b: float) -> HostOp:
     o, out = _Marshalled(O), _OrOp()
     _check(lib().or_divide(ctypes.byref(o.s), float(b), ctypes.byref(out)))
     return _take(out, O.n_qubits)
+
+
+def add_noise(O: HostOp, lam: float) -> HostOp:
+    """Depolarizing noise: every coefficient times exp(-lam * length)."""
+    o, out = _Marshalled(O), _OrOp()
+    _check(lib().or_add_noise(ctypes.byref(o.s), float(lam), ctypes.byref(out)))
+    return _take(out, O.n_qubits)
+
+
+def coefficients(O: HostOp, Q: HostOp) -> np.ndarray:
+    """O's coefficient of each string of Q (0 where O lacks it)."""
+    d = O.as_dict()
+    return np.array([d.get(k, 0j) for k in Q.keys()], dtype=complex)
+
+
+def evolve_noisy(H: HostOp, O0: HostOp, dt: float, steps: int, max_strings: int,
+                 noise: float, probes: HostOp | None = None, max_len: int = 0):
+    """The noisy Heisenberg loop of the Heisenberg section: per step an RK4
+    step with stages truncated to max_strings (O0 kept), the depolarizing
+    channel exp(-noise dt length), and a trim to max_strings (O0 kept).
+    Returns (O(t_steps), S[k] = <O0, O(t_k)>/<O0, O0>, P[k] = coefficients of
+    the probe strings in O(t_k)), k = 0..steps."""
+    t = Trunc(max_len=max_len, max_strings=max_strings, keep=O0)
+    n0 = norm2(O0)
+    S, P, cur = [], [], O0
+
+    def record(op):
+        S.append(inner(O0, op) / n0)
+        if probes is not None:
+            P.append(coefficients(op, probes))
+
+    record(cur)
+    for _ in range(steps):
+        cur = truncate(add_noise(rk4_step(H, cur, dt, t), noise * dt), t)
+        record(cur)
+    return cur, S, P
 
 
 def norm2(O: HostOp) -> float:

@@ -417,6 +417,28 @@ static int string_length(const uint64_t x[2], const uint64_t z[2], int n_qubits)
   return len;
 }
 
+/* Depolarizing noise (Heisenberg time evolution section): the string of
+ * length w is transmitted with rate exp(-lambda w), lambda = eps dt per step.
+ * Each coefficient is multiplied by that factor; exact zeros are dropped. */
+int or_add_noise(const or_op *in, double lambda, or_op *out) {
+  if (op_alloc(out, in->n_qubits, in->n)) return OR_ENOMEM;
+  int64_t m = 0;
+  for (int64_t k = 0; k < in->n; k++) {
+    uint64_t x[2], z[2];
+    get_key(in, k, x, z);
+    const double f = exp(-lambda * (double)string_length(x, z, in->n_qubits));
+    double re = in->re[k] * f, im = in->im[k] * f;
+    if (is_zero(re, im)) continue;
+    memcpy(&out->x[2 * m], x, 2 * sizeof(uint64_t));
+    memcpy(&out->z[2 * m], z, 2 * sizeof(uint64_t));
+    out->re[m] = re;
+    out->im[m] = im;
+    m++;
+  }
+  out->n = m;
+  return OR_OK;
+}
+
 static int in_keep(const or_op *keep, const uint64_t x[2], const uint64_t z[2]) {
   if (!keep) return 0;
   for (int64_t k = 0; k < keep->n; k++) {

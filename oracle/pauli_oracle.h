@@ -55,6 +55,7 @@ int or_add(const or_op *A, double ar, double ai, const or_op *B, double br, doub
            or_op *out);
 int or_truncate(const or_op *in, const or_trunc *t, or_op *out);
 int or_divide(const or_op *in, double b, or_op *out);
+int or_add_noise(const or_op *in, double lambda, or_op *out);
 double or_norm2(const or_op *A);
 void or_inner(const or_op *A, const or_op *B, double *re, double *im);
 double or_exact_sum(const double *v, int64_t n);

@@ -12,7 +12,7 @@ PAULI_OK, PAULI_EINVAL, PAULI_ECAPACITY, PAULI_EWORKSPACE, PAULI_BREAKDOWN, PAUL
 PAULI_C128, PAULI_C64K = 0, 1
 
 EXPORTS = ["pauli_commutator", "pauli_multiply", "pauli_trace", "pauli_add", "pauli_truncate",
-           "pauli_canonicalize",
+           "pauli_canonicalize", "pauli_add_noise", "pauli_coefficients",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
            "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_only", "pauli_profile_read",
            "pauli_last_stats", "pauli_order_keys", "pauli_strings_from_order_keys",
@@ -66,6 +66,8 @@ def load():
     L.pauli_commutator.argtypes = [op, op, tr, op, ws, vp]
     L.pauli_multiply.argtypes = [op, op, tr, op, ws, vp]
     L.pauli_trace.argtypes = [op, P(d), ws, vp]
+    L.pauli_add_noise.argtypes = [op, d, vp]
+    L.pauli_coefficients.argtypes = [op, op, P(d), ws, vp]
     L.pauli_add.argtypes = [op, d, d, op, d, d, tr, op, ws, vp]
     L.pauli_truncate.argtypes = [op, tr, op, ws, vp]
     L.pauli_canonicalize.argtypes = [op, op, ws, vp]

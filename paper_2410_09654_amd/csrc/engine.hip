@@ -1187,6 +1187,56 @@ int pauli_rk4_step(const pauli_op* H, const pauli_op* O, double dt, const pauli_
   return run_call(ar, ws, stream, c);
 }
 
+int pauli_add_noise(pauli_op* A, double lambda, void* stream_) {
+  if (check_op(A, false) || !(lambda >= 0.0)) return PAULI_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (A->size == 0) return PAULI_OK;
+  NoiseTable t;
+  for (int w = 0; w < NOISE_TABLE; w++) t.f[w] = std::exp(-lambda * (double)w);
+  const int W = words_of(A->n_qubits);
+  const int blocks = (int)std::min<int64_t>((A->size + 255) / 256, 8192);
+  const int f32 = A->dtype == PAULI_C64K ? 1 : 0;
+  if (W == 1)
+    LAUNCH("k_add_noise", k_add_noise<1>, blocks, 256, A->x, A->z, A->capacity, A->size,
+           A->coef, f32, t);
+  else
+    LAUNCH("k_add_noise", k_add_noise<2>, blocks, 256, A->x, A->z, A->capacity, A->size,
+           A->coef, f32, t);
+  return PAULI_OK;
+}
+
+int pauli_coefficients(const pauli_op* A, const pauli_op* Q, double* out, pauli_ws* ws,
+                       void* stream_) {
+  if (!ws || check_op(A, false) || check_op(Q, false) || (Q->size && !out)) return PAULI_EINVAL;
+  if (A->n_qubits != Q->n_qubits) return PAULI_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (Q->size == 0) return PAULI_OK;
+  const int W = words_of(A->n_qubits);
+  Arena ar = make_arena(ws);
+  void* keys = ar.take((size_t)std::max<int64_t>(A->size, 1) * 16 * W);
+  double2* res = (double2*)ar.take((size_t)Q->size * 16);
+  if (ar.short_) return ws_short(ar, ws);
+  const int64_t ba = (std::max<int64_t>(A->size, 1) + 255) / 256, bq = (Q->size + 255) / 256;
+  const int af32 = A->dtype == PAULI_C64K ? 1 : 0;
+  if (W == 1) {
+    if (A->size)
+      LAUNCH("k_order_keys", k_order_keys<1>, ba, 256, A->x, A->z, A->capacity, A->size,
+             reinterpret_cast<Key<1>*>(keys));
+    LAUNCH("k_lookup", k_lookup<1>, bq, 256, reinterpret_cast<const Key<1>*>(keys), A->coef,
+           af32, A->size, Q->x, Q->z, Q->capacity, Q->size, res);
+  } else {
+    if (A->size)
+      LAUNCH("k_order_keys", k_order_keys<2>, ba, 256, A->x, A->z, A->capacity, A->size,
+             reinterpret_cast<Key<2>*>(keys));
+    LAUNCH("k_lookup", k_lookup<2>, bq, 256, reinterpret_cast<const Key<2>*>(keys), A->coef,
+           af32, A->size, Q->x, Q->z, Q->capacity, Q->size, res);
+  }
+  HIP_TRY(hipMemcpyAsync(out, res, (size_t)Q->size * 16, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  return PAULI_OK;
+}
+
 int pauli_order_keys(const pauli_op* A, uint64_t* keys, void* stream_) {
   if (!keys || check_op(A, false)) return PAULI_EINVAL;
   hipStream_t stream = (hipStream_t)stream_;

@@ -1806,6 +1806,70 @@ __global__ void k_mix_keys(const uint64_t* x, const uint64_t* z, int64_t cap, in
   }
 }
 
+// Depolarizing noise in place: c_k *= f[len_k], f[w] = exp(-lambda w)
+// computed on the host (len = sites with x or z set).  FP32 coefficients are
+// scaled in double and rounded once.
+constexpr int NOISE_TABLE = 129;  // lengths 0..128
+struct NoiseTable {
+  double f[NOISE_TABLE];
+};
+template <int W>
+__global__ __launch_bounds__(256) void k_add_noise(const uint64_t* x, const uint64_t* z,
+                                                   int64_t cap, int64_t n, void* coef, int f32,
+                                                   NoiseTable t) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    int len = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++) len += __popcll(x[(size_t)w * cap + i] | z[(size_t)w * cap + i]);
+    const double f = t.f[len];
+    if (f32) {
+      float2* c = reinterpret_cast<float2*>(coef) + i;
+      const float2 v = *c;
+      *c = make_float2((float)((double)v.x * f), (float)((double)v.y * f));
+    } else {
+      double2* c = reinterpret_cast<double2*>(coef) + i;
+      const double2 v = *c;
+      *c = make_double2(v.x * f, v.y * f);
+    }
+  }
+}
+
+// Coefficients in A (canonical: ascending order keys `ak`) of the strings of
+// Q: out[q] = A's coefficient of Q's string q, or 0 when A lacks it.
+template <int W>
+__global__ __launch_bounds__(256) void k_lookup(const Key<W>* ak, const void* acoef, int af32,
+                                                int64_t na, const uint64_t* qx,
+                                                const uint64_t* qz, int64_t qcap, int64_t nq,
+                                                double2* out) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nq) return;
+  Key<W> raw;
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    raw.w[w] = qx[(size_t)w * qcap + q];
+    raw.w[W + w] = qz[(size_t)w * qcap + q];
+  }
+  const Key<W> mk = mix_key<W>(raw);
+  int64_t lo = 0, hi = na;
+  double2 v = make_double2(0.0, 0.0);
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int c = key_cmp<W>(ak[mid], mk);
+    if (c == 0) {
+      if (af32) {
+        const float2 f = reinterpret_cast<const float2*>(acoef)[mid];
+        v = make_double2((double)f.x, (double)f.y);
+      } else {
+        v = reinterpret_cast<const double2*>(acoef)[mid];
+      }
+      break;
+    }
+    if (c < 0) lo = mid + 1;
+    else hi = mid;
+  }
+  out[q] = v;
+}
+
 // Order keys of an operator's strings, and the strings of order keys.
 template <int W>
 __global__ void k_order_keys(const uint64_t* x, const uint64_t* z, int64_t cap, int64_t n,

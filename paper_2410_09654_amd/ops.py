@@ -234,6 +234,32 @@ def trace(A: PauliOp, ws: Workspace | None = None) -> complex:
     return complex(r[0], r[1])
 
 
+def add_noise(A: PauliOp, lam: float) -> PauliOp:
+    """Depolarizing noise in place: c *= exp(-lam * length); returns A."""
+    L = _lib.load()
+    As = A.c_struct()
+    st = L.pauli_add_noise(ctypes.byref(As), float(lam), _stream_handle())
+    if st != PAULI_OK:
+        raise PauliError(st, "pauli_add_noise", _lib.last_error())
+    return A
+
+
+def coefficients(A: PauliOp, Q: PauliOp, ws: Workspace | None = None) -> np.ndarray:
+    """complex128 [Q.size]: A's coefficient of each string of Q (0 if absent)."""
+    L = _lib.load()
+    ws = ws or default_workspace(A.device)
+    As, Qs = A.c_struct(), Q.c_struct()
+    r = (ctypes.c_double * (2 * max(Q.size, 1)))()
+
+    def fn(wss):
+        return L.pauli_coefficients(ctypes.byref(As), ctypes.byref(Qs), r, ctypes.byref(wss),
+                                    _stream_handle()), None
+
+    _call("pauli_coefficients", fn, ws, None)
+    v = np.frombuffer(r, dtype=np.float64)[:2 * Q.size]
+    return v[0::2] + 1j * v[1::2]
+
+
 def add(A: PauliOp, alpha: complex, B: PauliOp, beta: complex, trunc: Trunc | None = None,
         out: PauliOp | None = None, ws: Workspace | None = None) -> PauliOp:
     L = _lib.load()

@@ -149,6 +149,35 @@ def test_moments_vs_dense_matrix_powers(n):
     assert abs(mus[1] - float(np.sum(np.abs(H.coef) ** 2))) < 1e-12
 
 
+@pytest.mark.parametrize("n,lam,seed", [(2, 0.3, 61), (3, 0.05, 62), (4, 1.1, 63)])
+def test_noise_vs_dense_depolarizing_channel(n, lam, seed):
+    """Per-string factor exp(-lam * length) equals the product of single-qubit
+    depolarizing channels (1-p) M + p/3 (X M X + Y M Y + Z M Z) with
+    1 - 4p/3 = exp(-lam), applied to the dense matrix."""
+    O = wl.random_operator(n, 12, seed=seed, density=0.7)
+    M = dense(O)
+    p = 3.0 * (1.0 - math.exp(-lam)) / 4.0
+    for q in range(1, n + 1):
+        P = [dense(wl.from_terms(n, [(1.0, [(s, q)])])) for s in "XYZ"]
+        M = (1 - p) * M + (p / 3) * sum(Pk @ M @ Pk for Pk in P)
+    assert np.abs(dense(oracle.add_noise(O, lam)) - M).max() < 1e-13
+
+
+def test_noisy_evolution_total_z_decays_as_exp():
+    """XXZnnn conserves total Z, RK4 stages are commutators and the channel
+    scales the weight-1 strings by exp(-eps dt): n(t_k) = sum_j Tr[Z_1(t_k)
+    Z_j]/2^N = exp(-eps k dt) exactly (no truncation), while S(t) decays."""
+    n, eps, dt, steps = 8, 0.2, 0.1, 10
+    H = wl.xxz_nnn(n)
+    O0 = wl.from_terms(n, [(1.0, [("Z", 1)])])
+    probes = wl.from_terms(n, [(1.0, [("Z", j)]) for j in range(1, n + 1)])
+    _, S, P = oracle.evolve_noisy(H, O0, dt, steps, 0, eps, probes)
+    for k in range(steps + 1):
+        assert abs(sum(P[k]) - math.exp(-eps * k * dt)) < 1e-12, k
+        assert abs(S[k] - P[k][0]) < 1e-15
+    assert abs(S[-1]) < 0.95 * math.exp(-eps * steps * dt)
+
+
 def test_add_norm_inner_vs_dense():
     n = 5
     A = wl.random_operator(n, 20, seed=11)

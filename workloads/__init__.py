@@ -214,6 +214,33 @@ def xxz_random_field(n: int = 128, delta: float = 0.5, field: float = 0.3,
     return from_terms(n, terms), r
 
 
+def xxz_nnn(n: int = 30, delta: float = 2.0, gamma: float = 0.5) -> HostOp:
+    """Periodic next-nearest-neighbour XXZ chain of the Heisenberg section:
+    sum_i (X_i X_{i+1} + Y_i Y_{i+1} + delta Z_i Z_{i+1})
+    + gamma sum_i (X_i X_{i+2} + Y_i Y_{i+2} + delta Z_i Z_{i+2}), sites mod n
+    (the printed listing pairs site j with itself; the equation pairs it with
+    j+1 and j+2).  |H| = 6n for n >= 5."""
+    def s(j):
+        return (j - 1) % n + 1
+    terms = []
+    for j in range(1, n + 1):
+        for d, g in ((1, 1.0), (2, gamma)):
+            terms.append((g, [("X", j), ("X", s(j + d))]))
+            terms.append((g, [("Y", j), ("Y", s(j + d))]))
+            terms.append((g * delta, [("Z", j), ("Z", s(j + d))]))
+    return from_terms(n, terms)
+
+
+def config_noisy_xxz():
+    """Noisy diffusion run: N=30 periodic XXZnnn (delta=2, gamma=1/2),
+    O0 = Z_1, dt=0.05, 200 steps (t=10), M=2^18, eps=0.01, probes Z_1..Z_N."""
+    n = 30
+    H = xxz_nnn(n)
+    O0 = from_terms(n, [(1.0, [("Z", 1)])])
+    probes = from_terms(n, [(1.0, [("Z", j)]) for j in range(1, n + 1)])
+    return H, O0, probes
+
+
 def single_site_sum(n: int, pauli: str, coef: float) -> HostOp:
     """coef * sum_i P_i (e.g. sum X_i / sqrt(N))."""
     return from_terms(n, [(coef, [(pauli, i)]) for i in range(1, n + 1)])
