@@ -39,10 +39,11 @@ def parse():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--workload", default="commutator",
                     choices=["commutator", "lanczos-split", "rk4-tfim", "lanczos-small", "moments",
-                             "surrogate"],
+                             "noisy-xxz", "surrogate"],
                     help="commutator: the benchmark line (default); the others run the "
-                         "Lanczos precision-split, RK4, small-Lanczos, spectral-moment and "
-                         "b_n-surrogate configurations and print their own result line")
+                         "Lanczos precision-split, RK4, small-Lanczos, spectral-moment, "
+                         "noisy-diffusion and b_n-surrogate configurations and print their own "
+                         "result line")
     ap.add_argument("--max-strings", type=int, default=0,
                     help="truncation M for lanczos-split / rk4-tfim (0: the configuration's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -247,6 +248,66 @@ def run_moments(args):
     print(json.dumps(line), flush=True)
 
 
+def run_noisy_xxz(args):
+    """Noisy diffusion on the periodic next-nearest-neighbour XXZ chain
+    (N=30, delta=2, gamma=1/2): O0 = Z_1, dt=0.05, 200 RK4 steps (t = 10),
+    M = 2^18 with O0 kept, depolarizing eps = 0.01; S(t), the two-point
+    correlators S_{1-j}(t) and n(t) = sum_j S_{1-j}(t) (exp(-eps t) without
+    truncation)."""
+    import math
+    import torch
+    import workloads as wl
+    import paper_2410_09654_amd as pk
+    H_host, O0_host, probes_host = wl.config_noisy_xxz()
+    n = H_host.n_qubits
+    dt, steps, eps = 0.05, args.steps or 200, 0.01
+    M = args.max_strings or (1 << 18)
+    H = pk.PauliOp.from_raw(n, H_host.x, H_host.z, H_host.coef)
+    O0 = pk.PauliOp.from_host(O0_host)
+    probes = pk.PauliOp.from_raw(n, probes_host.x, probes_host.z, probes_host.coef)
+    ws = pk.Workspace(1 << 30)
+    pk.evolve_noisy(H, O0, dt, 2, M, eps, probes=probes, ws=ws)  # warm-up
+    def progress(k, op):
+        if k % 20 == 0:
+            print(f"step {k}: {op.size} strings, {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    O, S, P = pk.evolve_noisy(H, O0, dt, steps, M, eps, probes=probes, ws=ws, observe=progress)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nt = [float(np.sum(p).real) for p in P]
+    line = {"workload": "noisy XXZnnn diffusion: N=30 periodic, delta=2, gamma=1/2, O0 = Z_1, "
+                        "dt=0.05, eps=0.01, M=2^18 (O0 kept)",
+            "steps": steps, "max_strings": M, "seconds": wall, "ms_per_step": 1e3 * wall / steps,
+            "final_strings": O.size,
+            "S": [float(v.real) for v in S[::10]],
+            "S_1j_final": [float(v.real) for v in P[-1]],
+            "n_t_over_exp": [nt[k] / math.exp(-eps * k * dt) for k in range(0, steps + 1, 20)],
+            "max_abs_n_minus_exp": max(abs(nt[k] - math.exp(-eps * k * dt))
+                                       for k in range(steps + 1))}
+    if args.cpu_sample > 0:
+        import oracle
+        # one noisy step, oracle and GPU, from a sample of the evolved state: its
+        # 4096 largest strings (a full-M step would take minutes on one core)
+        Ms = 4096
+        Os = pk.truncate(O, pk.Trunc(max_strings=Ms), ws=ws)
+        hs = Os.to_host()
+        print(f"oracle step from {hs.n} strings", file=sys.stderr, flush=True)
+        tc = time.perf_counter()
+        oracle.evolve_noisy(H_host, hs, dt, 1, Ms, eps)
+        tcpu = time.perf_counter() - tc
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        pk.evolve_noisy(H, Os, dt, 1, Ms, eps, ws=ws)
+        torch.cuda.synchronize()
+        tgpu = time.perf_counter() - tg
+        line["step_from_4096_string_sample"] = {"strings": hs.n, "oracle_seconds": tcpu,
+                                                "gpu_seconds": tgpu, "cores": 1}
+    print(json.dumps(line), flush=True)
+
+
 MLP_FWD_FLOP = 2 * (16 * 256 + 256 * 256 + 256 * 16)  # per window
 MLP_TRAIN_FLOP = 3 * MLP_FWD_FLOP  # forward, input gradient, weight gradient
 
@@ -332,7 +393,7 @@ def main():
         torch.cuda.set_device(0)
         {"lanczos-split": run_lanczos_split, "rk4-tfim": run_rk4_tfim,
          "lanczos-small": run_lanczos_small, "surrogate": run_surrogate,
-         "moments": run_moments}[args.workload](args)
+         "moments": run_moments, "noisy-xxz": run_noisy_xxz}[args.workload](args)
         return
     import torch
     import workloads as wl

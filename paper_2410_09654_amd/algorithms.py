@@ -62,14 +62,15 @@ def moments(H: PauliOp, kmax: int, trunc: Trunc | None = None, ws: Workspace | N
 
 def evolve_noisy(H: PauliOp, O0: PauliOp, dt: float, steps: int, max_strings: int,
                  noise: float, probes: PauliOp | None = None, max_len: int = 0,
-                 ws: Workspace | None = None):
+                 ws: Workspace | None = None, observe=None):
     """Noisy Heisenberg evolution as the Heisenberg section runs it: per step
     one RK4 step with its stages truncated to `max_strings` (O0 kept), the
     depolarizing channel exp(-noise dt length), and a trim to `max_strings`
     (O0 kept).  Returns (O(t_steps), S, P): S[k] = Tr(O(t_k) O0^dagger) /
     Tr(O0 O0^dagger) for k = 0..steps, and, when `probes` is given, P[k] =
     the coefficients in O(t_k) of the probe strings (with O0 = Z_i and probes
-    Z_j: the two-point correlators S_{i-j}(t_k))."""
+    Z_j: the two-point correlators S_{i-j}(t_k)).  `observe(k, O(t_k))`, if
+    given, is called after every step."""
     ws = ws or ops.default_workspace(O0.device)
     tr = Trunc(max_len=max_len, max_strings=max_strings, keep=O0)
     n0 = ops.norm2(O0, ws=ws)
@@ -87,4 +88,6 @@ def evolve_noisy(H: PauliOp, O0: PauliOp, dt: float, steps: int, max_strings: in
         ops.add_noise(cur, noise * dt)
         cur = ops.truncate(cur, tr, ws=ws)
         record(cur)
+        if observe is not None:
+            observe(len(S) - 1, cur)
     return cur, S, P
