@@ -8,6 +8,7 @@ plus `mlp`, a float64 NumPy reference of the b_n surrogate network.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -67,6 +68,14 @@ def lib():
         L.or_truncate.argtypes = [P(_OrOp), P(_OrTrunc), P(_OrOp)]
         L.or_divide.argtypes = [P(_OrOp), ctypes.c_double, P(_OrOp)]
         L.or_add_noise.argtypes = [P(_OrOp), ctypes.c_double, P(_OrOp)]
+        U2 = ctypes.c_uint64 * 2
+        L.or_ts_canonical.argtypes = [ctypes.c_int, U2, U2, U2, U2]
+        L.or_ts_canonical.restype = None
+        L.or_ts_translate.argtypes = [ctypes.c_int, U2, U2, ctypes.c_int, U2, U2]
+        L.or_ts_translate.restype = None
+        L.or_commutator_ts.argtypes = [P(_OrOp), P(_OrOp), P(_OrOp)]
+        L.or_norm2_ts.argtypes = [P(_OrOp)]
+        L.or_norm2_ts.restype = ctypes.c_double
         L.or_norm2.argtypes = [P(_OrOp)]
         L.or_norm2.restype = ctypes.c_double
         L.or_inner.argtypes = [P(_OrOp), P(_OrOp), P(ctypes.c_double), P(ctypes.c_double)]
@@ -242,6 +251,94 @@ def evolve_noisy(H: HostOp, O0: HostOp, dt: float, steps: int, max_strings: int,
         cur = truncate(add_noise(rk4_step(H, cur, dt, t), noise * dt), t)
         record(cur)
     return cur, S, P
+
+
+# ---------------------------------------------------------------------------
+# Translation-symmetric operators on a periodic chain (Alg. 2): an operator
+# sum_k T_k(A0) is held as A0, one representative string per orbit.
+# ---------------------------------------------------------------------------
+def _words2(op: HostOp, k: int):
+    W = op.x.shape[1]
+    x = (ctypes.c_uint64 * 2)(*(list(int(v) for v in op.x[k]) + [0] * (2 - W)))
+    z = (ctypes.c_uint64 * 2)(*(list(int(v) for v in op.z[k]) + [0] * (2 - W)))
+    return x, z
+
+
+def _from_dict(n_qubits: int, d: dict) -> HostOp:
+    W = n_words(n_qubits)
+    items = [(k, c) for k, c in d.items() if c != 0]
+    x = np.array([k[:W] for k, _ in items], np.uint64).reshape(-1, W)
+    z = np.array([k[W:] for k, _ in items], np.uint64).reshape(-1, W)
+    return canonicalize(HostOp(n_qubits, x, z, np.array([c for _, c in items], complex)))
+
+
+def ts_representative(n_qubits: int, x2, z2):
+    """Shiftleft of Alg. 2: the orbit representative of one string."""
+    cx, cz = (ctypes.c_uint64 * 2)(), (ctypes.c_uint64 * 2)()
+    lib().or_ts_canonical(n_qubits, x2, z2, cx, cz)
+    return cx, cz
+
+
+def canonicalize_ts(op: HostOp) -> HostOp:
+    """Every string replaced by its orbit representative, duplicates summed."""
+    W, d = n_words(op.n_qubits), {}
+    for k in range(op.n):
+        cx, cz = ts_representative(op.n_qubits, *_words2(op, k))
+        key = tuple(int(cx[w]) for w in range(W)) + tuple(int(cz[w]) for w in range(W))
+        d[key] = d.get(key, 0) + complex(op.coef[k])
+    return _from_dict(op.n_qubits, d)
+
+
+def expand_ts(op: HostOp) -> HostOp:
+    """The full operator sum_k T_k(op) on the periodic chain."""
+    N, W, d = op.n_qubits, n_words(op.n_qubits), {}
+    for k in range(op.n):
+        x2, z2 = _words2(op, k)
+        for s in range(N):
+            ox, oz = (ctypes.c_uint64 * 2)(), (ctypes.c_uint64 * 2)()
+            lib().or_ts_translate(N, x2, z2, s, ox, oz)
+            key = tuple(int(ox[w]) for w in range(W)) + tuple(int(oz[w]) for w in range(W))
+            d[key] = d.get(key, 0) + complex(op.coef[k])
+    return _from_dict(N, d)
+
+
+def commutator_ts(H0: HostOp, O0: HostOp) -> HostOp:
+    """Representatives of [sum_k T_k(H0), sum_k T_k(O0)] (O0 representatives)."""
+    h, o, out = _Marshalled(H0), _Marshalled(O0), _OrOp()
+    _check(lib().or_commutator_ts(ctypes.byref(h.s), ctypes.byref(o.s), ctypes.byref(out)))
+    return _take(out, O0.n_qubits)
+
+
+def norm2_ts(O0: HostOp) -> float:
+    """||sum_k T_k(O0)||^2 / N (O0 representatives)."""
+    o = _Marshalled(O0)
+    r = lib().or_norm2_ts(ctypes.byref(o.s))
+    if r < 0:
+        raise RuntimeError("oracle error")
+    return r
+
+
+def lanczos_ts(H0: HostOp, O0: HostOp, steps: int, t: Trunc | None = None) -> list:
+    """Lanczos recursion on translation-symmetric operators (Krylov section,
+    with the Alg. 2 commutator): O'_n = [H, O_{n-1}] - b_{n-1} O_{n-2},
+    b_n = sqrt(norm2_ts(O'_n)), O_n = trunc(O'_n * fl(1/b_n)).  O0 must have
+    norm2_ts = 1."""
+    W = n_words(O0.n_qubits)
+    empty = HostOp(O0.n_qubits, np.zeros((0, W), np.uint64), np.zeros((0, W), np.uint64),
+                   np.zeros(0, complex))
+    bs, prev, cur, b_prev = [], empty, O0, 0.0
+    for _ in range(steps):
+        C = commutator_ts(H0, cur)
+        C = add(C, 1.0, prev, -b_prev)
+        b = math.sqrt(norm2_ts(C))
+        bs.append(b)
+        if b == 0.0:
+            break
+        nxt = add(C, 1.0 / b, empty, 0.0)
+        if t is not None:
+            nxt = truncate(nxt, t)
+        prev, cur, b_prev = cur, nxt, b
+    return bs
 
 
 def norm2(O: HostOp) -> float:

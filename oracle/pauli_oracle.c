@@ -366,6 +366,132 @@ int or_product(const or_op *A, const or_op *B, or_op *out) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Translation-symmetric operators on a periodic chain of N sites (Alg. 2):  */
+/* the operator sum_k T_k(A0) is stored as A0, one representative string per */
+/* translation orbit.  T_k moves site j to site (j + k) mod N.  The          */
+/* representative (Shiftleft) is the rotation whose occupied-site pattern,   */
+/* read as an N-bit number with site j as bit j, is smallest; ties by the    */
+/* x pattern, then the z pattern, read the same way.                         */
+/* ------------------------------------------------------------------------ */
+static void ts_translate(int N, const uint64_t x[2], const uint64_t z[2], int k, uint64_t ox[2],
+                         uint64_t oz[2]) {
+  ox[0] = ox[1] = oz[0] = oz[1] = 0;
+  for (int j = 0; j < N; j++) set_site(ox, oz, (j + k) % N, site_code(x, z, j));
+}
+
+void or_ts_translate(int N, const uint64_t x[2], const uint64_t z[2], int k, uint64_t ox[2],
+                     uint64_t oz[2]) {
+  ts_translate(N, x, z, k, ox, oz);
+}
+
+/* 2-word numbers, most significant word first */
+static int num_cmp(const uint64_t a[2], const uint64_t b[2]) {
+  if (a[1] != b[1]) return a[1] < b[1] ? -1 : 1;
+  if (a[0] != b[0]) return a[0] < b[0] ? -1 : 1;
+  return 0;
+}
+
+void or_ts_canonical(int N, const uint64_t x[2], const uint64_t z[2], uint64_t cx[2],
+                     uint64_t cz[2]) {
+  uint64_t bx[2] = {x[0], x[1]}, bz[2] = {z[0], z[1]};
+  uint64_t bm[2] = {x[0] | z[0], x[1] | z[1]};
+  for (int k = 1; k < N; k++) {
+    uint64_t tx[2], tz[2];
+    ts_translate(N, x, z, k, tx, tz);
+    uint64_t tm[2] = {tx[0] | tz[0], tx[1] | tz[1]};
+    int c = num_cmp(tm, bm);
+    if (c == 0) c = num_cmp(tx, bx);
+    if (c == 0) c = num_cmp(tz, bz);
+    if (c < 0) {
+      memcpy(bx, tx, sizeof(bx));
+      memcpy(bz, tz, sizeof(bz));
+      memcpy(bm, tm, sizeof(bm));
+    }
+  }
+  memcpy(cx, bx, sizeof(bx));
+  memcpy(cz, bz, sizeof(bz));
+}
+
+/* number of k in [0, N) with T_k(s) = s */
+static int ts_stabilizer(int N, const uint64_t x[2], const uint64_t z[2]) {
+  int s = 0;
+  for (int k = 0; k < N; k++) {
+    uint64_t tx[2], tz[2];
+    ts_translate(N, x, z, k, tx, tz);
+    if (!key_cmp(tx, tz, x, z)) s++;
+  }
+  return s;
+}
+
+/* [H, O] for H = sum_k T_k(H0) and O = sum_k T_k(O0): H0 expanded to the list
+ * T_0(h_0), T_1(h_0), ..., T_{N-1}(h_0), T_0(h_1), ... (that list's order is
+ * the summation order), every anticommuting pair with an O0 string gives
+ * 2 i^e h c on the representative of its product. */
+int or_commutator_ts(const or_op *H0, const or_op *O, or_op *out) {
+  int N = O->n_qubits;
+  if (H0->n_qubits != N || N < 1 || N > 128) return OR_EINVAL;
+  recbuf b = {0};
+  for (int64_t a = 0; a < H0->n; a++) {
+    uint64_t hx[2], hz[2];
+    get_key(H0, a, hx, hz);
+    for (int k = 0; k < N; k++) {
+      uint64_t ax[2], az[2];
+      ts_translate(N, hx, hz, k, ax, az);
+      for (int64_t j = 0; j < O->n; j++) {
+        uint64_t bx[2], bz[2], cx[2], cz[2], dx[2], dz[2];
+        get_key(O, j, bx, bz);
+        int kab, kba;
+        or_string_product(N, ax, az, bx, bz, cx, cz, &kab);
+        or_string_product(N, bx, bz, ax, az, dx, dz, &kba);
+        if (kab == kba) continue;
+        double pr, pi, qr, qi, dr, di, hr, hi;
+        ipow(kab, &pr, &pi);
+        ipow(kba, &qr, &qi);
+        dr = pr - qr;
+        di = pi - qi;
+        cmul(H0->re[a], H0->im[a], O->re[j], O->im[j], &hr, &hi);
+        rec_t r;
+        or_ts_canonical(N, cx, cz, r.x, r.z);
+        r.idx = a * N + k;
+        cmul(dr, di, hr, hi, &r.re, &r.im);
+        if (rb_push(&b, &r)) return OR_ENOMEM;
+      }
+    }
+  }
+  int rc = fold_records(&b, N, out);
+  free(b.r);
+  return rc;
+}
+
+/* ||sum_k T_k(A0)||^2 / N = sum over representatives of stab(s) |c_s|^2,
+ * exactly accumulated and rounded once (A0: one string per orbit). */
+double or_norm2_ts(const or_op *A) {
+  int *st = (int *)malloc((size_t)(A->n > 0 ? A->n : 1) * sizeof(int));
+  if (!st) return -1.0;
+  int64_t m = 0;
+  for (int64_t k = 0; k < A->n; k++) {
+    uint64_t x[2], z[2];
+    get_key(A, k, x, z);
+    st[k] = ts_stabilizer(A->n_qubits, x, z);
+    m += st[k];
+  }
+  double *v = (double *)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+  if (!v) {
+    free(st);
+    return -1.0;
+  }
+  int64_t t = 0;
+  for (int64_t k = 0; k < A->n; k++) {
+    const double w = A->re[k] * A->re[k] + A->im[k] * A->im[k];
+    for (int r = 0; r < st[k]; r++) v[t++] = w;
+  }
+  double r = or_exact_sum(v, m);
+  free(v);
+  free(st);
+  return r;
+}
+
+/* ------------------------------------------------------------------------ */
 /* alpha A + beta B: fl(fl(alpha a) + fl(beta b)); a missing side adds nothing */
 /* ------------------------------------------------------------------------ */
 int or_add(const or_op *A, double ar, double ai, const or_op *B, double br, double bi,

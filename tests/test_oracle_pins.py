@@ -3,6 +3,7 @@ textbook Pauli matrices, dense 2^N matrices, exactly rounded sums, the paper's
 printed worked example, closed forms of Lanczos coefficients and of one
 Runge-Kutta step.  CPU only.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -176,6 +177,82 @@ def test_noisy_evolution_total_z_decays_as_exp():
         assert abs(sum(P[k]) - math.exp(-eps * k * dt)) < 1e-12, k
         assert abs(S[k] - P[k][0]) < 1e-15
     assert abs(S[-1]) < 0.95 * math.exp(-eps * steps * dt)
+
+
+# ---------------------------------------------------------------------------
+# Translation-symmetric operators (Alg. 2)
+# ---------------------------------------------------------------------------
+def _bits(op, k):
+    W = op.x.shape[1]
+    x = sum(int(op.x[k][w]) << (64 * w) for w in range(W))
+    z = sum(int(op.z[k][w]) << (64 * w) for w in range(W))
+    return x, z
+
+
+def _rot(v, k, n):
+    """site j -> site (j + k) mod n of an n-bit integer"""
+    k %= n
+    return ((v << k) | (v >> (n - k))) & ((1 << n) - 1) if k else v
+
+
+def _w2(v):
+    return (ctypes.c_uint64 * 2)(v & (2 ** 64 - 1), v >> 64)
+
+
+@pytest.mark.parametrize("n,seed", [(6, 81), (10, 82), (64, 83), (70, 84)])
+def test_ts_representative_brute_force(n, seed):
+    """Shiftleft: the same representative for every translate, and it is the
+    rotation with the smallest (occupied pattern, x, z) as n-bit numbers."""
+    O = wl.random_operator(n, 40, seed=seed, density=min(1.0, 4.0 / n))
+    for k in range(O.n):
+        x, z = _bits(O, k)
+        best = min(((_rot(x, r, n) | _rot(z, r, n)), _rot(x, r, n), _rot(z, r, n))
+                   for r in range(n))
+        for r in (0, 1, n // 2, n - 1):
+            cx, cz = oracle.ts_representative(n, _w2(_rot(x, r, n)), _w2(_rot(z, r, n)))
+            got = (int(cx[0]) | int(cx[1]) << 64, int(cz[0]) | int(cz[1]) << 64)
+            assert got == (best[1], best[2])
+        assert best[0] & 1  # the representative starts on the first site
+
+
+@pytest.mark.parametrize("n,seed", [(6, 91), (8, 92)])
+def test_ts_commutator_expands_to_full_commutator(n, seed):
+    """The Alg. 2 commutator of representatives, expanded over translations,
+    equals the plain commutator of the expanded operators."""
+    H0 = wl.from_terms(n, [(1.0, [("Z", 1), ("Z", 2)]), (1.05, [("X", 1)]), (0.5, [("Z", 1)]),
+                           (0.3, [("X", 1), ("Y", 3)])])
+    O0 = oracle.canonicalize_ts(wl.random_operator(n, 15, seed=seed, density=0.5))
+    want = oracle.commutator(oracle.expand_ts(H0), oracle.expand_ts(O0))
+    got = oracle.expand_ts(oracle.commutator_ts(H0, O0))
+    gd, wd = got.as_dict(), want.as_dict()
+    assert set(gd) == set(wd)
+    for k, v in wd.items():
+        assert abs(gd[k] - v) <= 1e-12 * max(1.0, abs(v))
+
+
+def test_ts_norm_is_full_norm_over_n():
+    """norm2_ts(A0) = ||sum_k T_k(A0)||^2 / N, strings with a nontrivial
+    stabilizer (period 2 and 1) included."""
+    n = 8
+    A0 = oracle.canonicalize_ts(wl.from_terms(n, [
+        (0.5 + 0.25j, [("Z", 1), ("Z", 2)]), (1.5, [("X", 1)]),
+        (0.75, [("X", j) for j in range(1, n + 1, 2)]),       # period 2
+        (-0.4j, [("Z", j) for j in range(1, n + 1)])]))        # period 1
+    assert abs(oracle.norm2_ts(A0) - oracle.norm2(oracle.expand_ts(A0)) / n) < 1e-13
+
+
+def test_ts_lanczos_equals_full_periodic_lanczos():
+    """b_n of the translation-symmetric recursion (O0 = Z_1 as representative)
+    equal those of the plain recursion on the periodic chain with
+    O0 = sum_j Z_j / sqrt(N) (the norm's factor N drops out of the b_n)."""
+    n = 8
+    H0 = wl.from_terms(n, [(1.0, [("Z", 1), ("Z", 2)]), (1.05, [("X", 1)]), (0.5, [("Z", 1)])])
+    Z1 = wl.from_terms(n, [(1.0, [("Z", 1)])])
+    b_ts = oracle.lanczos_ts(H0, Z1, 8)
+    Of = wl.single_site_sum(n, "Z", 1 / math.sqrt(n))
+    b_full = oracle.lanczos(oracle.expand_ts(H0), Of, 8)
+    assert len(b_ts) == len(b_full) == 8
+    assert np.allclose(b_ts, b_full, rtol=1e-12, atol=0)
 
 
 def test_add_norm_inner_vs_dense():
