@@ -119,6 +119,29 @@ int pauli_commutator(const pauli_op *H, const pauli_op *O, const pauli_trunc *t,
 int pauli_multiply(const pauli_op *A, const pauli_op *B, const pauli_trunc *t,
                    pauli_op *out, pauli_ws *ws, void *stream);
 
+/* Translation-symmetric operators on a periodic chain of N = n_qubits sites
+ * (Methods, Alg. 2): the operator sum_k T_k(A0), T_k moving site j to
+ * (j + k) mod N, is held as A0 with one representative string per
+ * translation orbit.  The representative of a string is its rotation whose
+ * occupied-site pattern (x | z, site j = bit j) is the smallest N-bit number,
+ * ties by x, then z (it starts on the first site).
+ *
+ * pauli_commutator_ts1d: representatives of trunc([sum_k T_k(H0), sum_k T_k(O)])
+ * = sum over k, h, o of [T_k(h), o] with every product replaced by its
+ * representative; H0 is listed over its translations as T_0(h_0), ...,
+ * T_{N-1}(h_0), T_0(h_1), ... and each string's contributions are summed in
+ * that order.  O must hold representatives (pauli_canonicalize_ts1d);
+ * H0 any strings (PAULI_C128, N |H0| below one merge bucket's capacity).
+ * pauli_canonicalize_ts1d: every string replaced by its representative,
+ * duplicates summed in input order, canonical order.
+ * pauli_norm2_ts1d: *out (host) = ||sum_k T_k(A)||^2 / N = sum over A's
+ * representatives of stab(s)|c_s|^2 (stab: translations leaving s unchanged);
+ * the b_n of a Lanczos recursion are the same under this norm. */
+int pauli_commutator_ts1d(const pauli_op *H0, const pauli_op *O, const pauli_trunc *t,
+                          pauli_op *out, pauli_ws *ws, void *stream);
+int pauli_canonicalize_ts1d(const pauli_op *in, pauli_op *out, pauli_ws *ws, void *stream);
+int pauli_norm2_ts1d(const pauli_op *A, double *out, pauli_ws *ws, void *stream);
+
 /* out[0] + i out[1] (host) = Tr(A)/2^N: the coefficient of the identity string
  * (0 when A has none).  A's strings must be distinct.  With pauli_multiply it
  * gives the moments Tr(H^k)/2^N of the Conclusion's spectral outlook. */

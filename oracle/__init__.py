@@ -70,7 +70,7 @@ def lib():
         L.or_add_noise.argtypes = [P(_OrOp), ctypes.c_double, P(_OrOp)]
         U2 = ctypes.c_uint64 * 2
         L.or_ts_canonical.argtypes = [ctypes.c_int, U2, U2, U2, U2]
-        L.or_ts_canonical.restype = None
+        L.or_ts_canonical.restype = ctypes.c_int
         L.or_ts_translate.argtypes = [ctypes.c_int, U2, U2, ctypes.c_int, U2, U2]
         L.or_ts_translate.restype = None
         L.or_commutator_ts.argtypes = [P(_OrOp), P(_OrOp), P(_OrOp)]

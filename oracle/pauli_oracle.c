@@ -391,18 +391,22 @@ static int num_cmp(const uint64_t a[2], const uint64_t b[2]) {
   return 0;
 }
 
-void or_ts_canonical(int N, const uint64_t x[2], const uint64_t z[2], uint64_t cx[2],
-                     uint64_t cz[2]) {
+/* Returns the rotation r (the translation by N - r, moving site r to site 0)
+ * that gives the representative, the smallest r when several do. */
+int or_ts_canonical(int N, const uint64_t x[2], const uint64_t z[2], uint64_t cx[2],
+                    uint64_t cz[2]) {
   uint64_t bx[2] = {x[0], x[1]}, bz[2] = {z[0], z[1]};
   uint64_t bm[2] = {x[0] | z[0], x[1] | z[1]};
-  for (int k = 1; k < N; k++) {
+  int best = 0;
+  for (int r = 1; r < N; r++) {
     uint64_t tx[2], tz[2];
-    ts_translate(N, x, z, k, tx, tz);
+    ts_translate(N, x, z, N - r, tx, tz);
     uint64_t tm[2] = {tx[0] | tz[0], tx[1] | tz[1]};
     int c = num_cmp(tm, bm);
     if (c == 0) c = num_cmp(tx, bx);
     if (c == 0) c = num_cmp(tz, bz);
     if (c < 0) {
+      best = r;
       memcpy(bx, tx, sizeof(bx));
       memcpy(bz, tz, sizeof(bz));
       memcpy(bm, tm, sizeof(bm));
@@ -410,6 +414,7 @@ void or_ts_canonical(int N, const uint64_t x[2], const uint64_t z[2], uint64_t c
   }
   memcpy(cx, bx, sizeof(bx));
   memcpy(cz, bz, sizeof(bz));
+  return best;
 }
 
 /* number of k in [0, N) with T_k(s) = s */
@@ -424,9 +429,10 @@ static int ts_stabilizer(int N, const uint64_t x[2], const uint64_t z[2]) {
 }
 
 /* [H, O] for H = sum_k T_k(H0) and O = sum_k T_k(O0): H0 expanded to the list
- * T_0(h_0), T_1(h_0), ..., T_{N-1}(h_0), T_0(h_1), ... (that list's order is
- * the summation order), every anticommuting pair with an O0 string gives
- * 2 i^e h c on the representative of its product. */
+ * T_0(h_0), T_1(h_0), ..., T_{N-1}(h_0), T_0(h_1), ..., every anticommuting
+ * pair with an O0 string gives 2 i^e h c on the representative of its
+ * product.  Summation order per representative: ascending list entry, then
+ * ascending rotation r of the product (one O0 string per entry and r). */
 int or_commutator_ts(const or_op *H0, const or_op *O, or_op *out) {
   int N = O->n_qubits;
   if (H0->n_qubits != N || N < 1 || N > 128) return OR_EINVAL;
@@ -451,8 +457,8 @@ int or_commutator_ts(const or_op *H0, const or_op *O, or_op *out) {
         di = pi - qi;
         cmul(H0->re[a], H0->im[a], O->re[j], O->im[j], &hr, &hi);
         rec_t r;
-        or_ts_canonical(N, cx, cz, r.x, r.z);
-        r.idx = a * N + k;
+        const int rot = or_ts_canonical(N, cx, cz, r.x, r.z);
+        r.idx = (a * N + k) * 256 + rot;
         cmul(dr, di, hr, hi, &r.re, &r.im);
         if (rb_push(&b, &r)) return OR_ENOMEM;
       }

@@ -56,8 +56,8 @@ int or_add(const or_op *A, double ar, double ai, const or_op *B, double br, doub
 int or_truncate(const or_op *in, const or_trunc *t, or_op *out);
 int or_divide(const or_op *in, double b, or_op *out);
 int or_add_noise(const or_op *in, double lambda, or_op *out);
-void or_ts_canonical(int N, const uint64_t x[2], const uint64_t z[2], uint64_t cx[2],
-                     uint64_t cz[2]);
+int or_ts_canonical(int N, const uint64_t x[2], const uint64_t z[2], uint64_t cx[2],
+                    uint64_t cz[2]);
 void or_ts_translate(int N, const uint64_t x[2], const uint64_t z[2], int k, uint64_t ox[2],
                      uint64_t oz[2]);
 int or_commutator_ts(const or_op *H0, const or_op *O, or_op *out);

@@ -91,3 +91,26 @@ def evolve_noisy(H: PauliOp, O0: PauliOp, dt: float, steps: int, max_strings: in
         if observe is not None:
             observe(len(S) - 1, cur)
     return cur, S, P
+
+
+def lanczos_ts1d(H0: PauliOp, O0: PauliOp, steps: int, trunc: Trunc | None = None,
+                 ws: Workspace | None = None):
+    """Lanczos recursion on translation-symmetric operators of the periodic
+    chain (Krylov section with the Alg. 2 commutator):
+    O'_n = [H, O_{n-1}] - b_{n-1} O_{n-2}, b_n = sqrt(norm2_ts1d(O'_n)),
+    O_n = trunc(O'_n * fl(1/b_n)); O0 holds representatives with
+    norm2_ts1d(O0) = 1.  Same b_n as the plain recursion on the full operators."""
+    import math
+    ws = ws or ops.default_workspace(O0.device)
+    empty = PauliOp(O0.n_qubits, 1, O0.dtype, O0.device)
+    bs, prev, cur, b_prev = [], empty, O0, 0.0
+    for _ in range(steps):
+        C = ops.commutator_ts1d(H0, cur, ws=ws)
+        C = ops.add(C, 1.0, prev, -b_prev, ws=ws)
+        b = math.sqrt(ops.norm2_ts1d(C, ws=ws))
+        bs.append(b)
+        if b == 0.0:
+            break
+        nxt = ops.add(C, 1.0 / b, empty, 0.0, trunc, ws=ws)
+        prev, cur, b_prev = cur, nxt, b
+    return bs

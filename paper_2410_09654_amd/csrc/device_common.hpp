@@ -145,6 +145,107 @@ DEV bool key_eq(const Key<W>& a, const Key<W>& b) {
   return e;
 }
 
+// ---------------------------------------------------------------------------
+// Translation-symmetric operators on a periodic chain of N sites (site j is
+// bit j of the W words, bits from N up are zero).  T_k moves site j to site
+// (j + k) mod N.  The orbit representative is the rotation whose occupied
+// pattern x|z, read as an N-bit number, is smallest; ties by x, then z.
+// ---------------------------------------------------------------------------
+// v rotated so that site j of the result is site (j + r) mod N of v (0 <= r < N).
+template <int W>
+DEV void ts_rot_down(const uint64_t* v, int N, int r, uint64_t* out) {
+  if constexpr (W == 1) {
+    const uint64_t m = N == 64 ? ~0ull : ((1ull << N) - 1ull);
+    out[0] = r ? (((v[0] >> r) | (v[0] << (N - r))) & m) : v[0];
+  } else {
+    // 128-bit: lo = v[0], hi = v[1]
+    auto shr = [](uint64_t lo, uint64_t hi, int s, uint64_t& olo, uint64_t& ohi) {
+      if (s == 0) { olo = lo; ohi = hi; }
+      else if (s < 64) { olo = (lo >> s) | (hi << (64 - s)); ohi = hi >> s; }
+      else { olo = hi >> (s - 64); ohi = 0; }
+    };
+    auto shl = [](uint64_t lo, uint64_t hi, int s, uint64_t& olo, uint64_t& ohi) {
+      if (s == 0) { olo = lo; ohi = hi; }
+      else if (s < 64) { ohi = (hi << s) | (lo >> (64 - s)); olo = lo << s; }
+      else { ohi = lo << (s - 64); olo = 0; }
+    };
+    if (r == 0) {
+      out[0] = v[0];
+      out[1] = v[1];
+      return;
+    }
+    uint64_t alo, ahi, blo, bhi;
+    shr(v[0], v[1], r, alo, ahi);
+    shl(v[0], v[1], N - r, blo, bhi);
+    uint64_t lo = alo | blo, hi = ahi | bhi;
+    if (N <= 64) {
+      lo &= N == 64 ? ~0ull : ((1ull << N) - 1ull);
+      hi = 0;
+    } else if (N < 128) {
+      hi &= (1ull << (N - 64)) - 1ull;
+    }
+    out[0] = lo;
+    out[1] = hi;
+  }
+}
+
+// -1 / 0 / 1 comparison of W-word numbers, word W-1 most significant.
+template <int W>
+DEV int num_cmp(const uint64_t* a, const uint64_t* b) {
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < W; i++) c = a[i] != b[i] ? (a[i] < b[i] ? -1 : 1) : c;
+  return c;
+}
+
+// The orbit representative of the raw key k (x words, then z words), in place;
+// returns the rotation r (site r moved to site 0), the smallest one when
+// several give the representative.  Only rotations that bring an occupied
+// site to site 0 can be smallest.
+template <int W>
+DEV int ts_representative(uint64_t* k, int N) {
+  int best = 0;
+  uint64_t m[W], bm[W], bx[W], bz[W];
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    m[i] = k[i] | k[W + i];
+    bm[i] = m[i];
+    bx[i] = k[i];
+    bz[i] = k[W + i];
+  }
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    uint64_t bits = m[w];
+    while (bits) {
+      const int r = 64 * w + __builtin_ctzll(bits);
+      bits &= bits - 1;
+      if (r == 0) continue;
+      uint64_t tm[W], tx[W], tz[W];
+      ts_rot_down<W>(m, N, r, tm);
+      ts_rot_down<W>(k, N, r, tx);
+      ts_rot_down<W>(k + W, N, r, tz);
+      int c = num_cmp<W>(tm, bm);
+      if (c == 0) c = num_cmp<W>(tx, bx);
+      if (c == 0) c = num_cmp<W>(tz, bz);
+      if (c < 0) {
+        best = r;
+#pragma unroll
+        for (int i = 0; i < W; i++) {
+          bm[i] = tm[i];
+          bx[i] = tx[i];
+          bz[i] = tz[i];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < W; i++) {
+    k[i] = bx[i];
+    k[W + i] = bz[i];
+  }
+  return best;
+}
+
 // Number of non-identity sites of a raw key.
 template <int W>
 DEV int key_length(const Key<W>& raw) {

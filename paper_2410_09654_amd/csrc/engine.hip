@@ -207,6 +207,7 @@ struct Call {
   bool f32rec = false;  // FP32 record values (precision split)
   bool has_comm = false;
   bool product = false;  // A B instead of [A, B] (H = A, O = B)
+  int ts = 0;  // > 0: translation-symmetric operators on ts periodic sites (Alg. 2)
   OpV H, O;
   int comm_group = 0;
   int n_terms = 0;
@@ -270,6 +271,23 @@ int Engine::run(Call& c) {
   const size_t RB = sizeof(Rec<W, F32>);
   ar->bottom = 0;
   memset(&g_stats, 0, sizeof(g_stats));
+  // translation-symmetric commutator: H = sum_k T_k(H0), H0 listed over its
+  // N translations (entry h N + k), then the plain commutator with every
+  // product string replaced by its orbit representative
+  if (c.ts && c.has_comm && c.H.n > 0) {
+    const int64_t nf = c.H.n * c.ts;
+    uint64_t* hx = (uint64_t*)ar->take((size_t)nf * 8 * W);
+    uint64_t* hz = (uint64_t*)ar->take((size_t)nf * 8 * W);
+    double2* hc = (double2*)ar->take((size_t)nf * sizeof(double2));
+    if (ar->short_) return PAULI_EWORKSPACE;
+    LAUNCH("k_ts_expand", (k_ts_expand<W>), (nf + 255) / 256, 256, c.H.x, c.H.z, c.H.cap,
+           (const double2*)c.H.c, c.H.n, c.ts, hx, hz, hc);
+    c.H.x = hx;
+    c.H.z = hz;
+    c.H.c = hc;
+    c.H.n = nf;
+    c.H.cap = nf;
+  }
   // ----- inputs --------------------------------------------------------------
   const bool comm = c.has_comm && c.H.n > 0 && c.O.n > 0;
   int64_t tstart[MAX_TERMS + 1];
@@ -351,6 +369,7 @@ int Engine::run(Call& c) {
   ea.nH = comm ? (int)c.H.n : 0;
   ea.has_comm = comm ? 1 : 0;
   ea.product = c.product ? 1 : 0;
+  ea.ts_n = c.ts;
   ea.comm_rows = comm_rows;
   ea.comm_group = (uint32_t)c.comm_group;
   if (comm) {
@@ -431,7 +450,8 @@ int Engine::run(Call& c) {
   // ----- records, U, bucket tables, candidate lists -------------------------
   // source ids fold into the key bits implied by the bin unless an index
   // needs more than 11 bits (H above 2047 strings, canonicalisation lists)
-  bool wide = comm && c.H.n > 2047;
+  // (translation-symmetric calls carry (H entry, rotation) as the source id)
+  bool wide = comm && (c.H.n > 2047 || c.ts);
   for (int t = 0; t < c.n_terms; t++) wide = wide || c.tlist[t];
   void* recs = ar->take(ptot * RB);
   uint32_t* rsrc_wide = wide ? (uint32_t*)ar->take(ptot * 4) : nullptr;
@@ -991,6 +1011,87 @@ int pauli_multiply(const pauli_op* A, const pauli_op* B, const pauli_trunc* t, p
   c.out.f32 = out->dtype == PAULI_C64K;
   c.round32 = c.out.f32;
   return run_call(ar, ws, stream, c);
+}
+
+int pauli_commutator_ts1d(const pauli_op* H0, const pauli_op* O, const pauli_trunc* t,
+                          pauli_op* out, pauli_ws* ws, void* stream) {
+  if (!ws || check_op(H0, false) || check_op(O, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (H0->n_qubits != O->n_qubits || out->n_qubits != O->n_qubits) return PAULI_EINVAL;
+  if (H0->dtype != PAULI_C128 || out->dtype != O->dtype) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  Call c;
+  c.W = words_of(O->n_qubits);
+  c.f32rec = O->dtype == PAULI_C64K;
+  c.has_comm = true;
+  c.ts = O->n_qubits;
+  c.H = view(H0);
+  c.O = view(O);
+  c.comm_group = 0;
+  c.n_groups = 1;
+  c.groups[0].kind = c.f32rec ? G_SUM_KAHAN32 : G_SUM;
+  c.trunc = t;
+  c.out.user = out;
+  c.out.f32 = out->dtype == PAULI_C64K;
+  c.round32 = c.out.f32;
+  return run_call(ar, ws, stream, c);
+}
+
+int pauli_canonicalize_ts1d(const pauli_op* in, pauli_op* out, pauli_ws* ws, void* stream) {
+  if (!ws || check_op(in, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (out->n_qubits != in->n_qubits) return PAULI_EINVAL;
+  if (in->size >= ((int64_t)1 << GROUP_SHIFT)) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  Call c;
+  c.W = words_of(in->n_qubits);
+  c.f32rec = in->dtype == PAULI_C64K;
+  c.ts = in->n_qubits;
+  c.n_terms = 1;
+  c.T[0] = view(in);
+  c.tlist[0] = 1;
+  c.n_groups = 1;
+  c.groups[0].kind = G_SUM;
+  c.out.user = out;
+  c.out.f32 = out->dtype == PAULI_C64K;
+  c.round32 = c.out.f32;
+  return run_call(ar, ws, stream, c);
+}
+
+int pauli_norm2_ts1d(const pauli_op* A, double* out, pauli_ws* ws, void* stream_) {
+  if (!ws || !out || check_op(A, false)) return PAULI_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  Arena ar = make_arena(ws);
+  const int blocks = (int)std::min<int64_t>(std::max<int64_t>((A->size + 255) / 256, 1), 1024);
+  double2* part = (double2*)ar.take((size_t)blocks * 16);
+  double* res = (double*)ar.take(16);
+  if (ar.short_) return ws_short(ar, ws);
+  if (A->size == 0) {
+    *out = 0.0;
+    return PAULI_OK;
+  }
+  const int W = words_of(A->n_qubits), N = A->n_qubits;
+  const bool f32 = A->dtype == PAULI_C64K;
+  if (W == 1) {
+    if (f32)
+      LAUNCH("k_norm_part_ts", (k_norm_part_ts<1, true>), blocks, 256, A->x, A->z, A->capacity,
+             A->coef, A->size, N, part);
+    else
+      LAUNCH("k_norm_part_ts", (k_norm_part_ts<1, false>), blocks, 256, A->x, A->z, A->capacity,
+             A->coef, A->size, N, part);
+  } else {
+    if (f32)
+      LAUNCH("k_norm_part_ts", (k_norm_part_ts<2, true>), blocks, 256, A->x, A->z, A->capacity,
+             A->coef, A->size, N, part);
+    else
+      LAUNCH("k_norm_part_ts", (k_norm_part_ts<2, false>), blocks, 256, A->x, A->z, A->capacity,
+             A->coef, A->size, N, part);
+  }
+  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, part, (uint32_t)blocks, res);
+  double h[2];
+  HIP_TRY(hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  *out = h[0];
+  return PAULI_OK;
 }
 
 int pauli_trace(const pauli_op* A, double out[2], pauli_ws* ws, void* stream_) {

@@ -70,6 +70,8 @@ struct EmitArgs {
   int nH;
   int has_comm;
   int product;  // plain product A B (every pair, i^e h_a c_b) instead of [A, B]
+  int ts_n;     // > 0: translation-symmetric operators on ts_n periodic sites; every
+                // emitted string is replaced by its orbit representative
   int comm_rows;
   uint32_t comm_group;
   const uint64_t* Ox;
@@ -305,6 +307,9 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
         // pairs contribute 2 i^e h_a c_b to [P_a, P_b] h_a c_b, every pair
         // i^e h_a c_b to the product.
         const int e = (pa + pb + 2 * pz - pc) & 3;
+        // translation symmetry: several O strings can meet the same H entry
+        // in one orbit; (H entry, rotation) orders their contributions
+        const int rot = a.ts_n ? ts_representative<W>(c.w, a.ts_n) : 0;
         const uint32_t horig = a.Hidx[h];
         const double2 hd = a.Hc[horig];
         V hc;
@@ -313,7 +318,8 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
         V prod;
         if constexpr (F32) prod = cmulf(hc, bc);
         else prod = cmul(hc, bc);
-        deposit(c, a.product ? times_ie(prod, e) : times_2ie(prod, e), a.comm_group, horig);
+        deposit(c, a.product ? times_ie(prod, e) : times_2ie(prod, e), a.comm_group,
+                a.ts_n ? horig * 256u + (uint32_t)rot : horig);
       };
 
       uint32_t qn = 0;  // wave-uniform queue fill
@@ -362,6 +368,7 @@ __global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8)
           raw.w[w] = a.tx[t][(size_t)w * a.tcap[t] + k];
           raw.w[W + w] = a.tz[t][(size_t)w * a.tcap[t] + k];
         }
+        if (a.ts_n) (void)ts_representative<W>(raw.w, a.ts_n);
         V val;
         if (a.tf32[t]) {
           const float2 f = reinterpret_cast<const float2*>(a.tc[t])[k];
@@ -1868,6 +1875,89 @@ __global__ __launch_bounds__(256) void k_lookup(const Key<W>* ak, const void* ac
     else hi = mid;
   }
   out[q] = v;
+}
+
+// H = sum_k T_k(H0) listed as T_0(h_0), T_1(h_0), ..., T_{N-1}(h_0), T_0(h_1), ...
+// (entry h N + k: h_h translated by k sites); out word-major with capacity
+// nH0 N, FP64 coefficients.
+template <int W>
+__global__ __launch_bounds__(256) void k_ts_expand(const uint64_t* x, const uint64_t* z,
+                                                   int64_t cap, const double2* c, int64_t nh,
+                                                   int N, uint64_t* ox, uint64_t* oz,
+                                                   double2* oc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = nh * N;
+  if (i >= n) return;
+  const int64_t h = i / N;
+  const int k = (int)(i % N);
+  uint64_t vx[W], vz[W], tx[W], tz[W];
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    vx[w] = x[(size_t)w * cap + h];
+    vz[w] = z[(size_t)w * cap + h];
+  }
+  // translation by k = rotation down by (N - k) mod N
+  const int r = k ? N - k : 0;
+  ts_rot_down<W>(vx, N, r, tx);
+  ts_rot_down<W>(vz, N, r, tz);
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    ox[(size_t)w * n + i] = tx[w];
+    oz[(size_t)w * n + i] = tz[w];
+  }
+  oc[i] = c[h];
+}
+
+// Per-block double-double partials of sum_k stab(s_k) |c_k|^2: the norm of a
+// translation-symmetric operator held as representatives, over N (stab =
+// translations k in [0, N) that leave the string unchanged).
+template <int W, bool F32>
+__global__ __launch_bounds__(256) void k_norm_part_ts(const uint64_t* x, const uint64_t* z,
+                                                      int64_t cap, const void* coef, int64_t n,
+                                                      int N, double2* part) {
+  __shared__ double rh[4], rl[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  dd s = dd_zero();
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
+    double2 v;
+    if (F32) {
+      const float2 f = reinterpret_cast<const float2*>(coef)[i];
+      v = make_double2(f.x, f.y);
+    } else {
+      v = reinterpret_cast<const double2*>(coef)[i];
+    }
+    uint64_t vx[W], vz[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+      vx[w] = x[(size_t)w * cap + i];
+      vz[w] = z[(size_t)w * cap + i];
+    }
+    int st = 1;
+    for (int r = 1; r < N; r++) {
+      uint64_t tx[W], tz[W];
+      ts_rot_down<W>(vx, N, r, tx);
+      ts_rot_down<W>(vz, N, r, tz);
+      st += (num_cmp<W>(tx, vx) == 0 && num_cmp<W>(tz, vz) == 0) ? 1 : 0;
+    }
+    const double w2 = weight2(v);
+    for (int r = 0; r < st; r++) s = dd_add(s, w2);
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    dd o;
+    o.hi = __shfl_down(s.hi, d, 64);
+    o.lo = __shfl_down(s.lo, d, 64);
+    if (lane < d) s = dd_add(s, o);
+  }
+  if (lane == 0) {
+    rh[wv] = s.hi;
+    rl[wv] = s.lo;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    dd t = {rh[0], rl[0]};
+    for (int w = 1; w < 4; w++) t = dd_add(t, dd{rh[w], rl[w]});
+    part[blockIdx.x] = make_double2(t.hi, t.lo);
+  }
 }
 
 // Order keys of an operator's strings, and the strings of order keys.

@@ -220,6 +220,62 @@ def multiply(A: PauliOp, B: PauliOp, trunc: Trunc | None = None, out: PauliOp | 
     return out
 
 
+def commutator_ts1d(H0: PauliOp, O: PauliOp, trunc: Trunc | None = None,
+                    out: PauliOp | None = None, ws: Workspace | None = None) -> PauliOp:
+    """Translation-symmetric [H, O] on the periodic chain (Alg. 2): O and the
+    result hold one representative string per translation orbit."""
+    L = _lib.load()
+    ws = ws or default_workspace(O.device)
+    if out is None:
+        b = trunc.bound() if trunc else None
+        guess = b if b is not None else min(H0.size * O.n_qubits * O.size, 16 * O.size + 1024)
+        out = _out_like(O.n_qubits, guess, O.dtype, O.device)
+    hs, os_ = H0.c_struct(), O.c_struct()
+    keep_s, ts = trunc.c_struct() if trunc else (None, None)
+
+    def fn(wss):
+        outs = out.c_struct()
+        st = L.pauli_commutator_ts1d(ctypes.byref(hs), ctypes.byref(os_),
+                                     ctypes.byref(ts) if ts is not None else None,
+                                     ctypes.byref(outs), ctypes.byref(wss), _stream_handle())
+        return st, outs
+
+    _call("pauli_commutator_ts1d", fn, ws, out)
+    return out
+
+
+def canonicalize_ts1d(A: PauliOp, ws: Workspace | None = None) -> PauliOp:
+    """Every string replaced by its translation-orbit representative,
+    duplicates summed in input order."""
+    L = _lib.load()
+    ws = ws or default_workspace(A.device)
+    out = _out_like(A.n_qubits, max(A.size, 1), A.dtype, A.device)
+    As = A.c_struct()
+
+    def fn(wss):
+        outs = out.c_struct()
+        return L.pauli_canonicalize_ts1d(ctypes.byref(As), ctypes.byref(outs),
+                                         ctypes.byref(wss), _stream_handle()), outs
+
+    _call("pauli_canonicalize_ts1d", fn, ws, out)
+    return out
+
+
+def norm2_ts1d(A: PauliOp, ws: Workspace | None = None) -> float:
+    """||sum_k T_k(A)||^2 / N for representatives A."""
+    L = _lib.load()
+    ws = ws or default_workspace(A.device)
+    As = A.c_struct()
+    r = ctypes.c_double()
+
+    def fn(wss):
+        return L.pauli_norm2_ts1d(ctypes.byref(As), ctypes.byref(r), ctypes.byref(wss),
+                                  _stream_handle()), None
+
+    _call("pauli_norm2_ts1d", fn, ws, None)
+    return r.value
+
+
 def trace(A: PauliOp, ws: Workspace | None = None) -> complex:
     """Tr(A)/2^N: the coefficient of the identity string."""
     L = _lib.load()

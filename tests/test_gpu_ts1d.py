@@ -1,0 +1,117 @@
+"""GPU parity of the translation-symmetric operators of Alg. 2 (periodic
+chain, one representative string per translation orbit) through the C ABI,
+against the CPU oracle: representatives, the commutator over translates, the
+stabilizer-weighted norm and the Lanczos recursion built on them.  Keys
+bit-exact, FP64 coefficients within 1e-12 relative."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from helpers import assert_canonical_unique, assert_same_operator, exact_fraction, gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2410_09654_amd as pk
+    pk._lib.load()
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ws(pk):
+    return pk.Workspace(256 << 20)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def up(pk, host, ws, dtype=0):
+    return pk.PauliOp.from_host(host, dtype=dtype, ws=ws)
+
+
+def raw(pk, host):
+    return pk.PauliOp.from_raw(host.n_qubits, host.x, host.z, host.coef)
+
+
+def chain_h0(n):
+    """Terms of a chaotic periodic chain plus a longer-range one: H = sum_k T_k(H0)."""
+    return wl.from_terms(n, [(1.0, [("Z", 1), ("Z", 2)]), (1.05, [("X", 1)]), (0.5, [("Z", 1)]),
+                             (0.3, [("X", 1), ("Y", 3)]), (0.2, [("Y", 1), ("Z", 2), ("X", 4)])])
+
+
+@pytest.mark.parametrize("n,seed", [(8, 1), (64, 2), (100, 3), (128, 4)])
+def test_canonicalize_ts1d(pk, ws, n, seed):
+    say(f"ts canonicalize n={n}")
+    A = wl.random_operator(n, 800, seed=seed, density=min(1.0, 4.0 / n))
+    # add translates of some strings so that orbits collide
+    T = oracle.expand_ts(wl.HostOp(n, A.x[:3], A.z[:3], A.coef[:3]))
+    B = wl.HostOp(n, np.concatenate([A.x, T.x]), np.concatenate([A.z, T.z]),
+                  np.concatenate([A.coef, T.coef]))
+    want = oracle.canonicalize_ts(B)
+    got = pk.canonicalize_ts1d(raw(pk, B), ws=ws).to_host()
+    assert_canonical_unique(got)
+    assert_same_operator(got, want, what="ts representatives")
+
+
+@pytest.mark.parametrize("n,no,seed", [(8, 40, 11), (20, 400, 12), (64, 3000, 13),
+                                       (100, 1500, 14), (128, 800, 15)])
+def test_commutator_ts1d(pk, ws, n, no, seed):
+    say(f"ts commutator n={n} no={no}")
+    H0 = chain_h0(n)
+    O0 = oracle.canonicalize_ts(wl.random_local_strings(n, no, min(8, n), seed=seed))
+    want = oracle.commutator_ts(H0, O0)
+    got = pk.commutator_ts1d(raw(pk, H0), up(pk, O0, ws), ws=ws).to_host()
+    assert_canonical_unique(got)
+    assert_same_operator(got, want, what="ts commutator")
+    assert exact_fraction(got, want) == 1.0
+    # truncated (top-M with the length cap)
+    t = oracle.Trunc(max_len=6, max_strings=max(1, want.n // 3))
+    want_t = oracle.truncate(want, t)
+    got_t = pk.commutator_ts1d(raw(pk, H0), up(pk, O0, ws),
+                               pk.Trunc(max_len=6, max_strings=max(1, want.n // 3)),
+                               ws=ws).to_host()
+    assert_same_operator(got_t, want_t, what="truncated ts commutator")
+
+
+def test_norm2_ts1d(pk, ws):
+    say("ts norm")
+    for n in (8, 64, 100):
+        A0 = oracle.canonicalize_ts(wl.from_terms(n, [
+            (0.5 + 0.25j, [("Z", 1), ("Z", 2)]), (1.5, [("X", 1)]),
+            (0.75, [("X", j) for j in range(1, n + 1, 2)]),
+            (-0.4j, [("Z", j) for j in range(1, n + 1)]),
+            (0.1, [("Y", j) for j in range(1, n + 1, 4)] if n % 4 == 0 else [("Y", 2)])]))
+        R = oracle.canonicalize_ts(wl.random_operator(n, 500, seed=n, density=min(1.0, 4.0 / n)))
+        for op in (A0, R):
+            want = oracle.norm2_ts(op)
+            got = pk.norm2_ts1d(up(pk, op, ws), ws=ws)
+            assert abs(got - want) <= 1e-15 * want
+
+
+def test_lanczos_ts1d_matches_oracle_and_full_chain(pk, ws):
+    say("ts lanczos")
+    n, steps = 20, 12
+    H0 = chain_h0(n)
+    Z1 = wl.from_terms(n, [(1.0, [("Z", 1)])])
+    t = oracle.Trunc(max_strings=3000)
+    want = oracle.lanczos_ts(H0, Z1, steps, t)
+    got = pk.lanczos_ts1d(raw(pk, H0), up(pk, Z1, ws), steps, pk.Trunc(max_strings=3000), ws=ws)
+    assert np.allclose(got, want, rtol=1e-12, atol=0)
+    # untruncated: the same b_n as the plain recursion on the full periodic chain
+    n = 10
+    H0 = chain_h0(n)
+    Z1 = wl.from_terms(n, [(1.0, [("Z", 1)])])
+    b_ts = pk.lanczos_ts1d(raw(pk, H0), up(pk, Z1, ws), 8, ws=ws)
+    Hf = oracle.expand_ts(H0)
+    Of = wl.single_site_sum(n, "Z", 1 / math.sqrt(n))
+    b_full = pk.lanczos(raw(pk, Hf), up(pk, Of, ws), 8, ws=ws)
+    assert np.allclose(b_ts, b_full, rtol=1e-12, atol=0)
