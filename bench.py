@@ -39,11 +39,11 @@ def parse():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--workload", default="commutator",
                     choices=["commutator", "lanczos-split", "rk4-tfim", "lanczos-small", "moments",
-                             "noisy-xxz", "surrogate"],
+                             "noisy-xxz", "lanczos-ts", "surrogate"],
                     help="commutator: the benchmark line (default); the others run the "
                          "Lanczos precision-split, RK4, small-Lanczos, spectral-moment, "
-                         "noisy-diffusion and b_n-surrogate configurations and print their own "
-                         "result line")
+                         "noisy-diffusion, translation-symmetric Lanczos and b_n-surrogate "
+                         "configurations and print their own result line")
     ap.add_argument("--max-strings", type=int, default=0,
                     help="truncation M for lanczos-split / rk4-tfim (0: the configuration's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -308,6 +308,54 @@ def run_noisy_xxz(args):
     print(json.dumps(line), flush=True)
 
 
+def run_lanczos_ts(args):
+    """Lanczos recursion on translation-symmetric operators (Alg. 2) of two
+    periodic chains, O0 = P_1 as orbit representative (sum_j P_j / sqrt(N) in
+    full): the chaotic Ising chain (N = 64, H0 = {ZZ, 1.05 X, 0.5 Z}, P = Z),
+    40 steps at M = 2^18, and the XX chain (N = 50, H0 = {XX, YY}, P = X, as
+    total Z is conserved there), 50 steps at M = 2^16; with the oracle beside
+    it on 10 steps at M = 2^10."""
+    import torch
+    import workloads as wl
+    import paper_2410_09654_amd as pk
+    ws = pk.Workspace(1 << 30)
+    runs = {"chaotic_ising_N64": (64, [(1.0, [("Z", 1), ("Z", 2)]), (1.05, [("X", 1)]),
+                                       (0.5, [("Z", 1)])], "Z", 40, 1 << 18),
+            "xx_N50": (50, [(1.0, [("X", 1), ("X", 2)]), (1.0, [("Y", 1), ("Y", 2)])], "X", 50,
+                       1 << 16)}
+    line = {"workload": "translation-symmetric Lanczos (Alg. 2 commutator), O0 = P_1 "
+                        "(sum_j P_j / sqrt(N))"}
+    for name, (n, terms, p0, steps, M) in runs.items():
+        H0h = wl.from_terms(n, terms)
+        Z1 = wl.from_terms(n, [(1.0, [(p0, 1)])])
+        H0 = pk.PauliOp.from_raw(n, H0h.x, H0h.z, H0h.coef)
+        O0 = pk.PauliOp.from_host(Z1, ws=ws)
+        pk.lanczos_ts1d(H0, O0, 3, pk.Trunc(max_strings=M), ws=ws)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bs = pk.lanczos_ts1d(H0, O0, steps, pk.Trunc(max_strings=M), ws=ws)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        r = {"N": n, "O0": p0 + "_1", "steps": len(bs), "max_strings": M, "b": bs,
+             "seconds": wall,
+             "ms_per_step": 1e3 * wall / max(len(bs), 1)}
+        if args.cpu_sample > 0:
+            import oracle
+            tc = time.perf_counter()
+            bo = oracle.lanczos_ts(H0h, Z1, 10, oracle.Trunc(max_strings=1 << 10))
+            tcpu = time.perf_counter() - tc
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            bg = pk.lanczos_ts1d(H0, O0, 10, pk.Trunc(max_strings=1 << 10), ws=ws)
+            torch.cuda.synchronize()
+            r["oracle_10_steps_M1024"] = {
+                "oracle_seconds": tcpu, "gpu_seconds": time.perf_counter() - tg, "cores": 1,
+                "max_rel_diff_b": max(abs(a - b) / max(abs(b), 1e-300) for a, b in zip(bg, bo))}
+        line[name] = r
+        print(f"{name}: {len(bs)} steps in {wall:.2f} s", file=sys.stderr, flush=True)
+    print(json.dumps(line), flush=True)
+
+
 MLP_FWD_FLOP = 2 * (16 * 256 + 256 * 256 + 256 * 16)  # per window
 MLP_TRAIN_FLOP = 3 * MLP_FWD_FLOP  # forward, input gradient, weight gradient
 
@@ -393,7 +441,8 @@ def main():
         torch.cuda.set_device(0)
         {"lanczos-split": run_lanczos_split, "rk4-tfim": run_rk4_tfim,
          "lanczos-small": run_lanczos_small, "surrogate": run_surrogate,
-         "moments": run_moments, "noisy-xxz": run_noisy_xxz}[args.workload](args)
+         "moments": run_moments, "noisy-xxz": run_noisy_xxz,
+         "lanczos-ts": run_lanczos_ts}[args.workload](args)
         return
     import torch
     import workloads as wl
