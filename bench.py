@@ -309,40 +309,56 @@ def run_noisy_xxz(args):
 
 
 def run_lanczos_ts(args):
-    """Lanczos recursion on translation-symmetric operators (Alg. 2) of two
-    periodic chains, O0 = P_1 as orbit representative (sum_j P_j / sqrt(N) in
-    full): the chaotic Ising chain (N = 64, H0 = {ZZ, 1.05 X, 0.5 Z}, P = Z),
-    40 steps at M = 2^18, and the XX chain (N = 50, H0 = {XX, YY}, P = X, as
-    total Z is conserved there), 50 steps at M = 2^16; with the oracle beside
-    it on 10 steps at M = 2^10."""
+    """Lanczos recursion on translation-symmetric operators (Alg. 2) of the
+    periodic chains of the paper's translation-symmetry figure, N = 50, each
+    O0 given by its orbit representatives and normalised:
+      XX:        H0 = {XX, YY},              O0 ~ sum_j X_j,                    50 steps;
+      XXX:       H0 = {XX, YY, ZZ},          O0 ~ sum_j X_j Y_j+1 - Y_j X_j+1,  20 steps;
+      chaotic:   H0 = {XX, -1.05 Z, 0.5 X},  O0 ~ sum_j 1.05 X_j X_j+1 + Z_j,   40 steps;
+      chaotic with h_X = 0.1 in place of 0.5,                                   40 steps;
+    at M = 2^20 (--max-strings), with the oracle beside it on 10 steps at
+    M = 2^10."""
+    import math
     import torch
     import workloads as wl
     import paper_2410_09654_amd as pk
+    M = args.max_strings or (1 << 20)
     ws = pk.Workspace(1 << 30)
-    runs = {"chaotic_ising_N64": (64, [(1.0, [("Z", 1), ("Z", 2)]), (1.05, [("X", 1)]),
-                                       (0.5, [("Z", 1)])], "Z", 40, 1 << 18),
-            "xx_N50": (50, [(1.0, [("X", 1), ("X", 2)]), (1.0, [("Y", 1), ("Y", 2)])], "X", 50,
-                       1 << 16)}
-    line = {"workload": "translation-symmetric Lanczos (Alg. 2 commutator), O0 = P_1 "
-                        "(sum_j P_j / sqrt(N))"}
-    for name, (n, terms, p0, steps, M) in runs.items():
-        H0h = wl.from_terms(n, terms)
-        Z1 = wl.from_terms(n, [(1.0, [(p0, 1)])])
+    n = 50
+    XX = [(1.0, [("X", 1), ("X", 2)]), (1.0, [("Y", 1), ("Y", 2)])]
+    runs = {
+        "xx": (XX, [(1.0, [("X", 1)])], 50),
+        "xxx": (XX + [(1.0, [("Z", 1), ("Z", 2)])],
+                [(1.0, [("X", 1), ("Y", 2)]), (-1.0, [("Y", 1), ("X", 2)])], 20),
+        "chaotic_hx0.5": ([(1.0, [("X", 1), ("X", 2)]), (-1.05, [("Z", 1)]), (0.5, [("X", 1)])],
+                          [(1.05, [("X", 1), ("X", 2)]), (1.0, [("Z", 1)])], 40),
+        "chaotic_hx0.1": ([(1.0, [("X", 1), ("X", 2)]), (-1.05, [("Z", 1)]), (0.1, [("X", 1)])],
+                          [(1.05, [("X", 1), ("X", 2)]), (1.0, [("Z", 1)])], 40),
+    }
+    line = {"workload": "translation-symmetric Lanczos (Alg. 2 commutator), periodic N = 50",
+            "max_strings": M}
+    for name, (h_terms, o_terms, steps) in runs.items():
+        H0h = wl.from_terms(n, h_terms)
+        O0h = wl.from_terms(n, o_terms)
+        O0h.coef /= math.sqrt(float(np.sum(np.abs(O0h.coef) ** 2)))  # no stabilizers: norm 1
         H0 = pk.PauliOp.from_raw(n, H0h.x, H0h.z, H0h.coef)
-        O0 = pk.PauliOp.from_host(Z1, ws=ws)
+        O0 = pk.PauliOp.from_host(O0h, ws=ws)
         pk.lanczos_ts1d(H0, O0, 3, pk.Trunc(max_strings=M), ws=ws)  # warm-up
+        sizes = [O0.size]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        bs = pk.lanczos_ts1d(H0, O0, steps, pk.Trunc(max_strings=M), ws=ws)
+        bs = pk.lanczos_ts1d(H0, O0, steps, pk.Trunc(max_strings=M), ws=ws,
+                             observe=lambda k, O: sizes.append(O.size))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        r = {"N": n, "O0": p0 + "_1", "steps": len(bs), "max_strings": M, "b": bs,
-             "seconds": wall,
-             "ms_per_step": 1e3 * wall / max(len(bs), 1)}
+        # pairs of one step: N |H0| translated H strings times the representatives of O_{n-1}
+        pairs = n * H0.size * sum(sizes[:len(bs)])
+        r = {"steps": len(bs), "b": bs, "strings": sizes[1:], "seconds": wall,
+             "ms_per_step": 1e3 * wall / max(len(bs), 1), "pairs_per_s": pairs / wall}
         if args.cpu_sample > 0:
             import oracle
             tc = time.perf_counter()
-            bo = oracle.lanczos_ts(H0h, Z1, 10, oracle.Trunc(max_strings=1 << 10))
+            bo = oracle.lanczos_ts(H0h, O0h, 10, oracle.Trunc(max_strings=1 << 10))
             tcpu = time.perf_counter() - tc
             torch.cuda.synchronize()
             tg = time.perf_counter()

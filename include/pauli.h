@@ -136,11 +136,21 @@ int pauli_multiply(const pauli_op *A, const pauli_op *B, const pauli_trunc *t,
  * duplicates summed in input order, canonical order.
  * pauli_norm2_ts1d: *out (host) = ||sum_k T_k(A)||^2 / N = sum over A's
  * representatives of stab(s)|c_s|^2 (stab: translations leaving s unchanged);
- * the b_n of a Lanczos recursion are the same under this norm. */
+ * the b_n of a Lanczos recursion are the same under this norm.
+ * pauli_lanczos_step_ts1d: pauli_lanczos_step on translation-symmetric
+ * operators (the Krylov section's recursion with the commutator above and
+ * this norm): O'_n = [sum_k T_k(H0), O_cur] - b_prev O_prev as
+ * representatives, *b_out = sqrt(pauli_norm2_ts1d(O'_n)), O_next =
+ * trunc(O'_n / b_n); the same errors and breakdown rule as
+ * pauli_lanczos_step.  With O_0 of unit norm the b_n are those of the plain
+ * recursion on the full periodic-chain operators. */
 int pauli_commutator_ts1d(const pauli_op *H0, const pauli_op *O, const pauli_trunc *t,
                           pauli_op *out, pauli_ws *ws, void *stream);
 int pauli_canonicalize_ts1d(const pauli_op *in, pauli_op *out, pauli_ws *ws, void *stream);
 int pauli_norm2_ts1d(const pauli_op *A, double *out, pauli_ws *ws, void *stream);
+int pauli_lanczos_step_ts1d(const pauli_op *H0, const pauli_op *O_prev, const pauli_op *O_cur,
+                            double b_prev, const pauli_trunc *t, pauli_op *O_next,
+                            double *b_out, pauli_ws *ws, void *stream);
 
 /* out[0] + i out[1] (host) = Tr(A)/2^N: the coefficient of the identity string
  * (0 when A has none).  A's strings must be distinct.  With pauli_multiply it

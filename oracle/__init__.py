@@ -83,6 +83,8 @@ def lib():
         L.or_exact_sum.restype = ctypes.c_double
         L.or_lanczos_step.argtypes = [P(_OrOp), P(_OrOp), P(_OrOp), ctypes.c_double,
                                       P(_OrTrunc), ctypes.c_int, P(_OrOp), P(ctypes.c_double)]
+        L.or_lanczos_step_ts.argtypes = [P(_OrOp), P(_OrOp), P(_OrOp), ctypes.c_double,
+                                         P(_OrTrunc), P(_OrOp), P(ctypes.c_double)]
         L.or_rk4_step.argtypes = [P(_OrOp), P(_OrOp), ctypes.c_double, P(_OrTrunc), P(_OrOp)]
         _lib = L
     return _lib
@@ -318,25 +320,33 @@ def norm2_ts(O0: HostOp) -> float:
     return r
 
 
+def lanczos_step_ts(H0: HostOp, O_prev: HostOp | None, O_cur: HostOp, b_prev: float,
+                    t: Trunc = NO_TRUNC):
+    """One Lanczos step on translation-symmetric operators (Krylov section with
+    the Alg. 2 commutator and the stabilizer-weighted norm), with the rules of
+    lanczos_step: O_n = trunc(O'_n / b_n), breakdown when
+    b_n <= 1e-13 max(1, b_{n-1}).  Returns (O_next, b_n, breakdown)."""
+    h, c = _Marshalled(H0), _Marshalled(O_cur)
+    p = _Marshalled(O_prev) if O_prev is not None else None
+    pp = ctypes.byref(p.s) if p is not None else ctypes.POINTER(_OrOp)()
+    km, ts = t.marshal()
+    out, b = _OrOp(), ctypes.c_double()
+    rc = _check(lib().or_lanczos_step_ts(ctypes.byref(h.s), pp, ctypes.byref(c.s), float(b_prev),
+                                         ctypes.byref(ts), ctypes.byref(out), ctypes.byref(b)))
+    del km
+    return _take(out, O_cur.n_qubits), b.value, rc == OR_BREAKDOWN
+
+
 def lanczos_ts(H0: HostOp, O0: HostOp, steps: int, t: Trunc | None = None) -> list:
-    """Lanczos recursion on translation-symmetric operators (Krylov section,
-    with the Alg. 2 commutator): O'_n = [H, O_{n-1}] - b_{n-1} O_{n-2},
-    b_n = sqrt(norm2_ts(O'_n)), O_n = trunc(O'_n * fl(1/b_n)).  O0 must have
-    norm2_ts = 1."""
-    W = n_words(O0.n_qubits)
-    empty = HostOp(O0.n_qubits, np.zeros((0, W), np.uint64), np.zeros((0, W), np.uint64),
-                   np.zeros(0, complex))
-    bs, prev, cur, b_prev = [], empty, O0, 0.0
+    """b_1..b_steps of the translation-symmetric recursion (stops early at
+    breakdown).  O0 holds representatives with norm2_ts(O0) = 1; the b_n are
+    those of the plain recursion on sum_k T_k(H0) and sum_k T_k(O0)/sqrt(N)."""
+    bs, prev, cur, b_prev = [], None, O0, 0.0
     for _ in range(steps):
-        C = commutator_ts(H0, cur)
-        C = add(C, 1.0, prev, -b_prev)
-        b = math.sqrt(norm2_ts(C))
+        nxt, b, broke = lanczos_step_ts(H0, prev, cur, b_prev, t if t is not None else NO_TRUNC)
         bs.append(b)
-        if b == 0.0:
+        if broke:
             break
-        nxt = add(C, 1.0 / b, empty, 0.0)
-        if t is not None:
-            nxt = truncate(nxt, t)
         prev, cur, b_prev = cur, nxt, b
     return bs
 

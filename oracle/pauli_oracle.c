@@ -807,10 +807,14 @@ static void round_to_f32(or_op *o) {
   o->n = m;
 }
 
-int or_lanczos_step(const or_op *H, const or_op *O_prev, const or_op *O_cur, double b_prev,
-                    const or_trunc *t, int prec, or_op *O_next, double *b_out) {
+/* ts != 0: translation-symmetric operators of the periodic chain (Alg. 2):  */
+/* H holds H0, the operators hold orbit representatives, the commutator is   */
+/* or_commutator_ts and the norm the stabilizer-weighted or_norm2_ts (FP64). */
+static int lanczos_step(int ts, const or_op *H, const or_op *O_prev, const or_op *O_cur,
+                        double b_prev, const or_trunc *t, int prec, or_op *O_next,
+                        double *b_out) {
   or_op C = {0}, A = {0}, D = {0};
-  int rc = or_commutator(H, O_cur, prec, &C);
+  int rc = ts ? or_commutator_ts(H, O_cur, &C) : or_commutator(H, O_cur, prec, &C);
   if (rc) return rc;
   if (O_prev && O_prev->n > 0) {
     rc = or_add(&C, 1.0, 0.0, O_prev, -b_prev, 0.0, &A);
@@ -819,7 +823,7 @@ int or_lanczos_step(const or_op *H, const or_op *O_prev, const or_op *O_cur, dou
   } else {
     A = C;
   }
-  double b = sqrt(or_norm2(&A));
+  double b = sqrt(ts ? or_norm2_ts(&A) : or_norm2(&A));
   *b_out = b;
   double floor_b = 1e-13 * (b_prev > 1.0 ? b_prev : 1.0);
   if (!(b > floor_b)) {
@@ -834,6 +838,16 @@ int or_lanczos_step(const or_op *H, const or_op *O_prev, const or_op *O_cur, dou
   rc = or_truncate(&D, t, O_next);
   or_free(&D);
   return rc;
+}
+
+int or_lanczos_step(const or_op *H, const or_op *O_prev, const or_op *O_cur, double b_prev,
+                    const or_trunc *t, int prec, or_op *O_next, double *b_out) {
+  return lanczos_step(0, H, O_prev, O_cur, b_prev, t, prec, O_next, b_out);
+}
+
+int or_lanczos_step_ts(const or_op *H0, const or_op *O_prev, const or_op *O_cur, double b_prev,
+                       const or_trunc *t, or_op *O_next, double *b_out) {
+  return lanczos_step(1, H0, O_prev, O_cur, b_prev, t, OR_F64, O_next, b_out);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -14,6 +14,7 @@ PAULI_C128, PAULI_C64K = 0, 1
 EXPORTS = ["pauli_commutator", "pauli_multiply", "pauli_trace", "pauli_add", "pauli_truncate",
            "pauli_canonicalize", "pauli_add_noise", "pauli_coefficients",
            "pauli_commutator_ts1d", "pauli_canonicalize_ts1d", "pauli_norm2_ts1d",
+           "pauli_lanczos_step_ts1d",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
            "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_only", "pauli_profile_read",
            "pauli_last_stats", "pauli_order_keys", "pauli_strings_from_order_keys",
@@ -71,6 +72,7 @@ def load():
     L.pauli_commutator_ts1d.argtypes = [op, op, tr, op, ws, vp]
     L.pauli_canonicalize_ts1d.argtypes = [op, op, ws, vp]
     L.pauli_norm2_ts1d.argtypes = [op, P(d), ws, vp]
+    L.pauli_lanczos_step_ts1d.argtypes = [op, op, op, d, tr, op, P(d), ws, vp]
     L.pauli_coefficients.argtypes = [op, op, P(d), ws, vp]
     L.pauli_add.argtypes = [op, d, d, op, d, d, tr, op, ws, vp]
     L.pauli_truncate.argtypes = [op, tr, op, ws, vp]

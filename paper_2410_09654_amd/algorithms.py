@@ -94,23 +94,22 @@ def evolve_noisy(H: PauliOp, O0: PauliOp, dt: float, steps: int, max_strings: in
 
 
 def lanczos_ts1d(H0: PauliOp, O0: PauliOp, steps: int, trunc: Trunc | None = None,
-                 ws: Workspace | None = None):
+                 ws: Workspace | None = None, observe=None):
     """Lanczos recursion on translation-symmetric operators of the periodic
-    chain (Krylov section with the Alg. 2 commutator):
-    O'_n = [H, O_{n-1}] - b_{n-1} O_{n-2}, b_n = sqrt(norm2_ts1d(O'_n)),
-    O_n = trunc(O'_n * fl(1/b_n)); O0 holds representatives with
-    norm2_ts1d(O0) = 1.  Same b_n as the plain recursion on the full operators."""
-    import math
+    chain (Krylov section with the Alg. 2 commutator), one fused
+    pauli_lanczos_step_ts1d call per step: O'_n = [H, O_{n-1}] - b_{n-1} O_{n-2},
+    b_n = sqrt(norm2_ts1d(O'_n)), O_n = trunc(O'_n / b_n), stopping at
+    breakdown.  O0 holds representatives with norm2_ts1d(O0) = 1.  Same b_n as
+    the plain recursion on the full operators.  `observe(n, O_n)`, if given,
+    is called after every step that did not break down."""
     ws = ws or ops.default_workspace(O0.device)
-    empty = PauliOp(O0.n_qubits, 1, O0.dtype, O0.device)
-    bs, prev, cur, b_prev = [], empty, O0, 0.0
+    bs, prev, cur, b_prev = [], None, O0, 0.0
     for _ in range(steps):
-        C = ops.commutator_ts1d(H0, cur, ws=ws)
-        C = ops.add(C, 1.0, prev, -b_prev, ws=ws)
-        b = math.sqrt(ops.norm2_ts1d(C, ws=ws))
+        nxt, b, broke = ops.lanczos_step(H0, prev, cur, b_prev, trunc, ws=ws, ts1d=True)
         bs.append(b)
-        if b == 0.0:
+        if broke:
             break
-        nxt = ops.add(C, 1.0 / b, empty, 0.0, trunc, ws=ws)
         prev, cur, b_prev = cur, nxt, b
+        if observe is not None:
+            observe(len(bs), cur)
     return bs

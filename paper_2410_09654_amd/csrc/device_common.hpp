@@ -198,6 +198,20 @@ DEV int num_cmp(const uint64_t* a, const uint64_t* b) {
   return c;
 }
 
+// Translations T_r, r in [0, N), that leave the string (x, z) unchanged:
+// N / p for the string's period p (the smallest divisor r of N with T_r s = s).
+template <int W>
+DEV int ts_stabilizers(const uint64_t* x, const uint64_t* z, int N) {
+  for (int r = 1; r < N; r++) {
+    if (N % r) continue;
+    uint64_t tx[W], tz[W];
+    ts_rot_down<W>(x, N, r, tx);
+    ts_rot_down<W>(z, N, r, tz);
+    if (num_cmp<W>(tx, x) == 0 && num_cmp<W>(tz, z) == 0) return N / r;
+  }
+  return 1;
+}
+
 // The orbit representative of the raw key k (x words, then z words), in place;
 // returns the rotation r (site r moved to site 0), the smallest one when
 // several give the representative.  Only rotations that bring an occupied

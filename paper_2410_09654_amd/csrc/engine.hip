@@ -629,7 +629,11 @@ int Engine::run(Call& c) {
 
   // ----- Lanczos: b_n from the untruncated sum, then divide and filter -------
   if (c.mode == M_LANCZOS) {
-    LAUNCH("k_norm_bucket", k_norm_bucket, nbk, 256, b_ubase, b_slots, uc, norm_part);
+    if (c.ts)
+      LAUNCH("k_norm_bucket_ts", (k_norm_bucket_ts<W>), nbk, 256, b_ubase, b_slots, uk, uc,
+             c.ts, norm_part);
+    else
+      LAUNCH("k_norm_bucket", k_norm_bucket, nbk, 256, b_ubase, b_slots, uc, norm_part);
     LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, norm_part, nbk, &dctl->norm_hi);
     TRY(read_ctl());
     if (hctl->overflow) {
@@ -1177,11 +1181,12 @@ int pauli_canonicalize(const pauli_op* in, pauli_op* out, pauli_ws* ws, void* st
   return run_call(ar, ws, stream, c);
 }
 
-int pauli_lanczos_step(const pauli_op* H, const pauli_op* O_prev, const pauli_op* O_cur,
-                       double b_prev, const pauli_trunc* t, uint32_t flags, pauli_op* O_next,
-                       double* b_out, pauli_ws* ws, void* stream) {
-  if (!ws || flags != 0 || check_op(H, false) || check_op(O_cur, false) ||
-      check_op(O_next, true))
+// ts = N: translation-symmetric operators of the periodic chain (H holds H0,
+// the operators orbit representatives), else 0.
+static int lanczos_step(const pauli_op* H, const pauli_op* O_prev, const pauli_op* O_cur,
+                        double b_prev, const pauli_trunc* t, int ts, pauli_op* O_next,
+                        double* b_out, pauli_ws* ws, void* stream) {
+  if (!ws || check_op(H, false) || check_op(O_cur, false) || check_op(O_next, true))
     return PAULI_EINVAL;
   if (O_prev && check_op(O_prev, false)) return PAULI_EINVAL;
   if (H->dtype != PAULI_C128 || O_next->dtype != O_cur->dtype) return PAULI_EINVAL;
@@ -1194,6 +1199,7 @@ int pauli_lanczos_step(const pauli_op* H, const pauli_op* O_prev, const pauli_op
   c.W = words_of(O_cur->n_qubits);
   c.f32rec = O_cur->dtype == PAULI_C64K;
   c.has_comm = true;
+  c.ts = ts;
   c.H = view(H);
   c.O = view(O_cur);
   c.comm_group = 0;
@@ -1217,6 +1223,20 @@ int pauli_lanczos_step(const pauli_op* H, const pauli_op* O_prev, const pauli_op
   int rc = run_call(ar, ws, stream, c);
   if (b_out) *b_out = b;
   return rc;
+}
+
+int pauli_lanczos_step(const pauli_op* H, const pauli_op* O_prev, const pauli_op* O_cur,
+                       double b_prev, const pauli_trunc* t, uint32_t flags, pauli_op* O_next,
+                       double* b_out, pauli_ws* ws, void* stream) {
+  if (flags != 0) return PAULI_EINVAL;
+  return lanczos_step(H, O_prev, O_cur, b_prev, t, 0, O_next, b_out, ws, stream);
+}
+
+int pauli_lanczos_step_ts1d(const pauli_op* H0, const pauli_op* O_prev, const pauli_op* O_cur,
+                            double b_prev, const pauli_trunc* t, pauli_op* O_next,
+                            double* b_out, pauli_ws* ws, void* stream) {
+  if (!O_cur) return PAULI_EINVAL;
+  return lanczos_step(H0, O_prev, O_cur, b_prev, t, O_cur->n_qubits, O_next, b_out, ws, stream);
 }
 
 int pauli_rk4_step(const pauli_op* H, const pauli_op* O, double dt, const pauli_trunc* t,

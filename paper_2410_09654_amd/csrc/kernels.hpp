@@ -1190,6 +1190,42 @@ __global__ __launch_bounds__(256) void k_norm_bucket(const uint32_t* b_ubase,
   }
 }
 
+// k_norm_bucket for translation-symmetric operators: each merged unique
+// weighted by its stabilizer count (the norm of sum_k T_k(A) over N).
+template <int W>
+__global__ __launch_bounds__(256) void k_norm_bucket_ts(const uint32_t* b_ubase,
+                                                        const uint32_t* b_slots, const void* uk_,
+                                                        const double2* uc, int N, double2* part) {
+  __shared__ double rh[4], rl[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t b = blockIdx.x;
+  const uint32_t ub = b_ubase[b], ns = b_slots[b];
+  const Key<W>* uk = reinterpret_cast<const Key<W>*>(uk_) + ub;
+  dd s = dd_zero();
+  for (uint32_t i = tid; i < ns; i += 256) {
+    const Key<W> raw = unmix_key<W>(uk[i]);
+    const int st = ts_stabilizers<W>(raw.w, raw.w + W, N);
+    const double w2 = weight2(uc[ub + i]);
+    for (int r = 0; r < st; r++) s = dd_add(s, w2);
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    dd o;
+    o.hi = __shfl_down(s.hi, d, 64);
+    o.lo = __shfl_down(s.lo, d, 64);
+    if (lane < d) s = dd_add(s, o);
+  }
+  if (lane == 0) {
+    rh[wv] = s.hi;
+    rl[wv] = s.lo;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    dd t = {rh[0], rl[0]};
+    for (int w = 1; w < 4; w++) t = dd_add(t, dd{rh[w], rl[w]});
+    part[b] = make_double2(t.hi, t.lo);
+  }
+}
+
 // Totals of the per-bucket counters (one block): slots, survivors, keep-set
 // survivors, nonzero uniques.
 __global__ __launch_bounds__(1024) void k_bucket_totals(const uint32_t* b_slots,
@@ -1932,13 +1968,7 @@ __global__ __launch_bounds__(256) void k_norm_part_ts(const uint64_t* x, const u
       vx[w] = x[(size_t)w * cap + i];
       vz[w] = z[(size_t)w * cap + i];
     }
-    int st = 1;
-    for (int r = 1; r < N; r++) {
-      uint64_t tx[W], tz[W];
-      ts_rot_down<W>(vx, N, r, tx);
-      ts_rot_down<W>(vz, N, r, tz);
-      st += (num_cmp<W>(tx, vx) == 0 && num_cmp<W>(tz, vz) == 0) ? 1 : 0;
-    }
+    const int st = ts_stabilizers<W>(vx, vz, N);
     const double w2 = weight2(v);
     for (int r = 0; r < st; r++) s = dd_add(s, w2);
   }

@@ -378,8 +378,10 @@ def canonicalize(O: PauliOp, out: PauliOp | None = None, ws: Workspace | None = 
 
 def lanczos_step(H: PauliOp, O_prev: PauliOp | None, O_cur: PauliOp, b_prev: float,
                  trunc: Trunc | None = None, out: PauliOp | None = None,
-                 ws: Workspace | None = None):
-    """(O_next, b_n, breakdown) of one Liouvillian Lanczos step on the GPU."""
+                 ws: Workspace | None = None, ts1d: bool = False):
+    """(O_next, b_n, breakdown) of one Liouvillian Lanczos step on the GPU;
+    ts1d: H holds H0 and the operators orbit representatives of the periodic
+    chain (translation-symmetric step, Alg. 2)."""
     L = _lib.load()
     ws = ws or default_workspace(O_cur.device)
     if out is None:
@@ -394,14 +396,19 @@ def lanczos_step(H: PauliOp, O_prev: PauliOp | None, O_cur: PauliOp, b_prev: flo
 
     def fn(wss):
         outs = out.c_struct()
-        st = L.pauli_lanczos_step(ctypes.byref(hs), ctypes.byref(ps) if ps is not None else None,
-                                  ctypes.byref(cs), float(b_prev),
-                                  ctypes.byref(ts) if ts is not None else None, 0,
-                                  ctypes.byref(outs), ctypes.byref(bval), ctypes.byref(wss),
-                                  _stream_handle())
+        pp = ctypes.byref(ps) if ps is not None else None
+        tp = ctypes.byref(ts) if ts is not None else None
+        if ts1d:
+            st = L.pauli_lanczos_step_ts1d(ctypes.byref(hs), pp, ctypes.byref(cs), float(b_prev),
+                                           tp, ctypes.byref(outs), ctypes.byref(bval),
+                                           ctypes.byref(wss), _stream_handle())
+        else:
+            st = L.pauli_lanczos_step(ctypes.byref(hs), pp, ctypes.byref(cs), float(b_prev), tp,
+                                      0, ctypes.byref(outs), ctypes.byref(bval),
+                                      ctypes.byref(wss), _stream_handle())
         return st, outs
 
-    st = _call("pauli_lanczos_step", fn, ws, out)
+    st = _call("pauli_lanczos_step_ts1d" if ts1d else "pauli_lanczos_step", fn, ws, out)
     return out, bval.value, st == PAULI_BREAKDOWN
 
 

@@ -115,3 +115,55 @@ def test_lanczos_ts1d_matches_oracle_and_full_chain(pk, ws):
     Of = wl.single_site_sum(n, "Z", 1 / math.sqrt(n))
     b_full = pk.lanczos(raw(pk, Hf), up(pk, Of, ws), 8, ws=ws)
     assert np.allclose(b_ts, b_full, rtol=1e-12, atol=0)
+
+
+def test_lanczos_ts1d_xx_chain_closed_form(pk, ws):
+    """Periodic XX chain, N = 50, O0 = sum_j X_j / sqrt(N): b_n = sqrt(8n)
+    (Gaussian autocorrelation exp(-4t^2)) for n <= 24, untruncated."""
+    say("ts lanczos XX N=50 closed form")
+    n, steps = 50, 24
+    H0 = wl.from_terms(n, [(1.0, [("X", 1), ("X", 2)]), (1.0, [("Y", 1), ("Y", 2)])])
+    X1 = wl.from_terms(n, [(1.0, [("X", 1)])])
+    b = pk.lanczos_ts1d(raw(pk, H0), up(pk, X1, ws), steps, ws=ws)
+    assert np.allclose(np.array(b) ** 2, 8.0 * np.arange(1, steps + 1), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("name", ["xxx", "chaotic"])
+def test_lanczos_ts1d_paper_chains_match_oracle(pk, ws, name):
+    """The XXX chain with O0 ~ sum_j X_j Y_j+1 - Y_j X_j+1 and the chaotic
+    chain {XX, -1.05 Z, 0.5 X} with O0 ~ sum_j 1.05 X_j X_j+1 + Z_j, N = 50,
+    10 steps at M = 2^10."""
+    say(f"ts lanczos {name} N=50")
+    n = 50
+    if name == "xxx":
+        h = [(1.0, [(p, 1), (p, 2)]) for p in "XYZ"]
+        o = [(1.0, [("X", 1), ("Y", 2)]), (-1.0, [("Y", 1), ("X", 2)])]
+    else:
+        h = [(1.0, [("X", 1), ("X", 2)]), (-1.05, [("Z", 1)]), (0.5, [("X", 1)])]
+        o = [(1.05, [("X", 1), ("X", 2)]), (1.0, [("Z", 1)])]
+    H0, O0 = wl.from_terms(n, h), wl.from_terms(n, o)
+    O0.coef /= math.sqrt(oracle.norm2_ts(O0))
+    want = oracle.lanczos_ts(H0, O0, 10, oracle.Trunc(max_strings=1 << 10))
+    got = pk.lanczos_ts1d(raw(pk, H0), up(pk, O0, ws), 10, pk.Trunc(max_strings=1 << 10), ws=ws)
+    assert np.allclose(got, want, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("n,M", [(20, 0), (64, 500), (100, 300)])
+def test_lanczos_step_ts1d_operator(pk, ws, n, M):
+    """One fused step O_{n-2}, O_{n-1} -> O_n (representatives, truncated to M
+    when M > 0) equals the oracle's step, keys bit-exact; b_n within 1e-12."""
+    say(f"ts lanczos step n={n} M={M}")
+    H0 = chain_h0(n)
+    t = oracle.Trunc(max_strings=M) if M else oracle.NO_TRUNC
+    tg = pk.Trunc(max_strings=M) if M else None
+    Z1 = wl.from_terms(n, [(1.0, [("Z", 1)])])
+    O1, b1, _ = oracle.lanczos_step_ts(H0, None, Z1, 0.0, t)
+    O2, b2, _ = oracle.lanczos_step_ts(H0, Z1, O1, b1, t)
+    O3, b3, _ = oracle.lanczos_step_ts(H0, O1, O2, b2, t)
+    got, bg, broke = pk.lanczos_step(raw(pk, H0), up(pk, O1, ws), up(pk, O2, ws), b2, tg,
+                                     ws=ws, ts1d=True)
+    assert not broke
+    assert abs(bg - b3) <= 1e-12 * b3
+    g = got.to_host()
+    assert_canonical_unique(g)
+    assert_same_operator(g, O3, what="ts lanczos step")

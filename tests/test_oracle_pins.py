@@ -255,6 +255,47 @@ def test_ts_lanczos_equals_full_periodic_lanczos():
     assert np.allclose(b_ts, b_full, rtol=1e-12, atol=0)
 
 
+def _xx_periodic_dense(n):
+    """sum_j X_j X_j+1 + Y_j Y_j+1 (sites mod n) and sum_j X_j / sqrt(n) as dense matrices."""
+    d = 2 ** n
+
+    def site(p, j):
+        m = np.array([[1.0 + 0j]])
+        for s in range(n):
+            m = np.kron(m, p if s == j else np.eye(2))
+        return m
+    X, Y = SIGMA[(1, 0)], SIGMA[(1, 1)]
+    H = np.zeros((d, d), complex)
+    for j in range(n):
+        H += site(X, j) @ site(X, (j + 1) % n) + site(Y, j) @ site(Y, (j + 1) % n)
+    O = sum(site(X, j) for j in range(n)) / math.sqrt(n)
+    return H, O
+
+
+def test_xx_chain_gaussian_lanczos_closed_form():
+    """Periodic XX chain with O0 = sum_j X_j / sqrt(N): the infinite-temperature
+    autocorrelation of X_j is the Gaussian exp(-4t^2) (a free-fermion result),
+    whose Lanczos coefficients are b_n = sqrt(8n) while the operator's support
+    fits in the ring.  Checked first by a dense Lanczos recursion (N = 8,
+    Tr(A^dag B)/2^N), then on the oracle's translation-symmetric recursion
+    (Alg. 2 commutator and stabilizer-weighted norm) at N = 8 and N = 20."""
+    n = 8
+    H, O = _xx_periodic_dense(n)
+    d = 2 ** n
+    prev, cur, b_prev, bd = np.zeros_like(O), O, 0.0, []
+    for _ in range(4):
+        nxt = H @ cur - cur @ H - b_prev * prev
+        b = math.sqrt(np.vdot(nxt, nxt).real / d)
+        bd.append(b)
+        prev, cur, b_prev = cur, nxt / b, b
+    assert np.allclose(np.array(bd) ** 2, 8.0 * np.arange(1, 5), rtol=1e-12, atol=0)
+    for n, steps in ((8, 4), (20, 10)):
+        H0 = wl.from_terms(n, [(1.0, [("X", 1), ("X", 2)]), (1.0, [("Y", 1), ("Y", 2)])])
+        X1 = wl.from_terms(n, [(1.0, [("X", 1)])])
+        b_ts = oracle.lanczos_ts(H0, X1, steps)
+        assert np.allclose(np.array(b_ts) ** 2, 8.0 * np.arange(1, steps + 1), rtol=1e-12, atol=0)
+
+
 def test_add_norm_inner_vs_dense():
     n = 5
     A = wl.random_operator(n, 20, seed=11)
