@@ -520,6 +520,9 @@ int Engine::run(Call& c) {
   ea.wide = wide ? 1 : 0;
   uint32_t nbk = 0;  // buckets written so far
   int npass = 1 << pass_bits;
+  // the first count pass's prefixes stay in `counts` until a split count
+  // overwrites them
+  bool first_counts = pe_all < 0xFFFFFFFFull;
   for (bool done = false; !done;) {
     done = true;
     nbk = 0;
@@ -535,12 +538,23 @@ int Engine::run(Call& c) {
       ea.recs = precs;
       ea.psrc = psrc;
       ea.bin_base = pbase;
-      LAUNCH("k_emit_part_count", (k_emit<W, F32, false, PART_NBL>), rows, EMIT_THREADS, ea);
-      LAUNCH("k_scan_cols", k_scan_cols, (1 << PART_NBL) / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl,
-             1 << PART_NBL);
+      if (first_counts) {
+        // partition prefixes summed from the first count pass's bins, kept
+        // above its rows x NBINS entries: no second pass over the pairs
+        uint32_t* pcounts = counts + (size_t)rows * NBINS;
+        LAUNCH("k_part_from_bins", k_part_from_bins, rows + 1, 1024, counts, rows, pass_bits,
+               1 << PART_NBL, pcounts, bin_total);
+        ea.counts = pcounts;
+      } else {
+        LAUNCH("k_emit_part_count", (k_emit<W, F32, false, PART_NBL>), rows, EMIT_THREADS, ea);
+        LAUNCH("k_scan_cols", k_scan_cols, (1 << PART_NBL) / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl,
+               1 << PART_NBL);
+      }
       LAUNCH("k_scan_part", k_scan_part, 1, 1024, bin_total, npass, pbase, (1 << PART_NBL) + 1,
              dctl);
       LAUNCH("k_emit_part_scatter", (k_emit<W, F32, true, PART_NBL>), rows, EMIT_THREADS, ea);
+      ea.counts = counts;
+      first_counts = false;  // the split counts below reuse `counts`
       ea.part = 0;
       ea.recs = recs;
       ea.bin_base = bin_base;

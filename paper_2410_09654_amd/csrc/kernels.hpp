@@ -479,6 +479,46 @@ __global__ __launch_bounds__(1024) void k_scan_part(const uint32_t* total, int n
   if (t == 0) ctl->pe_total = tot;
 }
 
+// Partition prefixes from the first count pass, which binned every record by
+// the top NBINS_LOG bits of its order key and left, per bin, the exclusive
+// prefix over rows and the total.  A partition (top pass_bits bits) is an
+// aligned group of 2^(NBINS_LOG - pass_bits) bins, so its prefixes and total
+// are the sums of theirs.  Block r < rows writes row r of pc (ncol columns,
+// those at and above 2^pass_bits zero); block `rows` replaces the first
+// 2^pass_bits totals in place (all read before any is written).  The caller
+// guarantees fewer than 2^32 records, so no sum wraps.
+__global__ __launch_bounds__(1024) void k_part_from_bins(const uint32_t* counts, int rows,
+                                                         int pass_bits, int ncol, uint32_t* pc,
+                                                         uint32_t* total) {
+  const int r = blockIdx.x, t = threadIdx.x;
+  const int np = 1 << pass_bits, s = NBINS >> pass_bits;
+  if (r < rows) {
+    const uint32_t* row = counts + (size_t)r * NBINS;
+    for (int p = t; p < ncol; p += 1024) {
+      uint32_t v = 0u;
+      if (p < np)
+        for (int k = 0; k < s; k++) v += row[p * s + k];
+      pc[(size_t)r * ncol + p] = v;
+    }
+    return;
+  }
+  constexpr int PT = 4;  // partitions per thread: np <= 4096
+  uint32_t v[PT];
+#pragma unroll
+  for (int q = 0; q < PT; q++) {
+    const int p = t + q * 1024;
+    v[q] = 0u;
+    if (p < np)
+      for (int k = 0; k < s; k++) v[q] += total[p * s + k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PT; q++) {
+    const int p = t + q * 1024;
+    if (p < np) total[p] = v[q];
+  }
+}
+
 // Column-wise exclusive prefix of the counts matrix (rows x nbins, row
 // major) and the bin totals.  A block of SC_NSEG x SC_COLS threads covers
 // SC_COLS columns: thread (segment g, column b) loads rows
