@@ -182,16 +182,32 @@ def run_rk4_tfim(args):
 
 
 def run_lanczos_small(args):
-    """N=12 chain, O0 = Z_1, 12 untruncated FP64 Lanczos steps."""
+    """N=12 chain, O0 = Z_1, 12 untruncated FP64 Lanczos steps, timed (the
+    small operators make each step one library call at its host floor), with
+    the oracle's recursion on the same steps beside it."""
+    import torch
     import workloads as wl
     import paper_2410_09654_amd as pk
     H_host, O0_host, steps = wl.config_lanczos_small()
     H = pk.PauliOp.from_raw(12, H_host.x, H_host.z, H_host.coef)
-    bs, basis = pk.lanczos(H, pk.PauliOp.from_host(O0_host), steps, keep_basis=True)
+    O0 = pk.PauliOp.from_host(O0_host)
+    pk.lanczos(H, O0, steps)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bs, basis = pk.lanczos(H, O0, steps, keep_basis=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     counts = [B.size for B in basis[1:]]
     small = [int(np.sum(np.abs(B.to_host().coef) > 1e-12)) for B in basis[1:]]
-    print(json.dumps({"workload": "lanczos N=12 chain, O0 = Z_1", "b": bs,
-                      "strings": counts, "strings_above_1e-12": small}), flush=True)
+    line = {"workload": "lanczos N=12 chain, O0 = Z_1", "b": bs, "strings": counts,
+            "strings_above_1e-12": small, "seconds": wall, "ms_per_step": 1e3 * wall / len(bs)}
+    if args.cpu_sample > 0:
+        import oracle
+        tc = time.perf_counter()
+        bo = oracle.lanczos(H_host, O0_host, steps)
+        line["oracle"] = {"seconds": time.perf_counter() - tc, "cores": 1,
+                          "max_rel_diff_b": max(abs(a - b) / abs(b) for a, b in zip(bs, bo))}
+    print(json.dumps(line), flush=True)
 
 
 def run_moments(args):

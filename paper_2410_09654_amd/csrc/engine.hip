@@ -538,7 +538,7 @@ int Engine::run(Call& c) {
       ea.recs = precs;
       ea.psrc = psrc;
       ea.bin_base = pbase;
-      if (first_counts) {
+      if (first_counts && pass_bits <= 10) {
         // partition prefixes summed from the first count pass's bins, kept
         // above its rows x NBINS entries: no second pass over the pairs
         uint32_t* pcounts = counts + (size_t)rows * NBINS;

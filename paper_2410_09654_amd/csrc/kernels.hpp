@@ -483,39 +483,38 @@ __global__ __launch_bounds__(1024) void k_scan_part(const uint32_t* total, int n
 // the top NBINS_LOG bits of its order key and left, per bin, the exclusive
 // prefix over rows and the total.  A partition (top pass_bits bits) is an
 // aligned group of 2^(NBINS_LOG - pass_bits) bins, so its prefixes and total
-// are the sums of theirs.  Block r < rows writes row r of pc (ncol columns,
-// those at and above 2^pass_bits zero); block `rows` replaces the first
-// 2^pass_bits totals in place (all read before any is written).  The caller
-// guarantees fewer than 2^32 records, so no sum wraps.
+// are the sums of theirs.  Block r < rows reduces row r into row r of pc
+// (ncol columns, those at and above 2^pass_bits zero); block `rows` reduces
+// the bin totals and replaces the first 2^pass_bits of them in place (all
+// read before any is written).  Each thread sums 16 consecutive bins, then a
+// tree in LDS combines the 2^(10 - pass_bits) threads of a partition.
+// pass_bits <= 10; the caller guarantees fewer than 2^32 records, so no sum
+// wraps.
 __global__ __launch_bounds__(1024) void k_part_from_bins(const uint32_t* counts, int rows,
                                                          int pass_bits, int ncol, uint32_t* pc,
                                                          uint32_t* total) {
+  static_assert(NBINS == 16 * 1024, "one thread per 16 bins");
+  __shared__ uint32_t part[1024];
   const int r = blockIdx.x, t = threadIdx.x;
-  const int np = 1 << pass_bits, s = NBINS >> pass_bits;
-  if (r < rows) {
-    const uint32_t* row = counts + (size_t)r * NBINS;
-    for (int p = t; p < ncol; p += 1024) {
-      uint32_t v = 0u;
-      if (p < np)
-        for (int k = 0; k < s; k++) v += row[p * s + k];
-      pc[(size_t)r * ncol + p] = v;
-    }
-    return;
-  }
-  constexpr int PT = 4;  // partitions per thread: np <= 4096
-  uint32_t v[PT];
+  const int np = 1 << pass_bits, g = 1024 >> pass_bits;  // threads per partition
+  const uint32_t* src = r < rows ? counts + (size_t)r * NBINS : total;
+  const uint4* s4 = reinterpret_cast<const uint4*>(src) + 4 * t;
+  uint32_t v = 0u;
 #pragma unroll
-  for (int q = 0; q < PT; q++) {
-    const int p = t + q * 1024;
-    v[q] = 0u;
-    if (p < np)
-      for (int k = 0; k < s; k++) v[q] += total[p * s + k];
+  for (int q = 0; q < 4; q++) {
+    const uint4 u = s4[q];
+    v += u.x + u.y + u.z + u.w;
   }
+  part[t] = v;
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PT; q++) {
-    const int p = t + q * 1024;
-    if (p < np) total[p] = v[q];
+  for (int d = 1; d < g; d <<= 1) {
+    if ((t & (2 * d - 1)) == 0) part[t] += part[t + d];
+    __syncthreads();
+  }
+  if (r < rows) {
+    for (int p = t; p < ncol; p += 1024) pc[(size_t)r * ncol + p] = p < np ? part[p * g] : 0u;
+  } else if (t < np) {
+    total[t] = part[t * g];
   }
 }
 
