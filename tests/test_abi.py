@@ -64,3 +64,30 @@ def test_invalid_arguments_rejected_without_gpu_work():
     rc = L.pauli_lanczos_step(ctypes.byref(op), None, ctypes.byref(op), 0.0, None, 1,
                               ctypes.byref(op), None, ctypes.byref(ws), None)
     assert rc == _lib.PAULI_EINVAL
+
+
+def test_invalid_arguments_of_the_other_entry_points():
+    """The product, trace, noise, lookup and translation-symmetric entry points
+    also reject bad arguments on the host, before any HIP call."""
+    from paper_2410_09654_amd import _lib
+    L = _lib.load()
+    ws = _lib.PauliWsC(None, 0, 0)
+    bad = _lib.PauliOpC(200, 0, 0, 0, None, None, None)   # 200 qubits: unsupported
+    a10 = _lib.PauliOpC(10, 0, 0, 0, None, None, None)    # empty, valid
+    a12 = _lib.PauliOpC(12, 0, 0, 0, None, None, None)
+    r = ctypes.byref
+    d2 = (ctypes.c_double * 2)()
+    assert L.pauli_multiply(r(bad), r(a10), None, r(a10), r(ws), None) == _lib.PAULI_EINVAL
+    assert L.pauli_multiply(r(a10), r(a12), None, r(a12), r(ws), None) == _lib.PAULI_EINVAL
+    assert L.pauli_trace(r(bad), d2, r(ws), None) == _lib.PAULI_EINVAL
+    assert L.pauli_add_noise(r(a10), -1.0, None) == _lib.PAULI_EINVAL
+    assert L.pauli_add_noise(r(a10), float("nan"), None) == _lib.PAULI_EINVAL
+    assert L.pauli_coefficients(r(a10), r(a12), d2, r(ws), None) == _lib.PAULI_EINVAL
+    assert L.pauli_commutator_ts1d(r(a10), r(a12), None, r(a12), r(ws), None) == _lib.PAULI_EINVAL
+    assert L.pauli_canonicalize_ts1d(r(bad), r(a10), r(ws), None) == _lib.PAULI_EINVAL
+    assert L.pauli_norm2_ts1d(r(a10), None, r(ws), None) == _lib.PAULI_EINVAL
+    b = ctypes.c_double()
+    assert L.pauli_lanczos_step_ts1d(r(a10), None, None, 0.0, None, r(a10), r(b), r(ws),
+                                     None) == _lib.PAULI_EINVAL
+    assert L.pauli_lanczos_step_ts1d(r(a10), None, r(a12), 0.0, None, r(a12), r(b), r(ws),
+                                     None) == _lib.PAULI_EINVAL
