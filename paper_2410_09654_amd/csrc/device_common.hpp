@@ -212,35 +212,83 @@ DEV int ts_stabilizers(const uint64_t* x, const uint64_t* z, int N) {
   return 1;
 }
 
+// Occupied sites r (bit r of the result) that end a longest cyclic run of
+// empty sites, i.e. the rotations r (site r moved to site 0) whose occupied
+// pattern has the most leading zeros as an N-bit number: the only rotations
+// that can be smallest.  One-word strings (N <= 64) with at least one empty
+// site.  Bit s of A[j]: sites s, ..., s + 2^j - 1 (mod N) all empty; the
+// longest run G is then found by doubling and halving, and the runs of
+// length G that start at the set bits of `cur` end below sites s + G.
+DEV uint64_t ts_gap_candidates(uint64_t m, int N) {
+  const uint64_t mask = N == 64 ? ~0ull : ((1ull << N) - 1ull);
+  const uint64_t e = ~m & mask;
+  uint64_t A[6];
+  A[0] = e;
+  int lev = 0;
+#pragma unroll
+  for (int j = 1; j < 6; j++) {
+    if ((1 << (j - 1)) >= N) break;
+    uint64_t r;
+    ts_rot_down<1>(&A[j - 1], N, 1 << (j - 1), &r);
+    A[j] = A[j - 1] & r;
+    if (!A[j]) break;
+    lev = j;
+  }
+  uint64_t cur = A[lev];
+  int G = 1 << lev;  // a run of G empty sites starts at each set bit of cur; G < N
+#pragma unroll
+  for (int j = 4; j >= 0; j--) {
+    if (j >= lev) continue;
+    uint64_t r;
+    ts_rot_down<1>(&A[j], N, G, &r);
+    const uint64_t t = cur & r;
+    if (t) {
+      cur = t;
+      G += 1 << j;
+    }
+  }
+  uint64_t c;
+  ts_rot_down<1>(&cur, N, N - G, &c);  // bit s + G for every start s
+  return c;
+}
+
 // The orbit representative of the raw key k (x words, then z words), in place;
 // returns the rotation r (site r moved to site 0), the smallest one when
 // several give the representative.  Only rotations that bring an occupied
-// site to site 0 can be smallest.
+// site to site 0 can be smallest, and of those (one-word strings with more
+// than a few occupied sites) only the ones after a longest empty run.
 template <int W>
 DEV int ts_representative(uint64_t* k, int N) {
-  int best = 0;
-  uint64_t m[W], bm[W], bx[W], bz[W];
+  int best = -1;
+  uint64_t m[W], cand[W], bm[W], bx[W], bz[W];
 #pragma unroll
   for (int i = 0; i < W; i++) {
     m[i] = k[i] | k[W + i];
+    cand[i] = m[i];
     bm[i] = m[i];
     bx[i] = k[i];
     bz[i] = k[W + i];
   }
+  if constexpr (W == 1) {
+    const int p = __popcll(m[0]);
+    if (p > 6 && p < N) cand[0] = ts_gap_candidates(m[0], N);
+  }
 #pragma unroll
   for (int w = 0; w < W; w++) {
-    uint64_t bits = m[w];
+    uint64_t bits = cand[w];
     while (bits) {
       const int r = 64 * w + __builtin_ctzll(bits);
       bits &= bits - 1;
-      if (r == 0) continue;
       uint64_t tm[W], tx[W], tz[W];
       ts_rot_down<W>(m, N, r, tm);
       ts_rot_down<W>(k, N, r, tx);
       ts_rot_down<W>(k + W, N, r, tz);
-      int c = num_cmp<W>(tm, bm);
-      if (c == 0) c = num_cmp<W>(tx, bx);
-      if (c == 0) c = num_cmp<W>(tz, bz);
+      int c = -1;
+      if (best >= 0) {
+        c = num_cmp<W>(tm, bm);
+        if (c == 0) c = num_cmp<W>(tx, bx);
+        if (c == 0) c = num_cmp<W>(tz, bz);
+      }
       if (c < 0) {
         best = r;
 #pragma unroll
@@ -252,6 +300,7 @@ DEV int ts_representative(uint64_t* k, int N) {
       }
     }
   }
+  if (best < 0) return 0;  // the identity string
 #pragma unroll
   for (int i = 0; i < W; i++) {
     k[i] = bx[i];
