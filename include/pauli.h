@@ -10,9 +10,12 @@
  *
  * Memory and ownership
  *   - Every pointer inside pauli_op and pauli_ws is a DEVICE pointer owned by
- *     the caller.  The library never allocates or frees device memory, keeps
- *     no pointer after a call returns and keeps no state between calls
- *     (except the optional kernel-timing log, see pauli_profile_*).
+ *     the caller.  The library never allocates or frees device memory and
+ *     keeps no pointer to caller memory after a call returns.  State kept
+ *     between calls: a pinned host control block (under 1 KiB) per calling thread
+ *     (allocated with hipHostMalloc on the thread's first call, kept until the
+ *     process ends), the per-thread diagnostics below and the optional
+ *     kernel-timing log (pauli_profile_*).
  *   - x and z are word-major: word w of string k is x[w * capacity + k].
  *     coef holds `capacity` interleaved (re, im) pairs: double for
  *     PAULI_C128, float for PAULI_C64K.
