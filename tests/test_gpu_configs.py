@@ -1,0 +1,90 @@
+"""The RK4 and precision-split workloads at their full parameters, through the
+C ABI: element-wise against the oracle over the first steps (before the
+string budget binds, where the oracle still finishes in seconds), then
+properties that hold at any size once the budget binds.
+
+  * RK4: 8x8 open TFIM (J = 1, h_x = 2), O0 = Z(4,4), dt = 0.02,
+    M = 2^22, length <= 16, O0 kept.
+  * Lanczos precision split: N = 128 XXZ(0.5) + 0.3 r_i Z_i, O0 = sum X_i /
+    sqrt(N), M = 2^23, FP64 and FP32 + Kahan.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from helpers import assert_same_operator, gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2410_09654_amd as pk
+    pk._lib.load()
+    return pk
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def f32(op):
+    return wl.HostOp(op.n_qubits, op.x, op.z,
+                     op.coef.astype(np.complex64).astype(np.complex128))
+
+
+def test_rk4_tfim_full_parameters(pk):
+    import torch
+    H, O0 = wl.config_rk4_tfim()
+    M, L, dt = 1 << 22, 16, 0.02
+    ws = pk.Workspace(1 << 30)
+    Hd = pk.PauliOp.from_raw(64, H.x, H.z, H.coef)
+    Od = pk.PauliOp.from_host(O0, ws=ws)
+    tg = pk.Trunc(max_len=L, max_strings=M, keep=Od)
+    th = oracle.Trunc(max_len=L, max_strings=M, keep=O0)
+    cur_h, cur_d = O0, Od
+    for k in range(3):  # 50, 4100, 354934 strings: the budget does not bind yet
+        say(f"rk4 TFIM full parameters: step {k + 1} against the oracle")
+        cur_h = oracle.rk4_step(H, cur_h, dt, th)
+        cur_d = pk.rk4_step(Hd, cur_d, dt, tg, ws=ws)
+        assert_same_operator(cur_d.to_host(), cur_h, what=f"rk4 step {k + 1}")
+    for k in range(3, 6):  # the budget binds from step 4 on
+        say(f"rk4 TFIM full parameters: step {k + 1}, properties")
+        cur_d = pk.rk4_step(Hd, cur_d, dt, tg, ws=ws)
+        h = cur_d.to_host()
+        assert h.n == M
+        # i[H, O] of Hermitian strings with real coefficients is real: every
+        # coefficient stays exactly real
+        assert np.all(h.coef.imag == 0.0)
+        assert np.all(np.bitwise_count(h.x[:, 0] | h.z[:, 0]) <= L)
+        o = np.lexsort((h.z[:, 0], h.x[:, 0]))
+        sx, sz = h.x[o, 0], h.z[o, 0]
+        assert np.all((sx[1:] != sx[:-1]) | (sz[1:] != sz[:-1]))  # unique strings
+        assert np.any((h.x[:, 0] == O0.x[0, 0]) & (h.z[:, 0] == O0.z[0, 0]))  # O0 kept
+    del ws, Od, cur_d
+    torch.cuda.empty_cache()
+
+
+def test_lanczos_precision_split_full_parameters(pk):
+    import torch
+    H, O0 = wl.config_lanczos_split()
+    M, steps = 1 << 23, 4
+    ws = pk.Workspace(1 << 30)
+    Hd = pk.PauliOp.from_raw(128, H.x, H.z, H.coef)
+    say("precision split full parameters: 4 steps, FP64 and FP32 + Kahan, against the oracle")
+    want64 = oracle.lanczos(H, O0, steps, oracle.Trunc(max_strings=M))
+    want32 = oracle.lanczos(H, f32(O0), steps, oracle.Trunc(max_strings=M), prec=oracle.F32K)
+    got64 = pk.lanczos(Hd, pk.PauliOp.from_host(O0, ws=ws), steps, pk.Trunc(max_strings=M),
+                       ws=ws)
+    got32 = pk.lanczos(Hd, pk.PauliOp.from_host(f32(O0), dtype=pk.PAULI_C64K, ws=ws), steps,
+                       pk.Trunc(max_strings=M), ws=ws)
+    assert np.allclose(got64, want64, rtol=1e-12, atol=0)
+    assert np.allclose(got32, want32, rtol=1e-12, atol=0)
+    assert np.max(np.abs(np.array(got32) - np.array(got64)) / np.array(got64)) < 1e-6
+    del ws
+    torch.cuda.empty_cache()
