@@ -88,3 +88,26 @@ def test_lanczos_precision_split_full_parameters(pk):
     assert np.max(np.abs(np.array(got32) - np.array(got64)) / np.array(got64)) < 1e-6
     del ws
     torch.cuda.empty_cache()
+
+
+def test_noisy_xxz_full_parameters(pk):
+    """Noisy diffusion on the periodic XXZnnn chain (N = 30, delta = 2,
+    gamma = 1/2), O0 = Z_1, dt = 0.05, M = 2^18 with O0 kept, eps = 0.01:
+    two steps element-wise against the oracle (the second already trims to
+    M at every stage), with S(t) and the 30 correlators S_{1-j}(t)."""
+    import torch
+    H, O0, probes = wl.config_noisy_xxz()
+    n, dt, M, eps = H.n_qubits, 0.05, 1 << 18, 0.01
+    say("noisy XXZnnn full parameters: 2 steps against the oracle")
+    want_O, want_S, want_P = oracle.evolve_noisy(H, O0, dt, 2, M, eps, probes)
+    ws = pk.Workspace(1 << 30)
+    got_O, got_S, got_P = pk.evolve_noisy(
+        pk.PauliOp.from_raw(n, H.x, H.z, H.coef), pk.PauliOp.from_host(O0, ws=ws), dt, 2, M,
+        eps, probes=pk.PauliOp.from_raw(n, probes.x, probes.z, probes.coef), ws=ws)
+    g = got_O.to_host()
+    assert g.n == want_O.n == M
+    assert_same_operator(g, want_O, what="noisy O(2 dt)")
+    assert np.allclose(got_S, want_S, rtol=1e-12, atol=1e-15)
+    assert np.allclose(np.array(got_P), np.array(want_P), rtol=1e-12, atol=1e-15)
+    del ws, got_O
+    torch.cuda.empty_cache()
