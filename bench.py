@@ -397,7 +397,7 @@ def run_surrogate(args):
     hz ~ U[0,1], seed 5) of the N=64 Ising chain with O0 = sum Z_i/sqrt(N),
     truncated Lanczos to 46 steps at M = 2^20 for training; 64 held-out
     couplings (seed 55) computed to 30 steps and continued to 46 by one
-    network pass, judged by their plain 46-step recursion."""
+    network pass, scored against their plain 46-step recursion."""
     import math
     import torch
     import workloads as wl

@@ -5,7 +5,7 @@ consecutive Lanczos coefficients b_n, scaled by the window mean, and predicts
 the next 16.  It is trained on the GPU by the library's own BF16 matrix-core
 forward and backward kernels (pauli_mlp_*) on b_n sequences that the Lanczos
 recursion of this library computed, and the plain truncated recursion remains
-its fallback and the judge of its error.  The paper notes that a few Lanczos
+its fallback and the reference for its error.  The paper notes that a few Lanczos
 coefficients can suffice to estimate long-time dynamics; this component
 extrapolates the sequence beyond the computed depth.
 

@@ -153,8 +153,9 @@ def lanczos_tables(pk, couplings, steps, M, n=64):
 def test_trained_network_gains_over_extrapolation(sg):
     """Train on 46-step b_n runs of 512 random couplings, then continue 64
     held-out couplings from b_15..b_30 to b_46 in one network pass; the plain
-    truncated Lanczos recursion run to 46 steps judges the result against
-    holding b_30 constant and a least-squares line through b_15..b_30."""
+    truncated Lanczos recursion run to 46 steps is the reference, and the network
+    is compared with holding b_30 constant and a least-squares line through
+    b_15..b_30."""
     import torch
     import paper_2410_09654_amd as pk
     M = 1 << 16
