@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_sel_pass1(Sel2Args a) {
     for (uint32_t i0 = 0; i0 < ns; i0 += 64) {
       const uint32_t i = i0 + lane;
       bool cand = false;
-      const double2 v = vn;  // this round's value; the next round's load is issued now
+      const double2 v = vn;  // this iteration's value; the next iteration's load is issued now
       if (i + 64 < ns) vn = a.uc[ub + i + 64];
       if (i < ns) {
         if (!is_zero(v)) {
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(256) void k_write_out(WriteArgs a, uint32_t nbk) {
       const uint32_t i = i0 + lane;
       bool s = false, have_raw = false;
       Key<W> raw;
-      const double2 v = vn;  // this round's value; the next round's load is issued now
+      const double2 v = vn;  // this iteration's value; the next iteration's load is issued now
       if (i + 64 < ns) vn = a.uc[ub + i + 64];
       if (i < ns) {
         if (!is_zero(v)) {
