@@ -167,3 +167,24 @@ def test_lanczos_step_ts1d_operator(pk, ws, n, M):
     g = got.to_host()
     assert_canonical_unique(g)
     assert_same_operator(g, O3, what="ts lanczos step")
+
+
+@pytest.mark.parametrize("n", [8, 64, 100])
+def test_lanczos_step_ts1d_periodic_strings_in_norm(pk, ws, n):
+    """The fused step's norm weights every representative by its stabilizer
+    count: O_prev holds strings of period 1, 2 and 4, which reach O'_n
+    through -b_prev O_prev; b_n and O_n equal the oracle's step."""
+    say(f"ts lanczos step, periodic strings, n={n}")
+    H0 = chain_h0(n)
+    P = oracle.canonicalize_ts(wl.from_terms(n, [
+        (0.6, [("Z", j) for j in range(1, n + 1)]),                 # period 1
+        (-0.3j, [("X", j) for j in range(1, n + 1, 2)]),            # period 2
+        (0.25, [("Y", j) for j in range(1, n + 1, 4)]),             # period 4
+        (0.4, [("X", 1), ("Z", 2)])]))
+    C = oracle.canonicalize_ts(wl.random_local_strings(n, 60, min(6, n), seed=n))
+    want, bw, _ = oracle.lanczos_step_ts(H0, P, C, 0.7)
+    got, bg, broke = pk.lanczos_step(raw(pk, H0), up(pk, P, ws), up(pk, C, ws), 0.7, ws=ws,
+                                     ts1d=True)
+    assert not broke
+    assert abs(bg - bw) <= 1e-12 * bw
+    assert_same_operator(got.to_host(), want, what="ts step with periodic strings")
