@@ -305,8 +305,10 @@ int Engine::run(Call& c) {
     g_last_error = "H has more strings than one merge bucket holds";
     return PAULI_EINVAL;
   }
-  // at most 2^18 (commutator) and 2^17 (operator terms) threads of emit rows
-  constexpr int64_t COMM_ROWS_MAX = (1 << 18) / EMIT_THREADS, TERM_ROWS_MAX = (1 << 17) / EMIT_THREADS;
+  // at most 1024 commutator rows (one tile of EMIT_THREADS O strings each up
+  // to |O| = 2^20: more, shorter rows scatter faster, since twice as many
+  // workgroups fit a CU as there are CUs) and 128 rows of operator terms
+  constexpr int64_t COMM_ROWS_MAX = 1024, TERM_ROWS_MAX = (1 << 17) / EMIT_THREADS;
   static_assert(COMM_ROWS_MAX + TERM_ROWS_MAX <= SC_ROWS_MAX, "k_scan_cols covers every count row");
   int comm_rows = comm ? (int)std::min<int64_t>((c.O.n + EMIT_THREADS - 1) / EMIT_THREADS, COMM_ROWS_MAX) : 0;
   int term_rows = nterm_rec > 0 ? (int)std::min<int64_t>((nterm_rec + EMIT_THREADS - 1) / EMIT_THREADS, TERM_ROWS_MAX) : 0;

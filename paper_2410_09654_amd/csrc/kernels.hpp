@@ -524,7 +524,7 @@ __global__ __launch_bounds__(1024) void k_part_from_bins(const uint32_t* counts,
 // [SC_SEG g, SC_SEG g + SC_SEG) of column b all at once, the segment sums of
 // a column are combined in LDS, and each thread writes its rows' prefixes.
 // rows <= SC_NSEG * SC_SEG.
-constexpr int SC_COLS = 32, SC_SEG = 32, SC_NSEG = 16;
+constexpr int SC_COLS = 32, SC_SEG = 36, SC_NSEG = 32;
 constexpr int SC_ROWS_MAX = SC_SEG * SC_NSEG;
 __global__ __launch_bounds__(SC_COLS * SC_NSEG) void k_scan_cols(uint32_t* counts, int rows,
                                                                  uint32_t* bin_total, Ctl* ctl,
