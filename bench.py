@@ -544,11 +544,14 @@ def main():
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(dom), "alg_bytes_per_launch": alg_bytes[dom],
                     "avg_ms_timed_region": ms / c, "launches_timed_region": c}
-        # merge + truncate stage: every kernel after the two emission passes,
-        # from the per-kernel pass
+        # merge + truncate stage: every kernel after the scatter (the
+        # emission stage is H preparation, the count pass, its two scans and
+        # the scatter), from the per-kernel pass
         np_steps = min(args.steps, 10)
+        emission = ("k_prep_h", "k_mix_keys", "k_fill_u32", "k_emit_count", "k_scan_cols",
+                    "k_scan_bins", "k_emit_scatter")
         mt_ms = sum(per_kernel[k]["total_ms"] for k in per_kernel
-                    if k not in ("k_emit_count", "k_emit_scatter")) / np_steps
+                    if k not in emission) / np_steps
         mt_bytes = (pe + 2 * u + m_out) * R_BYTES
         roofline["merge_truncate"] = {"ms_per_step": round(mt_ms, 4),
                                       "alg_bytes": mt_bytes,
