@@ -460,12 +460,16 @@ int Engine::run(Call& c) {
   // several passes: every record is emitted once into 2^pass_bits partitions
   // (full order keys, source ids aside); each pass bins one partition
   constexpr int PART_NBL = 12;  // at most 2^12 partitions (MAX_PASS_BITS)
-  constexpr int SPLIT_ROWS = 256;  // blocks binning one partition
+  // blocks binning one partition: 1024 (one per CU, LDS-bound, so four
+  // rounds) write shorter per-(block, bin) runs and beat 256 and 512
+  constexpr int SPLIT_ROWS = 1024;
   static_assert(SPLIT_ROWS <= SC_ROWS_MAX, "k_scan_cols covers every split row");
   const bool partitioned = nbl == NBINS_LOG_MP;
   void* precs = partitioned ? ar->take(ptot * RB) : nullptr;
   uint32_t* psrc = partitioned ? (uint32_t*)ar->take(ptot * 4) : nullptr;
   uint32_t* pbase = partitioned ? (uint32_t*)ar->take(((1u << PART_NBL) + 1) * 4) : nullptr;
+  uint32_t* scounts =
+      partitioned ? (uint32_t*)ar->take((size_t)SPLIT_ROWS * NBINS_MP * 4) : nullptr;
   void* uk = ar->take(ptot * KB);
   double2* uc = (double2*)ar->take(ptot * sizeof(double2));
   uint32_t* b_ubase = (uint32_t*)ar->take((size_t)max_buckets * 4);
@@ -522,8 +526,8 @@ int Engine::run(Call& c) {
   ea.wide = wide ? 1 : 0;
   uint32_t nbk = 0;  // buckets written so far
   int npass = 1 << pass_bits;
-  // the first count pass's prefixes stay in `counts` until a split count
-  // overwrites them
+  // the first count pass's prefixes (in `counts`) and bin totals (in
+  // bin_total) serve the first partitioning only
   bool first_counts = pe_all < 0xFFFFFFFFull;
   for (bool done = false; !done;) {
     done = true;
@@ -556,7 +560,7 @@ int Engine::run(Call& c) {
              dctl);
       LAUNCH("k_emit_part_scatter", (k_emit<W, F32, true, PART_NBL>), rows, EMIT_THREADS, ea);
       ea.counts = counts;
-      first_counts = false;  // the split counts below reuse `counts`
+      first_counts = false;  // bin_total now holds partition, then split, totals
       ea.part = 0;
       ea.recs = recs;
       ea.bin_base = bin_base;
@@ -565,7 +569,7 @@ int Engine::run(Call& c) {
       sp.pbase = pbase;
       sp.pass_bits = pass_bits;
       sp.wide = wide ? 1 : 0;
-      sp.counts = counts;
+      sp.counts = scounts;
       sp.bin_base = bin_base;
       sp.recs = recs;
       sp.rsrc_wide = rsrc_wide;
@@ -577,7 +581,7 @@ int Engine::run(Call& c) {
         uint32_t* zero = p == 0 ? hist0 : (uint32_t*)nullptr;
         const uint32_t nzero = p == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
         LAUNCH("k_split_count", (k_split<W, F32, false, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
-        LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, counts, SPLIT_ROWS, bin_total,
+        LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, scounts, SPLIT_ROWS, bin_total,
                dctl, NBINS_MP);
         LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
                nzero);
