@@ -188,3 +188,18 @@ def test_lanczos_step_ts1d_periodic_strings_in_norm(pk, ws, n):
     assert not broke
     assert abs(bg - bw) <= 1e-12 * bw
     assert_same_operator(got.to_host(), want, what="ts step with periodic strings")
+
+
+def test_commutator_ts1d_fp32(pk, ws):
+    """FP32 coefficients (PAULI_C64K, Kahan sums): the same representatives as
+    the FP64 oracle on the FP32-rounded input, values within FP32 rounding."""
+    say("ts commutator fp32 n=64")
+    n = 64
+    H0 = chain_h0(n)
+    O0 = oracle.canonicalize_ts(wl.random_local_strings(n, 2000, 8, seed=77))
+    O0 = wl.HostOp(n, O0.x, O0.z, O0.coef.astype(np.complex64).astype(np.complex128))
+    want = oracle.commutator_ts(H0, O0)
+    got = pk.commutator_ts1d(raw(pk, H0), up(pk, O0, ws, dtype=pk.PAULI_C64K), ws=ws).to_host()
+    assert_same_operator(got, want, rtol=1e-5, what="fp32 ts commutator")
+    n2 = pk.norm2_ts1d(up(pk, O0, ws, dtype=pk.PAULI_C64K), ws=ws)
+    assert abs(n2 - oracle.norm2_ts(O0)) <= 1e-12 * n2
