@@ -110,3 +110,19 @@ def test_noisy_evolution_total_z_invariant(pk, ws):
     for k in range(steps + 1):
         assert abs(sum(P[k]) - math.exp(-eps * k * dt)) < 1e-12, k
         assert S[k] == P[k][0]
+
+
+def test_coefficients_lookup_fp32_operand(pk, ws):
+    """An FP32 operand (PAULI_C64K): the looked-up values are its stored
+    floats, widened exactly."""
+    say("coefficients lookup fp32")
+    n = 100
+    A = wl.random_operator(n, 3000, seed=5, density=0.1)
+    Q = wl.HostOp(n, A.x[::7], A.z[::7], np.ones(len(A.x[::7]), complex))
+    A32 = up(pk, A, ws, dtype=pk.PAULI_C64K)
+    got = pk.coefficients(A32, pk.PauliOp.from_raw(n, Q.x, Q.z, Q.coef), ws=ws)
+    h = A32.to_host()
+    d = {k: v for k, v in zip(h.keys(), h.coef)}
+    want = np.array([d.get(k, 0j) for k in Q.keys()])
+    assert np.array_equal(got, want)
+    assert np.array_equal(want, A.coef[::7].astype(np.complex64).astype(np.complex128))
