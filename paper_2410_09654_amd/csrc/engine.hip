@@ -329,6 +329,8 @@ int Engine::run(Call& c) {
   histL[0] = (uint32_t*)ar->take((size_t)HREP * SEL_BINS * 4);
   histL[1] = (uint32_t*)ar->take((size_t)HREP * SEL_BINS * 4);
   uint32_t* hsum = (uint32_t*)ar->take(SEL_BINS * 4);
+  uint32_t* h0sum = (uint32_t*)ar->take(SEL0_BINS * 4);
+  unsigned long long* psum = (unsigned long long*)ar->take(PLAN_PARTS * 4 * 8);
   if (ar->short_) return PAULI_EWORKSPACE;
   TRY(host_ctl(&hctl));
   // the control block starts at zero (cleared by k_prep_h when there is one)
@@ -720,7 +722,10 @@ int Engine::run(Call& c) {
   pa.max_strings = want_select ? (long long)tr->max_strings : 0;
   pa.hist0 = hist0;
   pa.hist1 = want_select ? histL[1] : nullptr;
+  pa.psum = psum;
+  pa.h0sum = h0sum;
   pa.ctl = dctl;
+  LAUNCH("k_plan_sums", k_plan_sums, 3 * PLAN_PARTS, 1024, pa);
   LAUNCH("k_sel_plan", k_sel_plan, 1, 1024, pa);
   if (want_select) {
     LAUNCH("k_sel_pass1", (k_sel_pass1<W>), nchunk, 256, s2);

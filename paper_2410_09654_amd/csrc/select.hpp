@@ -90,66 +90,78 @@ struct PlanArgs {
   long long max_strings;
   const uint32_t* hist0;     // HREP replicas of the level-0 |c|^2 histogram (SEL0_BINS each)
   uint32_t* hist1;           // digit-1 histogram replicas, cleared here (nullable)
+  unsigned long long* psum;  // [PLAN_PARTS][4] partial counter sums (k_plan_sums)
+  uint32_t* h0sum;           // [SEL0_BINS] the level-0 histogram, replicas summed
   Ctl* ctl;
 };
 
-// Totals of the per-bucket counters, the select mode, and the level-0 bin of
-// the threshold (one block of 1024 threads).  Clears the digit-1 histogram
-// for k_sel_pass1.
-__global__ __launch_bounds__(1024) void k_sel_plan(PlanArgs a) {
+// Reductions feeding k_sel_plan, spread over 3 x PLAN_PARTS blocks of 1024
+// threads: blocks [0, P) sum the four per-bucket counters over a P-th of the
+// buckets each, blocks [P, 2P) sum the HREP replicas of SEL0_BINS / P bins
+// of the level-0 histogram each, blocks [2P, 3P) clear a P-th of the digit-1
+// replicas.
+constexpr int PLAN_PARTS = 16;
+static_assert(SEL0_BINS == PLAN_PARTS * 256 && HREP % 4 == 0 &&
+                  HREP * SEL_BINS == PLAN_PARTS * 4096,
+              "k_plan_sums: 256 level-0 bins and 4096 digit-1 words per block");
+__global__ __launch_bounds__(1024) void k_plan_sums(PlanArgs a) {
   __shared__ unsigned long long red[4][16];
+  __shared__ uint32_t hr[4][256];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int blk = blockIdx.x;
+  if (blk < PLAN_PARTS) {
+    const uint32_t chunk = (a.nbk + PLAN_PARTS - 1) / PLAN_PARTS;
+    const uint32_t b0 = min(a.nbk, blk * chunk), b1 = min(a.nbk, b0 + chunk);
+    unsigned long long v[4] = {0, 0, 0, 0};
+    for (uint32_t b = b0 + t; b < b1; b += 1024) {
+      v[0] += a.b_slots[b];
+      v[1] += a.b_surv[b];
+      v[2] += a.b_keep[b];
+      if (a.b_unique) v[3] += a.b_unique[b];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      unsigned long long x = v[q];
+      for (int d = 32; d >= 1; d >>= 1) x += __shfl_down(x, d, 64);
+      if (lane == 0) red[q][wv] = x;
+    }
+    __syncthreads();
+    if (t < 4) {
+      unsigned long long s = 0;
+      for (int w = 0; w < 16; w++) s += red[t][w];
+      a.psum[blk * 4 + t] = s;
+    }
+  } else if (blk < 2 * PLAN_PARTS) {
+    const int bin = (blk - PLAN_PARTS) * 256 + (t & 255), g = t >> 8;
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = g; r < HREP; r += 4) s += a.hist0[(size_t)r * SEL0_BINS + bin];
+    hr[g][t & 255] = s;
+    __syncthreads();
+    if (t < 256) a.h0sum[bin] = hr[0][t] + hr[1][t] + hr[2][t] + hr[3][t];
+  } else if (a.hist1) {
+    uint4* z = reinterpret_cast<uint4*>(a.hist1) + (size_t)(blk - 2 * PLAN_PARTS) * 1024;
+    z[t] = make_uint4(0u, 0u, 0u, 0u);
+  }
+}
+
+// Totals of the per-bucket counters, the select mode, and the level-0 bin of
+// the threshold (one block of 1024 threads), from the sums of k_plan_sums.
+__global__ __launch_bounds__(1024) void k_sel_plan(PlanArgs a) {
   __shared__ unsigned long long tmp[19];
   __shared__ uint32_t hs[SEL0_BINS];
   __shared__ unsigned long long s_K;
   __shared__ int s_mode;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  // the level-0 histogram (its HREP replicas summed), loaded up front
+  const int t = threadIdx.x;
+  // the level-0 histogram and the counter totals, reduced by k_plan_sums
   constexpr int BPT0 = SEL0_BINS / 1024;
   uint32_t h0[BPT0];
 #pragma unroll
-  for (int k = 0; k < BPT0; k++) {
-    h0[k] = 0;
-#pragma unroll
-    for (int r = 0; r < HREP; r++) h0[k] += a.hist0[(size_t)r * SEL0_BINS + k * 1024 + t];
-  }
-  if (a.hist1) {
-    uint4* z = reinterpret_cast<uint4*>(a.hist1);
-#pragma unroll 4
-    for (int i = t; i < HREP * SEL_BINS / 4; i += 1024) z[i] = make_uint4(0u, 0u, 0u, 0u);
-  }
-  unsigned long long v[4] = {0, 0, 0, 0};
-  // four buckets per thread and step (16-byte loads; the arena aligns the tables)
-  const uint32_t nb4 = a.nbk / 4;
-#pragma unroll 4
-  for (uint32_t q = t; q < nb4; q += 1024) {
-    const uint4 s0 = reinterpret_cast<const uint4*>(a.b_slots)[q];
-    const uint4 s1 = reinterpret_cast<const uint4*>(a.b_surv)[q];
-    const uint4 s2 = reinterpret_cast<const uint4*>(a.b_keep)[q];
-    v[0] += (unsigned long long)s0.x + s0.y + s0.z + s0.w;
-    v[1] += (unsigned long long)s1.x + s1.y + s1.z + s1.w;
-    v[2] += (unsigned long long)s2.x + s2.y + s2.z + s2.w;
-    if (a.b_unique) {
-      const uint4 s3 = reinterpret_cast<const uint4*>(a.b_unique)[q];
-      v[3] += (unsigned long long)s3.x + s3.y + s3.z + s3.w;
-    }
-  }
-  for (uint32_t b = nb4 * 4 + t; b < a.nbk; b += 1024) {
-    v[0] += a.b_slots[b];
-    v[1] += a.b_surv[b];
-    v[2] += a.b_keep[b];
-    if (a.b_unique) v[3] += a.b_unique[b];
-  }
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    unsigned long long x = v[q];
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_down(x, d, 64);
-    if (lane == 0) red[q][wv] = x;
-  }
-  __syncthreads();
+  for (int k = 0; k < BPT0; k++) h0[k] = a.h0sum[k * 1024 + t];
   if (t == 0) {
     unsigned long long tot[4] = {0, 0, 0, 0};
     for (int q = 0; q < 4; q++)
-      for (int w = 0; w < 16; w++) tot[q] += red[q][w];
+      for (int p = 0; p < PLAN_PARTS; p++) tot[q] += a.psum[p * 4 + q];
     a.ctl->u_slots = tot[0];
     a.ctl->surv_total = tot[1];
     a.ctl->keep_total = tot[2];
