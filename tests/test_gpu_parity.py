@@ -398,3 +398,20 @@ def test_multi_pass_truncate(pk, n, count, f32):
     assert (np.lexsort(k.T[::-1]) == np.arange(len(k))).all()
     del O, got, ws
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,nh", [(64, 1976), (128, 1336)])
+def test_commutator_largest_h(pk, ws, n, nh):
+    """|H| at the largest size one merge bucket admits (1984 - 8 one-word,
+    1344 - 8 two-word slots): every output string can collect a contribution
+    from every H string; one more H string is rejected with PAULI_EINVAL."""
+    say(f"commutator largest H n={n} nh={nh}")
+    H = wl.random_operator(n, nh, seed=n + nh, density=4.0 / n)
+    O = wl.random_operator(n, 200, seed=n + 1, density=4.0 / n)
+    want = oracle.commutator(H, O)
+    got = pk.commutator(uph(pk, H), up(pk, O, ws), ws=ws).to_host()
+    assert_canonical_unique(got)
+    assert_same_operator(got, want, what="largest H")
+    H1 = wl.random_operator(n, nh + 1, seed=n + nh + 1, density=4.0 / n)
+    with pytest.raises(pk.PauliError):
+        pk.commutator(uph(pk, H1), up(pk, O, ws), ws=ws)
