@@ -656,7 +656,7 @@ int Engine::run(Call& c) {
              c.ts, norm_part);
     else
       LAUNCH("k_norm_bucket", k_norm_bucket, nbk, 256, b_ubase, b_slots, uc, norm_part);
-    LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, norm_part, nbk, &dctl->norm_hi);
+    LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, norm_part, nbk, &dctl->norm_hi);
     TRY(read_ctl());
     if (hctl->overflow) {
       g_last_error = "merge bucket overflow";
@@ -1114,7 +1114,7 @@ int pauli_norm2_ts1d(const pauli_op* A, double* out, pauli_ws* ws, void* stream_
       LAUNCH("k_norm_part_ts", (k_norm_part_ts<2, false>), blocks, 256, A->x, A->z, A->capacity,
              A->coef, A->size, N, part);
   }
-  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, part, (uint32_t)blocks, res);
+  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, part, (uint32_t)blocks, res);
   double h[2];
   HIP_TRY(hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -1436,7 +1436,7 @@ int pauli_norm2(const pauli_op* A, double* out, pauli_ws* ws, void* stream_) {
     LAUNCH("k_norm_part", k_norm_part<true>, blocks, 256, A->coef, A->size, part);
   else
     LAUNCH("k_norm_part", k_norm_part<false>, blocks, 256, A->coef, A->size, part);
-  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, part, (uint32_t)blocks, res);
+  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, part, (uint32_t)blocks, res);
   double h[2];
   HIP_TRY(hipMemcpyAsync(h, res, 16, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -1478,8 +1478,8 @@ int pauli_inner(const pauli_op* A, const pauli_op* B, double out[2], pauli_ws* w
            A->coef, A->dtype == PAULI_C64K, (const Key<2>*)bmk, B->size, B->coef,
            B->dtype == PAULI_C64K, pr, pi);
   }
-  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, pr, (uint32_t)blocks, res);
-  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 256, pi, (uint32_t)blocks, res + 2);
+  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, pr, (uint32_t)blocks, res);
+  LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, pi, (uint32_t)blocks, res + 2);
   double h[4];
   unsigned int bad = 0;
   HIP_TRY(hipMemcpyAsync(h, res, 32, hipMemcpyDeviceToHost, stream));

@@ -1299,27 +1299,36 @@ __global__ __launch_bounds__(1024) void k_bucket_totals(const uint32_t* b_slots,
 }
 
 // Deterministic double-double sum of n partials (one block).
-__global__ __launch_bounds__(256) void k_reduce_dd(const double2* part, uint32_t n, double* out) {
-  __shared__ double rh[4], rl[4];
+__global__ __launch_bounds__(1024) void k_reduce_dd(const double2* part, uint32_t n, double* out) {
+  // four independent double-double chains per thread (partials i, i + 1024,
+  // i + 2048, i + 3072 of every 4096), combined in a fixed order
+  __shared__ double rh[16], rl[16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  dd s = dd_zero();
-  for (uint32_t i = tid; i < n; i += 256) s = dd_add(s, dd{part[i].x, part[i].y});
+  dd s[4] = {dd_zero(), dd_zero(), dd_zero(), dd_zero()};
+  for (uint32_t i0 = 0; i0 < n; i0 += 4096) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const uint32_t i = i0 + q * 1024 + tid;
+      if (i < n) s[q] = dd_add(s[q], dd{part[i].x, part[i].y});
+    }
+  }
+  dd t = dd_add(dd_add(s[0], s[1]), dd_add(s[2], s[3]));
   for (int d = 32; d >= 1; d >>= 1) {
     dd o;
-    o.hi = __shfl_down(s.hi, d, 64);
-    o.lo = __shfl_down(s.lo, d, 64);
-    if (lane < d) s = dd_add(s, o);
+    o.hi = __shfl_down(t.hi, d, 64);
+    o.lo = __shfl_down(t.lo, d, 64);
+    if (lane < d) t = dd_add(t, o);
   }
   if (lane == 0) {
-    rh[wv] = s.hi;
-    rl[wv] = s.lo;
+    rh[wv] = t.hi;
+    rl[wv] = t.lo;
   }
   __syncthreads();
   if (tid == 0) {
-    dd t = {rh[0], rl[0]};
-    for (int w = 1; w < 4; w++) t = dd_add(t, dd{rh[w], rl[w]});
-    out[0] = t.hi;
-    out[1] = t.lo;
+    dd u = {rh[0], rl[0]};
+    for (int w = 1; w < 16; w++) u = dd_add(u, dd{rh[w], rl[w]});
+    out[0] = u.hi;
+    out[1] = u.lo;
   }
 }
 
