@@ -133,7 +133,11 @@ __device__ __forceinline__ uint32_t layout_row(uint32_t b, uint32_t n) {
 }
 
 template <int W, bool F32, bool SCATTER, int NBL>
-__global__ __launch_bounds__(EMIT_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void k_emit(EmitArgs a) {
+// Eight waves per SIMD (two workgroups per CU) where registers and LDS allow;
+// two-word strings need more than 64 registers per lane in the pair loop and
+// 2^15 bins fill the LDS of a CU, so those aim at four.
+__global__ __launch_bounds__(EMIT_THREADS)
+__attribute__((amdgpu_waves_per_eu(W == 1 && NBL <= 14 ? 8 : 4))) void k_emit(EmitArgs a) {
   constexpr int NB = 1 << NBL;  // hash bins of this call
   using V = RecV<F32>;
   __shared__ uint32_t hist[NB];
