@@ -434,21 +434,37 @@ __global__ __launch_bounds__(1024) void k_split(SplitArgs a) {
   const uint64_t* in = reinterpret_cast<const uint64_t*>(a.precs);
   uint64_t* out = reinterpret_cast<uint64_t*>(a.recs);
   const int F = NBL + a.pass_bits;
-  for (uint32_t i = r0 + tid; i < r1; i += 1024) {
-    uint64_t rw[RW];
+  // SB records per thread and step, all loaded before any is binned, so that
+  // each wave keeps SB loads in flight
+  constexpr int SB = 4;
+  for (uint32_t i0 = r0 + tid; i0 < r1; i0 += SB * 1024) {
+    uint64_t rw[SB][RW];
+    uint32_t src[SB];
 #pragma unroll
-    for (int q = 0; q < RW; q++) rw[q] = in[(size_t)i * RW + q];
-    const uint32_t bin = (uint32_t)((rw[0] << a.pass_bits) >> (64 - NBL));
-    const uint32_t pos = atomicAdd(&hist[bin], 1u);
-    if (SCATTER) {
-      const uint32_t src = a.psrc[i];
-      const uint64_t small =
-          a.wide ? 0ull
-                 : (((uint64_t)(src >> GROUP_SHIFT) << (F - 3)) | (src & ((1u << GROUP_SHIFT) - 1u)));
-      rw[0] = (small << (64 - F)) | (rw[0] & (~0ull >> F));
+    for (int u = 0; u < SB; u++) {
+      const uint32_t i = i0 + u * 1024;
+      if (i < r1) {
 #pragma unroll
-      for (int q = 0; q < RW; q++) out[(size_t)pos * RW + q] = rw[q];
-      if (a.wide) a.rsrc_wide[pos] = src;
+        for (int q = 0; q < RW; q++) rw[u][q] = in[(size_t)i * RW + q];
+        if (SCATTER) src[u] = a.psrc[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SB; u++) {
+      const uint32_t i = i0 + u * 1024;
+      if (i >= r1) break;
+      const uint32_t bin = (uint32_t)((rw[u][0] << a.pass_bits) >> (64 - NBL));
+      const uint32_t pos = atomicAdd(&hist[bin], 1u);
+      if (SCATTER) {
+        const uint64_t small =
+            a.wide ? 0ull
+                   : (((uint64_t)(src[u] >> GROUP_SHIFT) << (F - 3)) |
+                      (src[u] & ((1u << GROUP_SHIFT) - 1u)));
+        rw[u][0] = (small << (64 - F)) | (rw[u][0] & (~0ull >> F));
+#pragma unroll
+        for (int q = 0; q < RW; q++) out[(size_t)pos * RW + q] = rw[u][q];
+        if (a.wide) a.rsrc_wide[pos] = src[u];
+      }
     }
   }
   if (!SCATTER) {
