@@ -221,8 +221,17 @@ int pauli_rk4_step(const pauli_op *H, const pauli_op *O, double dt, const pauli_
  *   b_n  = ||O'_n|| = sqrt(sum |c|^2)         (norm of the untruncated O'_n)
  *   O_n  = trunc(O'_n / b_n)                 (IEEE division per component)
  * *b_out (host) receives b_n.  On PAULI_BREAKDOWN O_next->size = 0.
- * flags: must be 0.  For PAULI_C64K operators the commutator runs in FP32 with
- * compensated sums and everything after it in FP64 (O_n rounded to FP32). */
+ * For PAULI_C64K operators the commutator runs in FP32 with compensated sums
+ * and everything after it in FP64 (O_n rounded to FP32).
+ * flags: 0, or PAULI_REORTH_LOCAL: local re-orthogonalisation (not in the
+ * paper, whose recursion is the three-term one; it is a no-op in exact
+ * arithmetic without truncation): before b_n is taken, O'_n is replaced by
+ *   O'_n - a_1 O_{n-1} - a_2 O_{n-2},   a_k = <O_k, O'_n> / <O_k, O_k>,
+ * both coefficients computed from the same O'_n in FP64 (inner products and
+ * norms summed in double-double and rounded once, then divided), the
+ * combination summed as for pauli_add.  O_cur and O_prev must then be
+ * canonical (PAULI_EINVAL otherwise); the workspace also holds O'_n in FP64. */
+enum { PAULI_REORTH_LOCAL = 1 };
 int pauli_lanczos_step(const pauli_op *H, const pauli_op *O_prev, const pauli_op *O_cur,
                        double b_prev, const pauli_trunc *t, uint32_t flags,
                        pauli_op *O_next, double *b_out, pauli_ws *ws, void *stream);
@@ -235,6 +244,52 @@ int pauli_norm2(const pauli_op *A, double *out, pauli_ws *ws, void *stream);
  * strings of conj(a) b.  B must be canonical. */
 int pauli_inner(const pauli_op *A, const pauli_op *B, double out[2], pauli_ws *ws,
                 void *stream);
+
+/* S = <O0, O>/<O0, O0> = sum over common strings of conj(c0) c / sum |c0|^2
+ * (out[0] + i out[1], host): the autocorrelation of the Heisenberg section,
+ * which for unit O0 equals Tr(O(t) O0)/2^N.  O0 must be canonical and
+ * nonzero (PAULI_EINVAL otherwise).  Both sums in double-double, rounded
+ * once, then divided.  Synchronous at return. */
+int pauli_correlator(const pauli_op *O0, const pauli_op *O, double out[2], pauli_ws *ws,
+                     void *stream);
+
+/* Workspace and output sizing from the operand sizes alone (host only, no
+ * device work; only n_qubits, dtype and size of the operands are read, so
+ * their device pointers may be NULL).  The operands are those of the call:
+ *   PAULI_Q_COMMUTATOR, PAULI_Q_MULTIPLY, PAULI_Q_COMMUTATOR_TS1D: A = H (H0), B = O
+ *   PAULI_Q_ADD: A and B
+ *   PAULI_Q_TRUNCATE, PAULI_Q_CANONICALIZE, PAULI_Q_CANONICALIZE_TS1D: B = in
+ *   PAULI_Q_LANCZOS, PAULI_Q_LANCZOS_REORTH (flag PAULI_REORTH_LOCAL),
+ *   PAULI_Q_LANCZOS_TS1D: A = H (H0), B = O_cur, C = O_prev (nullable)
+ *   PAULI_Q_RK4: A = H, B = O
+ *   PAULI_Q_REDUCTION (norm2, inner, trace, coefficients, correlator,
+ *   norm2_ts1d): A, B (nullable)
+ * t is the truncation the call will receive (nullable).
+ * *ws_bytes: a workspace that holds the call when it emits at most the
+ * records its sizes bound (|H| |O| pairs, N |H0| |O| for translation-
+ * symmetric calls, plus the operator terms) and no hash bin holds more than
+ * 1.5 times the mean plus the records one string can collect; a call beyond
+ * that returns PAULI_EWORKSPACE with its exact need.  The bound is loose
+ * where few pairs anticommute (the engine sizes the real call after
+ * counting its records).
+ * *out_capacity_upper: an output capacity that always suffices.
+ * PAULI_EINVAL for an unknown op or missing operand. */
+enum {
+  PAULI_Q_COMMUTATOR = 0,
+  PAULI_Q_MULTIPLY = 1,
+  PAULI_Q_ADD = 2,
+  PAULI_Q_TRUNCATE = 3,
+  PAULI_Q_CANONICALIZE = 4,
+  PAULI_Q_LANCZOS = 5,
+  PAULI_Q_LANCZOS_REORTH = 6,
+  PAULI_Q_RK4 = 7,
+  PAULI_Q_COMMUTATOR_TS1D = 8,
+  PAULI_Q_CANONICALIZE_TS1D = 9,
+  PAULI_Q_LANCZOS_TS1D = 10,
+  PAULI_Q_REDUCTION = 11
+};
+int pauli_workspace_query(int op, const pauli_op *A, const pauli_op *B, const pauli_op *C,
+                          const pauli_trunc *t, size_t *ws_bytes, int64_t *out_capacity_upper);
 
 /* ------------------------------------------------------------------------ */
 /* b_n continuation network: a window of 16 Lanczos coefficients in, the next */

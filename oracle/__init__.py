@@ -83,6 +83,7 @@ def lib():
         L.or_exact_sum.restype = ctypes.c_double
         L.or_lanczos_step.argtypes = [P(_OrOp), P(_OrOp), P(_OrOp), ctypes.c_double,
                                       P(_OrTrunc), ctypes.c_int, P(_OrOp), P(ctypes.c_double)]
+        L.or_lanczos_step_reorth.argtypes = L.or_lanczos_step.argtypes
         L.or_lanczos_step_ts.argtypes = [P(_OrOp), P(_OrOp), P(_OrOp), ctypes.c_double,
                                          P(_OrTrunc), P(_OrOp), P(ctypes.c_double)]
         L.or_rk4_step.argtypes = [P(_OrOp), P(_OrOp), ctypes.c_double, P(_OrTrunc), P(_OrOp)]
@@ -369,26 +370,28 @@ def exact_sum(values) -> float:
 
 
 def lanczos_step(H: HostOp, O_prev: HostOp | None, O_cur: HostOp, b_prev: float,
-                 t: Trunc = NO_TRUNC, prec: int = F64):
-    """Returns (O_next, b_n, breakdown)."""
+                 t: Trunc = NO_TRUNC, prec: int = F64, reorth: bool = False):
+    """Returns (O_next, b_n, breakdown).  reorth: local re-orthogonalisation
+    of O'_n against O_cur and O_prev before b_n is taken."""
     h, c = _Marshalled(H), _Marshalled(O_cur)
     p = _Marshalled(O_prev) if O_prev is not None else None
     pp = ctypes.byref(p.s) if p is not None else ctypes.POINTER(_OrOp)()
     km, ts = t.marshal()
     out, b = _OrOp(), ctypes.c_double()
-    rc = _check(lib().or_lanczos_step(ctypes.byref(h.s), pp, ctypes.byref(c.s), float(b_prev),
-                                      ctypes.byref(ts), prec, ctypes.byref(out), ctypes.byref(b)))
+    fn = lib().or_lanczos_step_reorth if reorth else lib().or_lanczos_step
+    rc = _check(fn(ctypes.byref(h.s), pp, ctypes.byref(c.s), float(b_prev),
+                   ctypes.byref(ts), prec, ctypes.byref(out), ctypes.byref(b)))
     del km
     return _take(out, O_cur.n_qubits), b.value, rc == OR_BREAKDOWN
 
 
 def lanczos(H: HostOp, O0: HostOp, steps: int, t: Trunc = NO_TRUNC, prec: int = F64,
-            keep_basis: bool = False):
+            keep_basis: bool = False, reorth: bool = False):
     """b_1..b_steps (stops early at breakdown) and, optionally, the basis."""
     bs, basis = [], [O0]
     prev, cur, b_prev = None, O0, 0.0
     for _ in range(steps):
-        nxt, b, broke = lanczos_step(H, prev, cur, b_prev, t, prec)
+        nxt, b, broke = lanczos_step(H, prev, cur, b_prev, t, prec, reorth)
         bs.append(b)
         if broke:
             break

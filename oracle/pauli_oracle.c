@@ -217,9 +217,11 @@ int or_canonicalize(const or_op *in, or_op *out) {
 /* Commutator [H, O] (Alg. 1 with the commutator phase) and plain product.   */
 /* ------------------------------------------------------------------------ */
 
-/* FP32 mode with compensated sums: each contribution is fl32(h32 * c) times
- * the exact phase factor; each key's contributions are summed in ascending H
- * index with Kahan's compensated summation, per component; the key's value is
+/* FP32 mode with compensated sums: each contribution is the complex product
+ * of the FP64 H coefficient and the stored FP32 coefficient, formed in FP64
+ * and rounded once to FP32 per component, times the exact phase factor; each
+ * key's contributions are summed in ascending H index with Kahan's
+ * compensated summation, per component; the key's value is
  * (double)s - (double)comp. */
 typedef struct {
   uint64_t x[2], z[2];
@@ -282,7 +284,6 @@ int or_commutator(const or_op *H, const or_op *O, int prec, or_op *out) {
   for (int64_t a = 0; a < H->n; a++) {
     uint64_t ax[2], az[2];
     get_key(H, a, ax, az);
-    float hr32 = (float)H->re[a], hi32 = (float)H->im[a];
     for (int64_t j = 0; j < O->n; j++) {
       uint64_t bx[2], bz[2], cx[2], cz[2], dx[2], dz[2];
       get_key(O, j, bx, bz);
@@ -294,8 +295,9 @@ int or_commutator(const or_op *H, const or_op *O, int prec, or_op *out) {
       ipow(kab, &pr, &pi);
       ipow(kba, &qr, &qi);
       float dr = (float)(pr - qr), di = (float)(pi - qi);
-      float tr, ti;
-      cmul32(hr32, hi32, (float)O->re[j], (float)O->im[j], &tr, &ti);
+      double er, ei;
+      cmul(H->re[a], H->im[a], (double)(float)O->re[j], (double)(float)O->im[j], &er, &ei);
+      const float tr = (float)er, ti = (float)ei;
       if (n == cap) {
         cap = cap ? 2 * cap : 1024;
         rec32_t *p = (rec32_t *)realloc(rs, (size_t)cap * sizeof(rec32_t));
@@ -810,8 +812,36 @@ static void round_to_f32(or_op *o) {
 /* ts != 0: translation-symmetric operators of the periodic chain (Alg. 2):  */
 /* H holds H0, the operators hold orbit representatives, the commutator is   */
 /* or_commutator_ts and the norm the stabilizer-weighted or_norm2_ts (FP64). */
+/* reorth != 0: local re-orthogonalisation (not in the paper; its recursion */
+/* is the three-term one): O'_n is replaced by                               */
+/*   O'_n - a_1 O_{n-1} - a_2 O_{n-2},  a_k = <O_k, O'_n> / <O_k, O_k>,      */
+/* both a_k from the same O'_n (Gram-Schmidt against the two previous        */
+/* vectors), inner products and norms exact sums rounded once, the           */
+/* combination by two sums (O'_n + (-a_1) O_{n-1}) + (-a_2) O_{n-2}.         */
+static int project_out(or_op *A, const or_op *const V[2]) {
+  double ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
+  for (int k = 0; k < 2; k++) {
+    if (!V[k] || V[k]->n == 0) continue;
+    double n2 = or_norm2(V[k]), re, im;
+    or_inner(V[k], A, &re, &im);
+    if (n2 > 0.0) {
+      ar[k] = re / n2;
+      ai[k] = im / n2;
+    }
+  }
+  for (int k = 0; k < 2; k++) {
+    if (!V[k] || V[k]->n == 0) continue;
+    or_op B = {0};
+    int rc = or_add(A, 1.0, 0.0, V[k], -ar[k], -ai[k], &B);
+    if (rc) return rc;
+    or_free(A);
+    *A = B;
+  }
+  return OR_OK;
+}
+
 static int lanczos_step(int ts, const or_op *H, const or_op *O_prev, const or_op *O_cur,
-                        double b_prev, const or_trunc *t, int prec, or_op *O_next,
+                        double b_prev, const or_trunc *t, int prec, int reorth, or_op *O_next,
                         double *b_out) {
   or_op C = {0}, A = {0}, D = {0};
   int rc = ts ? or_commutator_ts(H, O_cur, &C) : or_commutator(H, O_cur, prec, &C);
@@ -822,6 +852,14 @@ static int lanczos_step(int ts, const or_op *H, const or_op *O_prev, const or_op
     if (rc) return rc;
   } else {
     A = C;
+  }
+  if (reorth) {
+    const or_op *V[2] = {O_cur, O_prev};
+    rc = project_out(&A, V);
+    if (rc) {
+      or_free(&A);
+      return rc;
+    }
   }
   double b = sqrt(ts ? or_norm2_ts(&A) : or_norm2(&A));
   *b_out = b;
@@ -842,12 +880,18 @@ static int lanczos_step(int ts, const or_op *H, const or_op *O_prev, const or_op
 
 int or_lanczos_step(const or_op *H, const or_op *O_prev, const or_op *O_cur, double b_prev,
                     const or_trunc *t, int prec, or_op *O_next, double *b_out) {
-  return lanczos_step(0, H, O_prev, O_cur, b_prev, t, prec, O_next, b_out);
+  return lanczos_step(0, H, O_prev, O_cur, b_prev, t, prec, 0, O_next, b_out);
+}
+
+int or_lanczos_step_reorth(const or_op *H, const or_op *O_prev, const or_op *O_cur,
+                           double b_prev, const or_trunc *t, int prec, or_op *O_next,
+                           double *b_out) {
+  return lanczos_step(0, H, O_prev, O_cur, b_prev, t, prec, 1, O_next, b_out);
 }
 
 int or_lanczos_step_ts(const or_op *H0, const or_op *O_prev, const or_op *O_cur, double b_prev,
                        const or_trunc *t, or_op *O_next, double *b_out) {
-  return lanczos_step(1, H0, O_prev, O_cur, b_prev, t, OR_F64, O_next, b_out);
+  return lanczos_step(1, H0, O_prev, O_cur, b_prev, t, OR_F64, 0, O_next, b_out);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -67,6 +67,10 @@ void or_inner(const or_op *A, const or_op *B, double *re, double *im);
 double or_exact_sum(const double *v, int64_t n);
 int or_lanczos_step(const or_op *H, const or_op *O_prev, const or_op *O_cur, double b_prev,
                     const or_trunc *t, int prec, or_op *O_next, double *b_out);
+/* the same step with local re-orthogonalisation against O_cur and O_prev */
+int or_lanczos_step_reorth(const or_op *H, const or_op *O_prev, const or_op *O_cur,
+                           double b_prev, const or_trunc *t, int prec, or_op *O_next,
+                           double *b_out);
 int or_lanczos_step_ts(const or_op *H0, const or_op *O_prev, const or_op *O_cur, double b_prev,
                        const or_trunc *t, or_op *O_next, double *b_out);
 int or_rk4_step(const or_op *H, const or_op *O, double dt, const or_trunc *t, or_op *out);

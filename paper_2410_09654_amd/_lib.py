@@ -10,12 +10,17 @@ LIB_PATH = os.path.join(HERE, "libpauli.so")
 PAULI_OK, PAULI_EINVAL, PAULI_ECAPACITY, PAULI_EWORKSPACE, PAULI_BREAKDOWN, PAULI_EHIP, \
     PAULI_EINTERNAL = range(7)
 PAULI_C128, PAULI_C64K = 0, 1
+PAULI_REORTH_LOCAL = 1
+(PAULI_Q_COMMUTATOR, PAULI_Q_MULTIPLY, PAULI_Q_ADD, PAULI_Q_TRUNCATE, PAULI_Q_CANONICALIZE,
+ PAULI_Q_LANCZOS, PAULI_Q_LANCZOS_REORTH, PAULI_Q_RK4, PAULI_Q_COMMUTATOR_TS1D,
+ PAULI_Q_CANONICALIZE_TS1D, PAULI_Q_LANCZOS_TS1D, PAULI_Q_REDUCTION) = range(12)
 
 EXPORTS = ["pauli_commutator", "pauli_multiply", "pauli_trace", "pauli_add", "pauli_truncate",
            "pauli_canonicalize", "pauli_add_noise", "pauli_coefficients",
            "pauli_commutator_ts1d", "pauli_canonicalize_ts1d", "pauli_norm2_ts1d",
            "pauli_lanczos_step_ts1d",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
+           "pauli_correlator", "pauli_workspace_query",
            "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_only", "pauli_profile_read",
            "pauli_last_stats", "pauli_order_keys", "pauli_strings_from_order_keys",
            "pauli_mlp_num_params", "pauli_mlp_sync", "pauli_mlp_forward",
@@ -81,6 +86,9 @@ def load():
     L.pauli_lanczos_step.argtypes = [op, op, op, d, tr, ctypes.c_uint32, op, P(d), ws, vp]
     L.pauli_norm2.argtypes = [op, P(d), ws, vp]
     L.pauli_inner.argtypes = [op, op, P(d), ws, vp]
+    L.pauli_correlator.argtypes = [op, op, P(d), ws, vp]
+    L.pauli_workspace_query.argtypes = [ctypes.c_int, op, op, op, tr, P(ctypes.c_size_t),
+                                        P(ctypes.c_int64)]
     L.pauli_strerror.argtypes = [ctypes.c_int]
     L.pauli_strerror.restype = ctypes.c_char_p
     L.pauli_last_error.argtypes = []

@@ -10,14 +10,15 @@ from .ops import PauliOp, Trunc, Workspace
 
 
 def lanczos(H: PauliOp, O0: PauliOp, steps: int, trunc: Trunc | None = None,
-            ws: Workspace | None = None, keep_basis: bool = False):
+            ws: Workspace | None = None, keep_basis: bool = False, reorth: bool = False):
     """Liouvillian Lanczos recursion (Krylov section): b_1..b_steps, stopping
-    at breakdown.  O0 must have unit norm."""
+    at breakdown.  O0 must have unit norm.  reorth: local
+    re-orthogonalisation at every step (PAULI_REORTH_LOCAL)."""
     ws = ws or ops.default_workspace(O0.device)
     bs, basis = [], [O0]
     prev, cur, b_prev = None, O0, 0.0
     for _ in range(steps):
-        nxt, b, broke = ops.lanczos_step(H, prev, cur, b_prev, trunc, ws=ws)
+        nxt, b, broke = ops.lanczos_step(H, prev, cur, b_prev, trunc, ws=ws, reorth=reorth)
         bs.append(b)
         if broke:
             break
@@ -35,12 +36,11 @@ def evolve(H: PauliOp, O0: PauliOp, dt: float, steps: int, trunc: Trunc | None =
     S(t) = <O0, O(t)> / <O0, O0> (the correlator of the Heisenberg section).
     """
     ws = ws or ops.default_workspace(O0.device)
-    n0 = ops.norm2(O0, ws=ws)
-    S = [ops.inner(O0, O0, ws=ws) / n0]
+    S = [ops.correlator(O0, O0, ws=ws)]
     cur = O0
     for _ in range(steps):
         cur = ops.rk4_step(H, cur, dt, trunc, ws=ws)
-        S.append(ops.inner(cur, O0, ws=ws).conjugate() / n0)
+        S.append(ops.correlator(O0, cur, ws=ws))
         if observe is not None:
             observe(cur)
     return cur, S
@@ -73,12 +73,11 @@ def evolve_noisy(H: PauliOp, O0: PauliOp, dt: float, steps: int, max_strings: in
     given, is called after every step."""
     ws = ws or ops.default_workspace(O0.device)
     tr = Trunc(max_len=max_len, max_strings=max_strings, keep=O0)
-    n0 = ops.norm2(O0, ws=ws)
     S, P = [], []
     cur = O0
 
     def record(op):
-        S.append(ops.inner(O0, op, ws=ws) / n0)
+        S.append(ops.correlator(O0, op, ws=ws))
         if probes is not None:
             P.append(ops.coefficients(op, probes, ws=ws))
 

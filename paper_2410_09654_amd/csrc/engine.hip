@@ -137,20 +137,24 @@ struct Arena {
   size_t need = 0;    // largest bottom + top requested so far
   bool short_ = false;
 
+  bool dry = false;    // size only (pauli_workspace_query): no memory behind it
+
   void* take(size_t bytes) {
     bottom = align256(bottom);
-    void* p = base + bottom;
+    const size_t at = bottom;
     bottom += align256(bytes);
     if (bottom + top > need) need = bottom + top;
+    if (dry) return nullptr;
     if (bottom + top > cap) {
       short_ = true;
       return nullptr;
     }
-    return p;
+    return base + at;
   }
   void* take_top(size_t bytes) {
     top += align256(bytes);
     if (bottom + top > need) need = bottom + top;
+    if (dry) return nullptr;
     if (bottom + top > cap) {
       short_ = true;
       return nullptr;
@@ -231,6 +235,122 @@ int alpha_kind(double2 a) {
   return A_GENERAL;
 }
 
+// ---------------------------------------------------------------------------
+// Planning and scratch layout of one engine call, shared by the engine and
+// pauli_workspace_query (which lays the same buffers out on an empty arena).
+// ---------------------------------------------------------------------------
+// at most 1024 commutator rows (one tile of EMIT_THREADS O strings each up
+// to |O| = 2^20: more, shorter rows scatter faster, since twice as many
+// workgroups fit a CU as there are CUs) and 128 rows of operator terms
+constexpr int64_t COMM_ROWS_MAX = 1024, TERM_ROWS_MAX = (1 << 17) / EMIT_THREADS;
+static_assert(COMM_ROWS_MAX + TERM_ROWS_MAX <= SC_ROWS_MAX, "k_scan_cols covers every count row");
+constexpr int MAX_PASS_BITS = 12;
+constexpr int PART_NBL = 12;  // at most 2^12 partitions (MAX_PASS_BITS)
+// blocks binning one partition: 1024 (one per CU, LDS-bound, so four
+// rounds) write shorter per-(block, bin) runs and beat 256 and 512
+constexpr int SPLIT_ROWS = 1024;
+static_assert(SPLIT_ROWS <= SC_ROWS_MAX, "k_scan_cols covers every split row");
+
+inline void plan_rows(bool comm, int64_t nO, int64_t nterm_rec, int* comm_rows, int* term_rows) {
+  *comm_rows = comm ? (int)std::min<int64_t>((nO + EMIT_THREADS - 1) / EMIT_THREADS, COMM_ROWS_MAX) : 0;
+  *term_rows = nterm_rec > 0
+                   ? (int)std::min<int64_t>((nterm_rec + EMIT_THREADS - 1) / EMIT_THREADS, TERM_ROWS_MAX)
+                   : 0;
+}
+
+// Hash passes from the largest bin of the NBINS_LOG-bin count: one pass when
+// every bin fits a merge bucket; otherwise NBINS_LOG_MP bins per pass, whose
+// largest holds about half as many, and one more pass bit per halving.
+template <int W>
+int plan_pass_bits(unsigned long long mx, int* nbl) {
+  int pass_bits = 0;
+  *nbl = NBINS_LOG;
+  if (mx > (unsigned long long)merge_cap<W>()) {
+    *nbl = NBINS_LOG_MP;
+    mx = (mx + 1) / 2;
+    while (mx > (unsigned long long)(merge_cap<W>() * 3 / 4) && pass_bits < 10) {
+      pass_bits++;
+      mx = (mx + 1) / 2;
+    }
+  }
+  return pass_bits;
+}
+
+// scratch taken before the count pass
+template <int W>
+struct Bufs1 {
+  Ctl* dctl = nullptr;
+  uint64_t* Hk = nullptr;
+  uint32_t* Hidx = nullptr;
+  uint32_t* hstart = nullptr;
+  int* hspan = nullptr;
+  Key<W>* keep_mk = nullptr;
+  uint32_t *counts = nullptr, *bin_total = nullptr, *bin_base = nullptr, *hist0 = nullptr;
+  uint32_t* histL[2] = {nullptr, nullptr};
+  uint32_t *hsum = nullptr, *h0sum = nullptr;
+  unsigned long long* psum = nullptr;
+};
+template <int W>
+void take_bufs1(Arena& ar, bool comm, int64_t nH, int64_t n_keep, int rows, Bufs1<W>& b) {
+  const size_t KB = sizeof(Key<W>);
+  b.dctl = (Ctl*)ar.take(sizeof(Ctl));
+  b.Hk = comm ? (uint64_t*)ar.take((size_t)nH * KB) : nullptr;
+  b.Hidx = comm ? (uint32_t*)ar.take((size_t)nH * 4) : nullptr;
+  b.hstart = comm ? (uint32_t*)ar.take((size_t)(64 * W + 2) * 4) : nullptr;
+  b.hspan = comm ? (int*)ar.take(4) : nullptr;
+  b.keep_mk = n_keep ? (Key<W>*)ar.take((size_t)n_keep * KB) : nullptr;
+  // rows of the emission, or of the partition binning (256 blocks)
+  b.counts = (uint32_t*)ar.take((size_t)std::max(rows, 256) * NBINS_MP * 4);
+  b.bin_total = (uint32_t*)ar.take(NBINS_MP * 4);
+  b.bin_base = (uint32_t*)ar.take((NBINS_MP + 1) * 4);
+  b.hist0 = (uint32_t*)ar.take((size_t)HREP * SEL0_BINS * 4);
+  b.histL[0] = (uint32_t*)ar.take((size_t)HREP * SEL_BINS * 4);
+  b.histL[1] = (uint32_t*)ar.take((size_t)HREP * SEL_BINS * 4);
+  b.hsum = (uint32_t*)ar.take(SEL_BINS * 4);
+  b.h0sum = (uint32_t*)ar.take(SEL0_BINS * 4);
+  b.psum = (unsigned long long*)ar.take(PLAN_PARTS * 4 * 8);
+}
+
+// scratch taken after the count pass: records (and their partitions),
+// merged strings, per-bucket tables, select candidate lists
+struct Bufs2 {
+  void* recs = nullptr;
+  uint32_t* rsrc_wide = nullptr;
+  void* precs = nullptr;
+  uint32_t *psrc = nullptr, *pbase = nullptr, *scounts = nullptr;
+  void* uk = nullptr;
+  double2* uc = nullptr;
+  uint32_t *b_ubase = nullptr, *b_slots = nullptr, *b_surv = nullptr, *b_keep = nullptr;
+  uint32_t *b_unique = nullptr, *b_abv = nullptr, *b_bcnt = nullptr, *b_obase = nullptr;
+  double2* norm_part = nullptr;
+  uint32_t* cand[3] = {nullptr, nullptr, nullptr};
+  uint32_t* ccnt[3] = {nullptr, nullptr, nullptr};
+};
+template <int W, bool F32>
+void take_bufs2(Arena& ar, size_t ptot, bool wide, bool partitioned, uint32_t max_buckets,
+                bool want_select, Bufs2& b) {
+  const size_t KB = sizeof(Key<W>), RB = sizeof(Rec<W, F32>);
+  b.recs = ar.take(ptot * RB);
+  b.rsrc_wide = wide ? (uint32_t*)ar.take(ptot * 4) : nullptr;
+  // several passes: every record is emitted once into 2^pass_bits partitions
+  // (full order keys, source ids aside); each pass bins one partition
+  b.precs = partitioned ? ar.take(ptot * RB) : nullptr;
+  b.psrc = partitioned ? (uint32_t*)ar.take(ptot * 4) : nullptr;
+  b.pbase = partitioned ? (uint32_t*)ar.take(((1u << PART_NBL) + 1) * 4) : nullptr;
+  b.scounts = partitioned ? (uint32_t*)ar.take((size_t)SPLIT_ROWS * NBINS_MP * 4) : nullptr;
+  b.uk = ar.take(ptot * KB);
+  b.uc = (double2*)ar.take(ptot * sizeof(double2));
+  uint32_t** tabs[8] = {&b.b_ubase, &b.b_slots, &b.b_surv,  &b.b_keep,
+                        &b.b_unique, &b.b_abv,  &b.b_bcnt, &b.b_obase};
+  for (auto t : tabs) *t = (uint32_t*)ar.take((size_t)max_buckets * 4);
+  b.norm_part = (double2*)ar.take((size_t)max_buckets * sizeof(double2));
+  if (want_select)
+    for (int k = 0; k < 3; k++) {
+      b.cand[k] = (uint32_t*)ar.take(ptot * 4);
+      b.ccnt[k] = (uint32_t*)ar.take((size_t)max_buckets * 4);
+    }
+}
+
 struct Engine {
   Arena* ar;
   hipStream_t stream;
@@ -305,32 +425,26 @@ int Engine::run(Call& c) {
     g_last_error = "H has more strings than one merge bucket holds";
     return PAULI_EINVAL;
   }
-  // at most 1024 commutator rows (one tile of EMIT_THREADS O strings each up
-  // to |O| = 2^20: more, shorter rows scatter faster, since twice as many
-  // workgroups fit a CU as there are CUs) and 128 rows of operator terms
-  constexpr int64_t COMM_ROWS_MAX = 1024, TERM_ROWS_MAX = (1 << 17) / EMIT_THREADS;
-  static_assert(COMM_ROWS_MAX + TERM_ROWS_MAX <= SC_ROWS_MAX, "k_scan_cols covers every count row");
-  int comm_rows = comm ? (int)std::min<int64_t>((c.O.n + EMIT_THREADS - 1) / EMIT_THREADS, COMM_ROWS_MAX) : 0;
-  int term_rows = nterm_rec > 0 ? (int)std::min<int64_t>((nterm_rec + EMIT_THREADS - 1) / EMIT_THREADS, TERM_ROWS_MAX) : 0;
+  int comm_rows = 0, term_rows = 0;
+  plan_rows(comm, c.O.n, nterm_rec, &comm_rows, &term_rows);
   const int rows = comm_rows + term_rows;
 
-  dctl = (Ctl*)ar->take(sizeof(Ctl));
-  uint64_t* Hk = comm ? (uint64_t*)ar->take((size_t)c.H.n * KB) : nullptr;
-  uint32_t* Hidx = comm ? (uint32_t*)ar->take((size_t)c.H.n * 4) : nullptr;
-  uint32_t* hstart = comm ? (uint32_t*)ar->take((size_t)(64 * W + 2) * 4) : nullptr;
-  int* hspan = comm ? (int*)ar->take(4) : nullptr;
-  Key<W>* keep_mk = n_keep ? (Key<W>*)ar->take((size_t)n_keep * KB) : nullptr;
-  // rows of the emission, or of the partition binning (256 blocks)
-  uint32_t* counts = (uint32_t*)ar->take((size_t)std::max(rows, 256) * NBINS_MP * 4);
-  uint32_t* bin_total = (uint32_t*)ar->take(NBINS_MP * 4);
-  uint32_t* bin_base = (uint32_t*)ar->take((NBINS_MP + 1) * 4);
-  uint32_t* hist0 = (uint32_t*)ar->take((size_t)HREP * SEL0_BINS * 4);
-  uint32_t* histL[2];
-  histL[0] = (uint32_t*)ar->take((size_t)HREP * SEL_BINS * 4);
-  histL[1] = (uint32_t*)ar->take((size_t)HREP * SEL_BINS * 4);
-  uint32_t* hsum = (uint32_t*)ar->take(SEL_BINS * 4);
-  uint32_t* h0sum = (uint32_t*)ar->take(SEL0_BINS * 4);
-  unsigned long long* psum = (unsigned long long*)ar->take(PLAN_PARTS * 4 * 8);
+  Bufs1<W> b1;
+  take_bufs1<W>(*ar, comm, c.H.n, n_keep, rows, b1);
+  dctl = b1.dctl;
+  uint64_t* Hk = b1.Hk;
+  uint32_t* Hidx = b1.Hidx;
+  uint32_t* hstart = b1.hstart;
+  int* hspan = b1.hspan;
+  Key<W>* keep_mk = b1.keep_mk;
+  uint32_t* counts = b1.counts;
+  uint32_t* bin_total = b1.bin_total;
+  uint32_t* bin_base = b1.bin_base;
+  uint32_t* hist0 = b1.hist0;
+  uint32_t* histL[2] = {b1.histL[0], b1.histL[1]};
+  uint32_t* hsum = b1.hsum;
+  uint32_t* h0sum = b1.h0sum;
+  unsigned long long* psum = b1.psum;
   if (ar->short_) return PAULI_EWORKSPACE;
   TRY(host_ctl(&hctl));
   // the control block starts at zero (cleared by k_prep_h when there is one)
@@ -433,21 +547,8 @@ int Engine::run(Call& c) {
   // largest bin does not always halve with each extra pass bit (all records
   // of one string share a bin), so a pass that still overflows restarts the
   // loop with one more pass bit
-  int pass_bits = 0;
-  {
-    // the count pass measured every bin exactly: one pass when they all fit;
-    // otherwise twice the bins, whose largest holds about half as many
-    unsigned long long mx = hctl->maxg[0];
-    if (mx > (unsigned long long)merge_cap<W>()) {
-      nbl = NBINS_LOG_MP;
-      mx = (mx + 1) / 2;
-      while (mx > (unsigned long long)(merge_cap<W>() * 3 / 4) && pass_bits < 10) {
-        pass_bits++;
-        mx = (mx + 1) / 2;
-      }
-    }
-  }
-  constexpr int MAX_PASS_BITS = 12;
+  // the count pass measured every bin exactly
+  int pass_bits = plan_pass_bits<W>(hctl->maxg[0], &nbl);
   const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
   const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
   const uint32_t max_buckets = (uint32_t)(1u << nbl) << table_bits;
@@ -457,41 +558,30 @@ int Engine::run(Call& c) {
   // (translation-symmetric calls carry (H entry, rotation) as the source id)
   bool wide = comm && (c.H.n > 2047 || c.ts);
   for (int t = 0; t < c.n_terms; t++) wide = wide || c.tlist[t];
-  void* recs = ar->take(ptot * RB);
-  uint32_t* rsrc_wide = wide ? (uint32_t*)ar->take(ptot * 4) : nullptr;
-  // several passes: every record is emitted once into 2^pass_bits partitions
-  // (full order keys, source ids aside); each pass bins one partition
-  constexpr int PART_NBL = 12;  // at most 2^12 partitions (MAX_PASS_BITS)
-  // blocks binning one partition: 1024 (one per CU, LDS-bound, so four
-  // rounds) write shorter per-(block, bin) runs and beat 256 and 512
-  constexpr int SPLIT_ROWS = 1024;
-  static_assert(SPLIT_ROWS <= SC_ROWS_MAX, "k_scan_cols covers every split row");
   const bool partitioned = nbl == NBINS_LOG_MP;
-  void* precs = partitioned ? ar->take(ptot * RB) : nullptr;
-  uint32_t* psrc = partitioned ? (uint32_t*)ar->take(ptot * 4) : nullptr;
-  uint32_t* pbase = partitioned ? (uint32_t*)ar->take(((1u << PART_NBL) + 1) * 4) : nullptr;
-  uint32_t* scounts =
-      partitioned ? (uint32_t*)ar->take((size_t)SPLIT_ROWS * NBINS_MP * 4) : nullptr;
-  void* uk = ar->take(ptot * KB);
-  double2* uc = (double2*)ar->take(ptot * sizeof(double2));
-  uint32_t* b_ubase = (uint32_t*)ar->take((size_t)max_buckets * 4);
-  uint32_t* b_slots = (uint32_t*)ar->take((size_t)max_buckets * 4);
-  uint32_t* b_surv = (uint32_t*)ar->take((size_t)max_buckets * 4);
-  uint32_t* b_keep = (uint32_t*)ar->take((size_t)max_buckets * 4);
-  uint32_t* b_unique = (uint32_t*)ar->take((size_t)max_buckets * 4);
-  uint32_t* b_abv = (uint32_t*)ar->take((size_t)max_buckets * 4);
-  uint32_t* b_bcnt = (uint32_t*)ar->take((size_t)max_buckets * 4);
-  uint32_t* b_obase = (uint32_t*)ar->take((size_t)max_buckets * 4);
-  double2* norm_part = (double2*)ar->take((size_t)max_buckets * sizeof(double2));
   const bool want_select = tr && tr->max_strings > 0;
-  uint32_t* cand[3] = {nullptr, nullptr, nullptr};
-  uint32_t* ccnt[3] = {nullptr, nullptr, nullptr};
-  if (want_select)
-    for (int k = 0; k < 3; k++) {
-      cand[k] = (uint32_t*)ar->take(ptot * 4);
-      ccnt[k] = (uint32_t*)ar->take((size_t)max_buckets * 4);
-    }
+  Bufs2 b2;
+  take_bufs2<W, F32>(*ar, ptot, wide, partitioned, max_buckets, want_select, b2);
   if (ar->short_) return PAULI_EWORKSPACE;
+  void* recs = b2.recs;
+  uint32_t* rsrc_wide = b2.rsrc_wide;
+  void* precs = b2.precs;
+  uint32_t* psrc = b2.psrc;
+  uint32_t* pbase = b2.pbase;
+  uint32_t* scounts = b2.scounts;
+  void* uk = b2.uk;
+  double2* uc = b2.uc;
+  uint32_t* b_ubase = b2.b_ubase;
+  uint32_t* b_slots = b2.b_slots;
+  uint32_t* b_surv = b2.b_surv;
+  uint32_t* b_keep = b2.b_keep;
+  uint32_t* b_unique = b2.b_unique;
+  uint32_t* b_abv = b2.b_abv;
+  uint32_t* b_bcnt = b2.b_bcnt;
+  uint32_t* b_obase = b2.b_obase;
+  double2* norm_part = b2.norm_part;
+  uint32_t* const* cand = b2.cand;
+  uint32_t* const* ccnt = b2.ccnt;
 
   MergeArgs ma;
   memset(&ma, 0, sizeof(ma));
@@ -589,8 +679,17 @@ int Engine::run(Call& c) {
                nzero);
         TRY(read_ctl());
       } else if (nbl != NBINS_LOG) {
-        // one pass at NBINS_LOG_MP bins: count again at that bin count
+        // one pass at NBINS_LOG_MP bins: count again at that bin count; this
+        // overwrites the first count pass's NBINS_LOG-bin prefixes and totals
         TRY(count_pass(pass_bits, (uint32_t)p));
+        first_counts = false;
+      }
+      if (pass_bits > 0 && p == 0 && hctl->part_total != pe_all) {
+        char msg[160];
+        snprintf(msg, sizeof(msg), "partitions hold %llu records, the count pass %llu",
+                 (unsigned long long)hctl->part_total, pe_all);
+        g_last_error = msg;
+        return PAULI_EINTERNAL;
       }
       const unsigned long long pe = hctl->pe_total;
       if (hctl->maxg[0] > (unsigned int)merge_cap<W>()) {
@@ -932,6 +1031,214 @@ Arena make_arena(pauli_ws* ws) {
 
 OpV as_input(const OpV& v) { return v; }
 
+// ---------------------------------------------------------------------------
+// Workspace sizing without device work: the engine's own scratch layout on a
+// dry arena, with the records at their bound from the sizes and bins assumed
+// to fill evenly (largest bin at most 1.5 times the mean plus the records one
+// string can collect).
+// ---------------------------------------------------------------------------
+struct DryCall {
+  bool comm = false;
+  int64_t nH = 0, nO = 0;   // commutator operands (nH after the translation expansion)
+  int ts = 0;               // translation-symmetric sites (H0 listed over ts translates)
+  int64_t nterm = 0;        // operator-term records
+  int n_terms = 0;
+  bool wide = false;        // source ids kept aside (long canonicalisation lists)
+  int64_t n_keep = 0;
+  bool select = false;
+  int64_t out_arena = -1;   // >= 0: output rows taken from the top of the workspace
+  bool out_f32 = false;
+};
+
+template <int W, bool F32>
+void dry_call(Arena& ar, const DryCall& d, unsigned long long* pe_out) {
+  ar.bottom = 0;
+  int64_t nH = d.nH;
+  if (d.ts && d.comm && d.nH > 0) {
+    nH = d.nH * d.ts;
+    ar.take((size_t)nH * 8 * W);
+    ar.take((size_t)nH * 8 * W);
+    ar.take((size_t)nH * sizeof(double2));
+  }
+  const bool comm = d.comm && nH > 0 && d.nO > 0;
+  int comm_rows = 0, term_rows = 0;
+  plan_rows(comm, d.nO, d.nterm, &comm_rows, &term_rows);
+  Bufs1<W> b1;
+  take_bufs1<W>(ar, comm, nH, d.n_keep, comm_rows + term_rows, b1);
+  const unsigned long long pe =
+      (comm ? (unsigned long long)nH * (unsigned long long)d.nO : 0ull) + (unsigned long long)d.nterm;
+  if (pe_out) *pe_out = pe;
+  const unsigned long long mx = pe * 3 / (2 * NBINS) + 1 + (comm ? nH : 0) + d.n_terms;
+  int nbl = NBINS_LOG;
+  const int pass_bits = plan_pass_bits<W>(mx, &nbl);
+  const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
+  const uint32_t max_buckets = (uint32_t)(1u << nbl) << table_bits;
+  Bufs2 b2;
+  take_bufs2<W, F32>(ar, (size_t)std::max<unsigned long long>(pe, 1), d.wide || (comm && (nH > 2047 || d.ts)),
+                     nbl == NBINS_LOG_MP, max_buckets, d.select, b2);
+  if (d.out_arena >= 0) {
+    const size_t n = (size_t)std::max<int64_t>(d.out_arena, 1);
+    ar.take_top(n * 8 * W);
+    ar.take_top(n * 8 * W);
+    ar.take_top(n * (d.out_f32 ? 8 : 16));
+  }
+}
+
+void dry(int W, bool f32rec, Arena& ar, const DryCall& d, unsigned long long* pe) {
+  if (W == 1) f32rec ? dry_call<1, true>(ar, d, pe) : dry_call<1, false>(ar, d, pe);
+  else f32rec ? dry_call<2, true>(ar, d, pe) : dry_call<2, false>(ar, d, pe);
+}
+
+// the output bound of a call emitting `pe` records under truncation t
+int64_t out_bound(unsigned long long pe, const pauli_trunc* t) {
+  unsigned long long b = pe;
+  if (t && t->max_strings > 0) {
+    const long long k = t->keep ? t->keep->size : 0;
+    b = std::min<unsigned long long>(b, (unsigned long long)std::max<long long>(t->max_strings, k));
+  }
+  return (int64_t)std::max<unsigned long long>(b, 1);
+}
+
+int workspace_query(int op, const pauli_op* A, const pauli_op* B, const pauli_op* C,
+                    const pauli_trunc* t, size_t* ws_bytes, int64_t* out_cap) {
+  auto sz = [](const pauli_op* o) -> int64_t { return o ? std::max<int64_t>(o->size, 0) : 0; };
+  const pauli_op* any = B ? B : A;
+  if (!any || any->n_qubits < 1 || any->n_qubits > 128) return PAULI_EINVAL;
+  const int W = words_of(any->n_qubits);
+  const bool f32 = any->dtype == PAULI_C64K;
+  const int64_t n_keep = (t && t->keep) ? t->keep->size : 0;
+  const bool select = t && t->max_strings > 0;
+  Arena ar;
+  ar.dry = true;
+  ar.cap = ~(size_t)0;
+  unsigned long long pe = 0;
+  int64_t cap = 1;
+  DryCall d;
+  d.n_keep = n_keep;
+  d.select = select;
+  switch (op) {
+    case PAULI_Q_COMMUTATOR:
+    case PAULI_Q_MULTIPLY:
+    case PAULI_Q_COMMUTATOR_TS1D: {
+      if (!A || !B) return PAULI_EINVAL;
+      d.comm = true;
+      d.nH = sz(A);
+      d.nO = sz(B);
+      d.ts = op == PAULI_Q_COMMUTATOR_TS1D ? B->n_qubits : 0;
+      dry(W, f32, ar, d, &pe);
+      cap = out_bound(pe, t);
+      break;
+    }
+    case PAULI_Q_ADD: {
+      if (!A || !B) return PAULI_EINVAL;
+      d.nterm = sz(A) + sz(B);
+      d.n_terms = 2;
+      dry(W, A->dtype == PAULI_C64K && B->dtype == PAULI_C64K, ar, d, &pe);
+      cap = out_bound(pe, t);
+      break;
+    }
+    case PAULI_Q_TRUNCATE:
+    case PAULI_Q_CANONICALIZE:
+    case PAULI_Q_CANONICALIZE_TS1D: {
+      if (!B) return PAULI_EINVAL;
+      d.nterm = sz(B);
+      d.n_terms = 1;
+      d.wide = op != PAULI_Q_TRUNCATE;
+      d.select = op == PAULI_Q_TRUNCATE && select;
+      dry(W, f32, ar, d, &pe);
+      cap = op == PAULI_Q_TRUNCATE ? out_bound(pe, t) : out_bound(pe, nullptr);
+      break;
+    }
+    case PAULI_Q_LANCZOS:
+    case PAULI_Q_LANCZOS_TS1D: {
+      if (!A || !B) return PAULI_EINVAL;
+      d.comm = true;
+      d.nH = sz(A);
+      d.nO = sz(B);
+      d.ts = op == PAULI_Q_LANCZOS_TS1D ? B->n_qubits : 0;
+      d.nterm = sz(C);
+      d.n_terms = C ? 1 : 0;
+      dry(W, f32, ar, d, &pe);
+      cap = out_bound(pe, t);
+      break;
+    }
+    case PAULI_Q_LANCZOS_REORTH: {
+      if (!A || !B) return PAULI_EINVAL;
+      DryCall d1;
+      d1.comm = true;
+      d1.nH = sz(A);
+      d1.nO = sz(B);
+      d1.nterm = sz(C);
+      d1.n_terms = C ? 1 : 0;
+      unsigned long long pe1 = 0;
+      // O' at the top of the workspace, a bound without truncation
+      d1.out_arena = (int64_t)std::max<unsigned long long>(
+          (unsigned long long)d1.nH * (unsigned long long)d1.nO + (unsigned long long)d1.nterm, 1);
+      dry(W, f32, ar, d1, &pe1);
+      // projections: flags, results, partials, order keys of O_cur / O_prev
+      ar.bottom = 0;
+      ar.take(16);
+      ar.take(6 * 16);
+      ar.take((size_t)1024 * 16);
+      ar.take((size_t)1024 * 16);
+      ar.take((size_t)std::max<int64_t>(std::max(sz(B), sz(C)), 1) * 16 * W);
+      d.nterm = d1.out_arena + sz(B) + sz(C);
+      d.n_terms = 3;
+      dry(W, false, ar, d, &pe);
+      cap = out_bound(pe, t);
+      break;
+    }
+    case PAULI_Q_RK4: {
+      if (!A || !B) return PAULI_EINVAL;
+      const int64_t nO = sz(B), nH = sz(A);
+      int64_t S = nO, ksum = 0;
+      for (int stage = 0; stage < 4; stage++) {
+        DryCall dk;  // k = i [H, S], untruncated, at the top
+        dk.comm = true;
+        dk.nH = nH;
+        dk.nO = S;
+        const int64_t k = (int64_t)std::max<int64_t>(nH * S, 1);
+        dk.out_arena = k;
+        dry(W, false, ar, dk, nullptr);
+        ksum += k;
+        if (stage < 3) {
+          DryCall ds;  // S = trunc(O + h k), at the top
+          ds.nterm = nO + k;
+          ds.n_terms = 2;
+          ds.n_keep = n_keep;
+          ds.select = select;
+          ds.out_arena = out_bound((unsigned long long)(nO + k), t);
+          dry(W, false, ar, ds, nullptr);
+          S = ds.out_arena;
+        }
+      }
+      d.nterm = nO + ksum;
+      d.n_terms = 5;
+      dry(W, false, ar, d, &pe);
+      cap = out_bound(pe, t);
+      break;
+    }
+    case PAULI_Q_REDUCTION: {
+      // norm2, inner, trace, coefficients, norm2_ts1d: partials and order keys
+      const int64_t n = std::max(sz(A), sz(B));
+      ar.take(sizeof(Ctl));
+      ar.take((size_t)std::max<int64_t>(n, 1) * 16 * W);
+      ar.take((size_t)std::max<int64_t>(std::max(sz(A), sz(B)), 1) * 16);
+      ar.take((size_t)1024 * 16);
+      ar.take((size_t)1024 * 16);
+      ar.take(32);
+      cap = 0;
+      break;
+    }
+    default:
+      return PAULI_EINVAL;
+  }
+  // the engine adds the same margin when it reports a shortfall
+  if (ws_bytes) *ws_bytes = ar.need + (1 << 20);
+  if (out_cap) *out_cap = cap;
+  return PAULI_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1250,11 +1557,146 @@ static int lanczos_step(const pauli_op* H, const pauli_op* O_prev, const pauli_o
   return rc;
 }
 
+// Lanczos step with local re-orthogonalisation: O' = [H, O_cur] - b_prev O_prev
+// (untruncated, FP64, at the top of the workspace), then
+// O'' = O' - (<O_cur,O'>/<O_cur,O_cur>) O_cur - (<O_prev,O'>/<O_prev,O_prev>) O_prev
+// with both coefficients taken from O' (inner products and norms summed in
+// double-double, rounded once, divided in FP64), b_n = ||O''||,
+// O_next = trunc(O'' / b_n).
+static int lanczos_step_reorth(const pauli_op* H, const pauli_op* O_prev, const pauli_op* O_cur,
+                               double b_prev, const pauli_trunc* t, pauli_op* O_next,
+                               double* b_out, pauli_ws* ws, void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  Arena ar = make_arena(ws);
+  const int W = words_of(O_cur->n_qubits);
+  const bool f32 = O_cur->dtype == PAULI_C64K;
+  const bool has_prev = O_prev && O_prev->size > 0;
+  double b = 0.0;
+  // 1. O' in FP64 (the commutator in FP32 with compensated sums for PAULI_C64K)
+  Call c1;
+  c1.W = W;
+  c1.f32rec = f32;
+  c1.has_comm = true;
+  c1.H = view(H);
+  c1.O = view(O_cur);
+  c1.n_groups = 1;
+  c1.groups[0].kind = f32 ? G_SUM_KAHAN32 : G_SUM;
+  if (has_prev) {
+    c1.n_terms = 1;
+    c1.T[0] = view(O_prev);
+    c1.tgroup[0] = 1;
+    c1.n_groups = 2;
+    c1.groups[1].kind = G_TERM;
+    c1.groups[1].alpha = make_double2(-b_prev, 0.0);
+  }
+  c1.out.to_arena = true;
+  c1.out.f32 = 0;
+  TRY(run_call(ar, ws, stream, c1));
+  const OpV Op = c1.out.arena_op;
+  // 2. projections of O' on O_cur and O_prev
+  double2 alpha[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+  const pauli_op* V[2] = {O_cur, has_prev ? O_prev : nullptr};
+  if (Op.n > 0) {
+    ar.bottom = 0;
+    unsigned int* bad = (unsigned int*)ar.take(16);
+    double* res = (double*)ar.take(6 * 16);
+    const int blocks = (int)std::min<int64_t>(std::max<int64_t>((Op.n + 255) / 256, 1), 1024);
+    double2* pr = (double2*)ar.take((size_t)1024 * 16);  // partials of up to 1024 blocks
+    double2* pi = (double2*)ar.take((size_t)1024 * 16);
+    int64_t nk = 0;
+    for (int k = 0; k < 2; k++)
+      if (V[k]) nk = std::max<int64_t>(nk, V[k]->size);
+    void* vmk = ar.take((size_t)std::max<int64_t>(nk, 1) * 16 * W);
+    if (ar.short_) return ws_short(ar, ws);
+    LAUNCH("k_fill_u32", k_fill_u32, 1, 256, (uint32_t*)bad, 0u, (size_t)4);
+    for (int k = 0; k < 2; k++) {
+      const pauli_op* v = V[k];
+      if (!v || v->size == 0) continue;
+      const int vb = (int)std::min<int64_t>((v->size + 255) / 256, 1024);
+      const int vf32 = v->dtype == PAULI_C64K;
+      // <O', V> = sum conj(o') v over common strings (V canonical: binary search)
+      if (W == 1) {
+        LAUNCH("k_mix_keys", k_mix_keys<1>, (v->size + 255) / 256, 256, v->x, v->z, v->capacity,
+               v->size, (Key<1>*)vmk, bad);
+        LAUNCH("k_inner_part", k_inner_part<1>, blocks, 256, Op.x, Op.z, Op.cap, Op.n, Op.c, 0,
+               (const Key<1>*)vmk, v->size, v->coef, vf32, pr, pi);
+      } else {
+        LAUNCH("k_mix_keys", k_mix_keys<2>, (v->size + 255) / 256, 256, v->x, v->z, v->capacity,
+               v->size, (Key<2>*)vmk, bad);
+        LAUNCH("k_inner_part", k_inner_part<2>, blocks, 256, Op.x, Op.z, Op.cap, Op.n, Op.c, 0,
+               (const Key<2>*)vmk, v->size, v->coef, vf32, pr, pi);
+      }
+      LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, pr, (uint32_t)blocks, res + 6 * k);
+      LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, pi, (uint32_t)blocks, res + 6 * k + 2);
+      // ||V||^2 (the partials reuse pr: same stream, after the reduction above)
+      if (vf32)
+        LAUNCH("k_norm_part", k_norm_part<true>, vb, 256, v->coef, v->size, pr);
+      else
+        LAUNCH("k_norm_part", k_norm_part<false>, vb, 256, v->coef, v->size, pr);
+      LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, pr, (uint32_t)vb, res + 6 * k + 4);
+    }
+    double h[12];
+    unsigned int hbad = 0;
+    HIP_TRY(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    g_prof.resolve();
+    if (hbad) {
+      g_last_error = "re-orthogonalisation needs canonical O_cur and O_prev";
+      return PAULI_EINVAL;
+    }
+    for (int k = 0; k < 2; k++) {
+      if (!V[k] || V[k]->size == 0) continue;
+      const double n2 = h[6 * k + 4];
+      // <V, O'> = conj(<O', V>), divided by <V, V>
+      if (n2 > 0.0) alpha[k] = make_double2(h[6 * k] / n2, -h[6 * k + 2] / n2);
+    }
+  }
+  // 3. O'' = O' - alpha_0 O_cur - alpha_1 O_prev, b_n, divide, truncate
+  Call c2;
+  c2.W = W;
+  c2.f32rec = false;
+  c2.n_terms = 0;
+  c2.n_groups = 0;
+  // a term with a zero coefficient only adds exact zeros: left out
+  auto add_term = [&](const OpV& v, double2 al) {
+    if (v.n == 0 || (al.x == 0.0 && al.y == 0.0)) return;
+    c2.T[c2.n_terms] = v;
+    c2.tgroup[c2.n_terms] = c2.n_groups;
+    c2.groups[c2.n_groups].kind = G_TERM;
+    c2.groups[c2.n_groups].alpha = al;
+    c2.n_terms++;
+    c2.n_groups++;
+  };
+  add_term(Op, make_double2(1.0, 0.0));
+  for (int k = 0; k < 2; k++)
+    if (V[k]) add_term(view(V[k]), make_double2(-alpha[k].x, -alpha[k].y));
+  c2.mode = M_LANCZOS;
+  c2.trunc = t;
+  c2.out.user = O_next;
+  c2.out.f32 = f32;
+  c2.b_prev = b_prev;
+  c2.b_out = &b;
+  const int rc = run_call(ar, ws, stream, c2);
+  if (b_out) *b_out = b;
+  return rc;
+}
+
 int pauli_lanczos_step(const pauli_op* H, const pauli_op* O_prev, const pauli_op* O_cur,
                        double b_prev, const pauli_trunc* t, uint32_t flags, pauli_op* O_next,
                        double* b_out, pauli_ws* ws, void* stream) {
-  if (flags != 0) return PAULI_EINVAL;
-  return lanczos_step(H, O_prev, O_cur, b_prev, t, 0, O_next, b_out, ws, stream);
+  if (flags & ~(uint32_t)PAULI_REORTH_LOCAL) return PAULI_EINVAL;
+  if (!(flags & PAULI_REORTH_LOCAL))
+    return lanczos_step(H, O_prev, O_cur, b_prev, t, 0, O_next, b_out, ws, stream);
+  if (!ws || check_op(H, false) || check_op(O_cur, false) || check_op(O_next, true))
+    return PAULI_EINVAL;
+  if (O_prev && check_op(O_prev, false)) return PAULI_EINVAL;
+  if (H->dtype != PAULI_C128 || O_next->dtype != O_cur->dtype) return PAULI_EINVAL;
+  if (O_prev && O_prev->dtype != O_cur->dtype) return PAULI_EINVAL;
+  if (H->n_qubits != O_cur->n_qubits || O_next->n_qubits != O_cur->n_qubits ||
+      (O_prev && O_prev->n_qubits != O_cur->n_qubits))
+    return PAULI_EINVAL;
+  return lanczos_step_reorth(H, O_prev, O_cur, b_prev, t, O_next, b_out, ws, stream);
 }
 
 int pauli_lanczos_step_ts1d(const pauli_op* H0, const pauli_op* O_prev, const pauli_op* O_cur,
@@ -1417,6 +1859,24 @@ int pauli_strings_from_order_keys(int32_t n_qubits, const uint64_t* keys, int64_
            reinterpret_cast<const Key<2>*>(keys), n, x, z, cap);
   HIP_TRY(hipStreamSynchronize(stream));
   g_prof.resolve();
+  return PAULI_OK;
+}
+
+int pauli_workspace_query(int op, const pauli_op* A, const pauli_op* B, const pauli_op* C,
+                          const pauli_trunc* t, size_t* ws_bytes, int64_t* out_capacity_upper) {
+  return workspace_query(op, A, B, C, t, ws_bytes, out_capacity_upper);
+}
+
+int pauli_correlator(const pauli_op* O0, const pauli_op* O, double out[2], pauli_ws* ws,
+                     void* stream) {
+  if (!out || check_op(O0, false) || check_op(O, false)) return PAULI_EINVAL;
+  double n0 = 0.0, ip[2] = {0.0, 0.0};
+  TRY(pauli_norm2(O0, &n0, ws, stream));
+  // <O, O0> looped over O with order-key lookups in O0, then conjugated
+  TRY(pauli_inner(O, O0, ip, ws, stream));
+  if (!(n0 > 0.0)) return PAULI_EINVAL;
+  out[0] = ip[0] / n0;
+  out[1] = -ip[1] / n0;
   return PAULI_OK;
 }
 

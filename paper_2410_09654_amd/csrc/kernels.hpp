@@ -55,6 +55,7 @@ struct Ctl {
   unsigned int fin_level;        // 0: finish on the level-1 list, 1: after digit 1
   unsigned int deep;             // the device select stopped: the host finishes it
   unsigned int sel_d0, sel_d1;   // threshold digits 0 and 1
+  unsigned long long part_total; // records in all partitions (several-pass calls)
 };
 
 struct EmitArgs {
@@ -316,12 +317,15 @@ __attribute__((amdgpu_waves_per_eu(W == 1 && NBL <= 14 ? 8 : 4))) void k_emit(Em
         const int rot = a.ts_n ? ts_representative<W>(c.w, a.ts_n) : 0;
         const uint32_t horig = a.Hidx[h];
         const double2 hd = a.Hc[horig];
-        V hc;
-        hc.x = hd.x;
-        hc.y = hd.y;
+        // FP32 records: the product of the FP64 H coefficient and the stored
+        // FP32 coefficient is formed in FP64 and rounded once to FP32
         V prod;
-        if constexpr (F32) prod = cmulf(hc, bc);
-        else prod = cmul(hc, bc);
+        if constexpr (F32) {
+          const double2 pd = cmul(hd, make_double2((double)bc.x, (double)bc.y));
+          prod = make_float2((float)pd.x, (float)pd.y);
+        } else {
+          prod = cmul(hd, bc);
+        }
         deposit(c, a.product ? times_ie(prod, e) : times_2ie(prod, e), a.comm_group,
                 a.ts_n ? horig * 256u + (uint32_t)rot : horig);
       };
@@ -496,7 +500,7 @@ __global__ __launch_bounds__(1024) void k_scan_part(const uint32_t* total, int n
     pre += v[k];
   }
   for (int p = np + t; p < nbase; p += 1024) pbase[p] = tot;
-  if (t == 0) ctl->pe_total = tot;
+  if (t == 0) ctl->part_total = tot;
 }
 
 // Partition prefixes from the first count pass, which binned every record by

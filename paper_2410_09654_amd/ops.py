@@ -378,10 +378,13 @@ def canonicalize(O: PauliOp, out: PauliOp | None = None, ws: Workspace | None = 
 
 def lanczos_step(H: PauliOp, O_prev: PauliOp | None, O_cur: PauliOp, b_prev: float,
                  trunc: Trunc | None = None, out: PauliOp | None = None,
-                 ws: Workspace | None = None, ts1d: bool = False):
+                 ws: Workspace | None = None, ts1d: bool = False, reorth: bool = False):
     """(O_next, b_n, breakdown) of one Liouvillian Lanczos step on the GPU;
     ts1d: H holds H0 and the operators orbit representatives of the periodic
-    chain (translation-symmetric step, Alg. 2)."""
+    chain (translation-symmetric step, Alg. 2); reorth: local
+    re-orthogonalisation against O_cur and O_prev (PAULI_REORTH_LOCAL)."""
+    if ts1d and reorth:
+        raise ValueError("re-orthogonalisation is not offered for translation-symmetric steps")
     L = _lib.load()
     ws = ws or default_workspace(O_cur.device)
     if out is None:
@@ -404,7 +407,8 @@ def lanczos_step(H: PauliOp, O_prev: PauliOp | None, O_cur: PauliOp, b_prev: flo
                                            ctypes.byref(wss), _stream_handle())
         else:
             st = L.pauli_lanczos_step(ctypes.byref(hs), pp, ctypes.byref(cs), float(b_prev), tp,
-                                      0, ctypes.byref(outs), ctypes.byref(bval),
+                                      _lib.PAULI_REORTH_LOCAL if reorth else 0,
+                                      ctypes.byref(outs), ctypes.byref(bval),
                                       ctypes.byref(wss), _stream_handle())
         return st, outs
 
@@ -511,6 +515,35 @@ def profile_read() -> dict:
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+def correlator(O0: PauliOp, O: PauliOp, ws: Workspace | None = None) -> complex:
+    """S = <O0, O> / <O0, O0> (pauli_correlator; O0 canonical)."""
+    L = _lib.load()
+    ws = ws or default_workspace(O.device)
+    a, b = O0.c_struct(), O.c_struct()
+    res = (ctypes.c_double * 2)()
+    _call("pauli_correlator",
+          lambda wss: (L.pauli_correlator(ctypes.byref(a), ctypes.byref(b), res,
+                                          ctypes.byref(wss), _stream_handle()), None), ws, None)
+    return complex(res[0], res[1])
+
+
+def workspace_query(op: int, A: PauliOp | None, B: PauliOp | None, C: PauliOp | None = None,
+                    trunc: Trunc | None = None):
+    """(workspace bytes, output capacity) that pauli_workspace_query gives
+    for call `op` (one of the PAULI_Q_* codes) on these operands."""
+    L = _lib.load()
+    structs = [o.c_struct() if o is not None else None for o in (A, B, C)]
+    keep_s, ts = trunc.c_struct() if trunc else (None, None)
+    nb, cap = ctypes.c_size_t(0), ctypes.c_int64(0)
+    st = L.pauli_workspace_query(int(op), *[ctypes.byref(x) if x is not None else None
+                                            for x in structs],
+                                 ctypes.byref(ts) if ts is not None else None,
+                                 ctypes.byref(nb), ctypes.byref(cap))
+    if st != PAULI_OK:
+        raise PauliError(st, "pauli_workspace_query", _lib.last_error())
+    return int(nb.value), int(cap.value)
 
 
 def last_stats() -> dict:

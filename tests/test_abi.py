@@ -91,3 +91,45 @@ def test_invalid_arguments_of_the_other_entry_points():
                                      None) == _lib.PAULI_EINVAL
     assert L.pauli_lanczos_step_ts1d(r(a10), None, r(a12), 0.0, None, r(a12), r(b), r(ws),
                                      None) == _lib.PAULI_EINVAL
+
+
+def _query(L, _lib, op, sizes, n=64, dtype=0, trunc=None):
+    ops = [(_lib.PauliOpC(n, dtype, s, s, None, None, None) if s is not None else None)
+           for s in sizes]
+    nb, cap = ctypes.c_size_t(0), ctypes.c_int64(0)
+    rc = L.pauli_workspace_query(op, *[ctypes.byref(o) if o is not None else None for o in ops],
+                                 ctypes.byref(trunc) if trunc is not None else None,
+                                 ctypes.byref(nb), ctypes.byref(cap))
+    return rc, nb.value, cap.value
+
+
+def test_workspace_query_runs_on_host():
+    """pauli_workspace_query reads sizes only: it runs without a GPU, grows
+    with the operands, bounds the output by the top-M budget and rejects
+    unknown calls."""
+    from paper_2410_09654_amd import _lib
+    L = _lib.load()
+    for op in range(12):
+        rc, nb, cap = _query(L, _lib, op, [191, 1 << 14, 1 << 10])
+        assert rc == _lib.PAULI_OK and nb >= 1 << 20, (op, rc)
+    _, small, _ = _query(L, _lib, _lib.PAULI_Q_COMMUTATOR, [191, 1 << 12, None])
+    _, big, cap = _query(L, _lib, _lib.PAULI_Q_COMMUTATOR, [191, 1 << 16, None])
+    assert big > small and cap == 191 << 16
+    t = _lib.PauliTruncC(0, 0.0, 1000, None)
+    _, _, cap = _query(L, _lib, _lib.PAULI_Q_COMMUTATOR, [191, 1 << 16, None], trunc=t)
+    assert cap == 1000
+    _, _, cap = _query(L, _lib, _lib.PAULI_Q_ADD, [300, 500, None])
+    assert cap == 800
+    assert _query(L, _lib, 99, [1, 1, None])[0] == _lib.PAULI_EINVAL
+    assert _query(L, _lib, _lib.PAULI_Q_COMMUTATOR, [None, 5, None])[0] == _lib.PAULI_EINVAL
+
+
+def test_lanczos_rejects_unknown_flags():
+    from paper_2410_09654_amd import _lib
+    L = _lib.load()
+    op = _lib.PauliOpC(10, 0, 0, 0, None, None, None)
+    ws = _lib.PauliWsC(None, 0, 0)
+    b = ctypes.c_double()
+    rc = L.pauli_lanczos_step(ctypes.byref(op), None, ctypes.byref(op), 0.0, None, 2,
+                              ctypes.byref(op), ctypes.byref(b), ctypes.byref(ws), None)
+    assert rc == _lib.PAULI_EINVAL

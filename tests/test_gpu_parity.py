@@ -415,3 +415,46 @@ def test_commutator_largest_h(pk, ws, n, nh):
     H1 = wl.random_operator(n, nh + 1, seed=n + nh + 1, density=4.0 / n)
     with pytest.raises(pk.PauliError):
         pk.commutator(uph(pk, H1), up(pk, O, ws), ws=ws)
+
+
+def test_multi_pass_restart_after_wide_count(pk):
+    """A canonicalisation whose first count (2^14 bins) fits one pass at 2^15
+    bins, but whose 2^15-bin count still overflows a merge bucket (one string
+    repeated 1500 times on a background of 20 M distinct strings): the engine
+    restarts with two hash-range passes and must take the partition prefixes
+    from a fresh count, not from the overwritten first one.  Every string is
+    summed exactly once, in input order."""
+    import torch
+    count, rep, n = 20_000_000, 1500, 64
+    say(f"multi-pass restart canonicalize count={count} rep={rep}")
+    rng = np.random.default_rng(2026)
+
+    def words(k):
+        return (rng.integers(0, 2**63, size=k, dtype=np.uint64) * np.uint64(2) +
+                rng.integers(0, 2, size=k, dtype=np.uint64))
+    x, z = words(count), words(count)
+    c = rng.standard_normal(count) + 1j * rng.standard_normal(count)
+    pos = np.sort(rng.choice(count, size=rep, replace=False))
+    x[pos], z[pos] = x[0] ^ np.uint64(0x5555), z[0] ^ np.uint64(0xAAAA)
+    O = pk.PauliOp.from_raw(n, x[:, None], z[:, None], c)
+    ws = pk.Workspace(1 << 30)
+    got = pk.canonicalize(O, ws=ws)
+    st = pk.last_stats()
+    assert st["passes"] == 2, st
+    # reference: the distinct strings as given, the repeated one summed in input order
+    dup = complex(0.0)
+    for k in pos:
+        dup += c[k]
+    keep = np.ones(count, bool)
+    keep[pos] = False
+    rx = np.concatenate([x[keep], x[pos[:1]]])
+    rz = np.concatenate([z[keep], z[pos[:1]]])
+    rc = np.concatenate([c[keep], [dup]])
+    h = got.to_host()
+    assert h.n == len(rc)
+    go = np.lexsort([h.z[:, 0], h.x[:, 0]])
+    ro = np.lexsort([rz, rx])
+    assert np.array_equal(h.x[go, 0], rx[ro]) and np.array_equal(h.z[go, 0], rz[ro])
+    assert np.array_equal(h.coef[go], rc[ro])
+    del O, got, ws
+    torch.cuda.empty_cache()

@@ -100,3 +100,40 @@ def test_lanczos_f32k_two_words_truncated(pk, ws):
     assert np.allclose(got32, want32, rtol=1e-12, atol=0)
     rel = np.abs(np.array(got32) - np.array(got64)) / np.array(got64)
     assert rel.max() < 1e-6, rel
+
+
+def test_kahan_fold_hand_derived_gpu(pk, ws):
+    """The compensated FP32 fold on the GPU: Z_1 collects the contributions
+    2 c_i = (2^-20, -2^24, -1, 2^24) in ascending H index; Kahan's fold gives
+    exactly -1 (a plain FP32 sum gives 0, an FP64 sum -1 + 2^-20)."""
+    say("f32k kahan fold, hand-derived")
+    t = [2.0**-20, -2.0**24, -1.0, 2.0**24]
+    H, O = wl.same_key_runs(8, [v / 2 for v in t], seed=9)
+    got = pk.commutator(uph(pk, H), pk.PauliOp.from_raw(8, O.x, O.z, O.coef, dtype=C64K),
+                        ws=ws).to_host().as_dict()
+    assert got[(0, 1)] == complex(0.0, -1.0)
+
+
+@pytest.mark.parametrize("n,k,seed", [(20, 200, 2), (128, 1000, 0)])
+def test_kahan_long_runs_bit_exact(pk, ws, n, k, seed):
+    """Long cancelling runs into one string (k contributions of widely
+    different size): the GPU's FP32 fold equals the oracle's FP32 mode bit
+    for bit, on an instance where the compensated fold, a plain FP32 sum and
+    an FP64 sum of the same contributions round to three different FP32
+    values."""
+    say(f"f32k kahan long runs n={n} k={k}")
+    coefs = wl.cancelling_values(k, seed) / 2
+    H, O = wl.same_key_runs(n, coefs, seed=seed)
+    want = oracle.commutator(H, O, oracle.F32K)
+    z1 = (0,) * H.W + (1,) + (0,) * (H.W - 1)
+    wv = want.as_dict()[z1].imag
+    contrib = [np.float32(2 * c) for c in coefs]
+    plain = np.float32(0)
+    for v in contrib:
+        plain = np.float32(plain + v)
+    f64 = math.fsum(float(v) for v in contrib)
+    assert len({float(np.float32(wv)), float(plain), float(np.float32(f64))}) == 3
+    got = pk.commutator(uph(pk, H), pk.PauliOp.from_raw(n, O.x, O.z, O.coef, dtype=C64K),
+                        ws=ws).to_host()
+    assert exact_fraction(got, f32(want)) == 1.0
+    assert got.as_dict()[z1] == complex(0.0, float(np.float32(wv)))

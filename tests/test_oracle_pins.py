@@ -439,6 +439,94 @@ def test_dense_lanczos_random_small():
     assert np.allclose(bs, ref, rtol=1e-11)
 
 
+def test_reorth_is_a_noop_untruncated():
+    """Without truncation the Krylov vectors are orthogonal, so the local
+    re-orthogonalisation changes nothing: config 1's b_1..b_12 agree to
+    1e-15."""
+    H, O0, steps = wl.config_lanczos_small()
+    plain = oracle.lanczos(H, O0, steps)
+    ro = oracle.lanczos(H, O0, steps, reorth=True)
+    assert len(ro) == len(plain)
+    assert np.max(np.abs(np.array(ro) - plain) / np.array(plain)) <= 1e-15
+
+
+def test_reorth_lowers_overlap_when_truncated():
+    """With a top-M cut the three-term recursion loses orthogonality to
+    O_{n-2} (consecutive vectors share no strings here, so <O_n, O_{n-1}>
+    vanishes either way); the re-orthogonalised run keeps |<O_n, O_{n-2}>|
+    well below the plain recursion's."""
+    n = 10
+    H = wl.random_operator(n, 20, seed=51, real=True, density=0.3)
+    O0 = wl.from_terms(n, [(1.0, [("Z", 5)])])
+    t = oracle.Trunc(max_strings=60)
+
+    def worst(reorth):
+        _, basis = oracle.lanczos(H, O0, 14, t, keep_basis=True, reorth=reorth)
+        w1 = max(abs(oracle.inner(basis[k], basis[k - 1])) for k in range(1, len(basis)))
+        w2 = max(abs(oracle.inner(basis[k], basis[k - 2])) for k in range(2, len(basis)))
+        return w1, w2
+    p1, p2 = worst(False)
+    r1, r2 = worst(True)
+    assert p2 > 0.1 and r2 < p2 / 3
+    assert r1 <= p1
+
+
+def _pauli_basis(n):
+    """Every string of n sites (x, z in 0..2^n-1), its dense matrix and key."""
+    keys, mats = [], []
+    for x in range(2 ** n):
+        for z in range(2 ** n):
+            keys.append((x, z))
+            mats.append(dense_string(n, (x, z)))
+    return keys, mats
+
+
+def test_reorth_truncated_lanczos_vs_dense_vector_space():
+    """The whole re-orthogonalised, truncated step against an independent
+    implementation: operators as coefficient vectors over all 4^n strings,
+    the Liouvillian as the matrix Tr(P_i [H, P_j]) / 2^n from dense matrices,
+    Gram-Schmidt against the two previous vectors with numpy inner products,
+    division by b_n, then the top-M cut by |c| (ties by the smaller key)."""
+    n, M, steps = 4, 40, 10
+    H = wl.random_operator(n, 9, seed=41, real=True)
+    O0 = wl.random_operator(n, 5, seed=42, real=True)
+    O0.coef = O0.coef / math.sqrt(float(np.sum(np.abs(O0.coef) ** 2)))
+    keys, mats = _pauli_basis(n)
+    d = 2 ** n
+    dH = dense(H)
+    L = np.array([[np.trace(Pi @ (dH @ Pj - Pj @ dH)) / d for Pj in mats] for Pi in mats])
+    index = {k: i for i, k in enumerate(keys)}
+
+    def vec(op):
+        v = np.zeros(len(keys), complex)
+        for k, c in zip(op.keys(), op.coef):
+            v[index[k]] = c
+        return v
+
+    def trunc(v):
+        m2 = v.real * v.real + v.imag * v.imag
+        order = sorted((i for i in range(len(v)) if m2[i] > 0),
+                       key=lambda i: (-m2[i], keys[i][0], keys[i][1]))
+        out = np.zeros_like(v)
+        out[order[:M]] = v[order[:M]]
+        return out
+    prev, cur, b_prev, ref = None, vec(O0), 0.0, []
+    for _ in range(steps):
+        A = L @ cur
+        if prev is not None:
+            A = A - b_prev * prev
+        coefs = [np.vdot(V, A) / np.vdot(V, V).real for V in (cur, prev) if V is not None]
+        for V, a in zip((cur, prev), coefs):
+            A = A - a * V
+        b = math.sqrt(np.vdot(A, A).real)
+        ref.append(b)
+        prev, cur, b_prev = cur, trunc(A / b), b
+    got = oracle.lanczos(H, O0, steps, oracle.Trunc(max_strings=M), reorth=True)
+    assert np.allclose(got, ref, rtol=1e-12, atol=0)
+    plain = oracle.lanczos(H, O0, steps, oracle.Trunc(max_strings=M))
+    assert not np.allclose(plain, ref, rtol=1e-6, atol=0)  # the flag matters here
+
+
 @pytest.mark.parametrize("n", [6, 70])
 def test_majorana_chain_closed_form(n):
     J, h = 1.0, 0.7
@@ -618,6 +706,30 @@ def test_kahan_sum_matches_exact_sum():
     for c in contrib:
         naive = np.float32(naive + np.float32(c))
     assert abs(float(naive) - exact) > abs(got.imag - exact)
+
+
+def test_kahan_fold_hand_derived():
+    """The FP32 mode's compensated fold on one string, worked out by hand.
+
+    [X_1 S_i, c_i Y_1 S_i] = 2i c_i Z_1, so the imaginary part of Z_1's
+    coefficient sums t_i = 2 c_i in ascending H index, with
+    t = (2^-20, -2^24, -1, 2^24) (c_i = t_i / 2, all exact).  Kahan's update
+    y = t - comp, u = s + y, comp = (u - s) - y, s = u in FP32 gives:
+      t1: y = 2^-20, u = 2^-20, comp = 0, s = 2^-20
+      t2: y = -2^24, u = RN(2^-20 - 2^24) = -2^24,
+          comp = RN(-2^24 - 2^-20) + 2^24 = 0, s = -2^24
+      t3: y = -1, u = RN(-2^24 - 1) = -2^24 (tie to even), comp = 0 + 1 = 1
+      t4: y = 2^24 - 1 (exact), u = -1, comp = (2^24 - 1) - (2^24 - 1) = 0
+    so the value is (double)s - (double)comp = -1 exactly.  A plain FP32 sum
+    gives 0 (the string would be dropped) and an FP64 sum gives the exact
+    -1 + 2^-20: the three readings of the fold differ."""
+    t = [2.0**-20, -2.0**24, -1.0, 2.0**24]
+    H, O = wl.same_key_runs(8, [v / 2 for v in t], seed=9)
+    z1 = (0, 1)  # x word 0, z word 0 of Z_1
+    got = oracle.commutator(H, O, oracle.F32K).as_dict()[z1]
+    assert got == complex(0.0, -1.0)
+    exact = oracle.commutator(H, O, oracle.F64).as_dict()[z1]
+    assert exact == complex(0.0, -1.0 + 2.0**-20)
 
 
 def test_f32k_lanczos_within_split_tolerance():

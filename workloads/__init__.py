@@ -296,6 +296,37 @@ def random_local_strings(n_qubits: int, count: int, max_support: int = 10,
     return HostOp(n_qubits, xs[:count], zs[:count], coef)
 
 
+def cancelling_values(k: int, seed: int) -> np.ndarray:
+    """k signed powers of two in seeded random order: k//4 large values
+    +-2^20..2^24 each paired with its negative, the rest small values
+    +-2^-24..2^-1 (their sum is the exact total)."""
+    rng = np.random.default_rng(seed)
+    nb = k // 4
+    big = np.ldexp(rng.choice([-1.0, 1.0], nb), rng.integers(20, 25, nb))
+    small = np.ldexp(rng.choice([-1.0, 1.0], k - 2 * nb), rng.integers(-24, 0, k - 2 * nb))
+    vals = np.concatenate([big, -big, small])
+    return vals[rng.permutation(k)]
+
+
+def same_key_runs(n_qubits: int, coefs, seed: int = 5):
+    """H = [X_1 S_1, ..., X_1 S_k] (coefficient 1) and O = [Y_1 S_1, c_1, ...,
+    Y_1 S_k, c_k] with k distinct seeded strings S_i on sites 2..n_qubits:
+    pair (i, i) is the only one of H_i with O_i that lands on Z_1, so the
+    coefficient of Z_1 in [H, O] collects k contributions, one per H index."""
+    k = len(coefs)
+    rng = np.random.default_rng(seed)
+    S = set()
+    while len(S) < k:
+        S.add(tuple(int(v) for v in rng.integers(0, 4, n_qubits - 1)))
+    S = sorted(S)
+
+    def op(first, cs):
+        return from_terms(n_qubits, [(c, [(first, 1)] + [("IXZY"[p], j + 2)
+                                                         for j, p in enumerate(s) if p])
+                                     for s, c in zip(S, cs)])
+    return op("X", np.ones(k)), op("Y", np.asarray(coefs, np.complex128))
+
+
 def random_operator(n_qubits: int, count: int, seed: int, density: float = 0.5,
                     real: bool = False) -> HostOp:
     """`count` distinct strings with every site independently non-identity with
