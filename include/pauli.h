@@ -114,6 +114,19 @@ typedef struct pauli_ws {
 int pauli_commutator(const pauli_op *H, const pauli_op *O, const pauli_trunc *t,
                      pauli_op *out, pauli_ws *ws, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): pauli_commutator with its
+ * scratch in a static device array of 256 MiB per GPU (held from the first
+ * call on that GPU until the process ends) instead of a caller workspace.
+ * Allocates no device or pinned host memory.  Inputs, output and errors as
+ * pauli_commutator; a call whose scratch exceeds 256 MiB returns
+ * PAULI_EWORKSPACE (pauli_last_error names the need) and writes no output.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (several host threads or streams) race and must be serialised by the
+ * caller.  Synchronous at return, like pauli_commutator. */
+int pauli_commutator_noalloc(const pauli_op *H, const pauli_op *O, const pauli_trunc *t,
+                             pauli_op *out, void *stream);
+
 /* out = trunc(A B) = sum_{a,b} a_a b_b P_a P_b (Alg. 1 as written: every pair,
  * the string product and phase of the single-site multiplication table),
  * summed per string in ascending index of A.  A must be PAULI_C128 with fewer

@@ -20,7 +20,7 @@ EXPORTS = ["pauli_commutator", "pauli_multiply", "pauli_trace", "pauli_add", "pa
            "pauli_commutator_ts1d", "pauli_canonicalize_ts1d", "pauli_norm2_ts1d",
            "pauli_lanczos_step_ts1d",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
-           "pauli_correlator", "pauli_workspace_query",
+           "pauli_correlator", "pauli_workspace_query", "pauli_commutator_noalloc",
            "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_only", "pauli_profile_read",
            "pauli_last_stats", "pauli_order_keys", "pauli_strings_from_order_keys",
            "pauli_mlp_num_params", "pauli_mlp_sync", "pauli_mlp_forward",
@@ -72,6 +72,7 @@ def load():
     vp, d = ctypes.c_void_p, ctypes.c_double
     L.pauli_commutator.argtypes = [op, op, tr, op, ws, vp]
     L.pauli_multiply.argtypes = [op, op, tr, op, ws, vp]
+    L.pauli_commutator_noalloc.argtypes = [op, op, tr, op, vp]
     L.pauli_trace.argtypes = [op, P(d), ws, vp]
     L.pauli_add_noise.argtypes = [op, d, vp]
     L.pauli_commutator_ts1d.argtypes = [op, op, tr, op, ws, vp]

@@ -446,7 +446,7 @@ int Engine::run(Call& c) {
   uint32_t* h0sum = b1.h0sum;
   unsigned long long* psum = b1.psum;
   if (ar->short_) return PAULI_EWORKSPACE;
-  TRY(host_ctl(&hctl));
+  if (!hctl) TRY(host_ctl(&hctl));
   // the control block starts at zero (cleared by k_prep_h when there is one)
   if (!comm || rows == 0) TRY(zero_u32(dctl, sizeof(Ctl) / 4));
 
@@ -1013,10 +1013,12 @@ int dispatch(Engine& e, Call& c) {
   return PAULI_EINVAL;
 }
 
-int run_call(Arena& ar, pauli_ws* ws, void* stream, Call& c) {
+// hctl: host copy of the control block (nullptr: this thread's pinned block)
+int run_call(Arena& ar, pauli_ws* ws, void* stream, Call& c, Ctl* hctl = nullptr) {
   Engine e;
   e.ar = &ar;
   e.stream = (hipStream_t)stream;
+  e.hctl = hctl;
   int rc = dispatch(e, c);
   if (rc == PAULI_EWORKSPACE || ar.short_) return ws_short(ar, ws);
   return rc;
@@ -1239,6 +1241,45 @@ int workspace_query(int op, const pauli_op* A, const pauli_op* B, const pauli_op
   return PAULI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch that needs no allocation: a file-scope device array (one copy per
+// GPU, held until the process ends) for callers that cannot allocate.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): its device address on each GPU comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)256 << 20;
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {nullptr};
+// host copy of the control block for these calls (pageable: no host allocation)
+thread_local Ctl t_static_hctl;
+
+}  // namespace
+
+__device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+int static_scratch(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    g_last_error = "device ordinal beyond the static scratch table";
+    return PAULI_EINVAL;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255)) {
+      g_last_error = "static scratch address not 256-byte aligned";
+      return PAULI_EINTERNAL;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PAULI_OK;
+}
 }  // namespace
 
 // ===========================================================================
@@ -1324,6 +1365,39 @@ int pauli_commutator(const pauli_op* H, const pauli_op* O, const pauli_trunc* t,
   c.out.f32 = out->dtype == PAULI_C64K;
   c.round32 = c.out.f32;
   return run_call(ar, ws, stream, c);
+}
+
+int pauli_commutator_noalloc(const pauli_op* H, const pauli_op* O, const pauli_trunc* t,
+                             pauli_op* out, void* stream) {
+  if (check_op(H, false) || check_op(O, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (H->n_qubits != O->n_qubits || out->n_qubits != O->n_qubits) return PAULI_EINVAL;
+  if (H->dtype != PAULI_C128 || out->dtype != O->dtype) return PAULI_EINVAL;
+  void* base = nullptr;
+  TRY(static_scratch(&base));
+  pauli_ws ws = {base, STATIC_SCRATCH_BYTES, 0};
+  Arena ar = make_arena(&ws);
+  Call c;
+  c.W = words_of(O->n_qubits);
+  c.f32rec = O->dtype == PAULI_C64K;
+  c.has_comm = true;
+  c.H = view(H);
+  c.O = view(O);
+  c.comm_group = 0;
+  c.n_groups = 1;
+  c.groups[0].kind = c.f32rec ? G_SUM_KAHAN32 : G_SUM;
+  c.trunc = t;
+  c.out.user = out;
+  c.out.f32 = out->dtype == PAULI_C64K;
+  c.round32 = c.out.f32;
+  const int rc = run_call(ar, &ws, stream, c, &t_static_hctl);
+  if (rc == PAULI_EWORKSPACE) {
+    char msg[200];
+    snprintf(msg, sizeof(msg),
+             "the call needs %zu bytes of scratch; the static scratch holds %zu",
+             ws.required, STATIC_SCRATCH_BYTES);
+    g_last_error = msg;
+  }
+  return rc;
 }
 
 int pauli_multiply(const pauli_op* A, const pauli_op* B, const pauli_trunc* t, pauli_op* out,
