@@ -97,6 +97,31 @@ class PauliOp:
         x, z, c = self.to_numpy()
         return HostOp(self.n_qubits, x, z, c)
 
+    # -- checkpoints -------------------------------------------------------------
+    def save(self, path: str):
+        """Checkpoint: the operator's rows as stored (word-major masks, coefficients
+        in their own precision, the library's order) in one .npz file."""
+        n = self.size
+        np.savez(path, n_qubits=np.int64(self.n_qubits), dtype=np.int64(self.dtype),
+                 x=self.x[:, :n].cpu().numpy().view(np.uint64),
+                 z=self.z[:, :n].cpu().numpy().view(np.uint64),
+                 coef=self.coef[:n].cpu().numpy())
+
+    @classmethod
+    def load(cls, path: str, device="cuda") -> "PauliOp":
+        """An operator saved by `save`, restored row for row (no recomputation)."""
+        with np.load(path, allow_pickle=False) as f:
+            n_qubits, dtype = int(f["n_qubits"]), int(f["dtype"])
+            x, z, coef = f["x"], f["z"], f["coef"]
+        n = coef.shape[0]
+        op = cls(n_qubits, max(n, 1), dtype, device)
+        if n:
+            op.x[:, :n] = torch.from_numpy(np.ascontiguousarray(x).view(np.int64)).to(device)
+            op.z[:, :n] = torch.from_numpy(np.ascontiguousarray(z).view(np.int64)).to(device)
+            op.coef[:n] = torch.from_numpy(np.ascontiguousarray(coef)).to(device)
+        op.size = n
+        return op
+
 
 class Trunc:
     """Truncation parameters (see pauli_trunc in include/pauli.h)."""

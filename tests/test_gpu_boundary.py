@@ -148,3 +148,29 @@ def test_workspace_query_is_sufficient(pk):
     Ots = pk.canonicalize_ts1d(pk.PauliOp.from_host(wl.random_local_strings(24, 3000, 6, seed=9)))
     nbytes, _ = pk.workspace_query(Q.PAULI_Q_COMMUTATOR_TS1D, H0, Ots)
     assert _fits(pk, nbytes, lambda w: pk.commutator_ts1d(H0, Ots, ws=w))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_checkpoint_resume_is_exact(pk, ws, tmp_path, dtype):
+    """Saving the Krylov vectors to .npz and resuming the recursion from them
+    gives the same b_n, bit for bit, as the uninterrupted run."""
+    say(f"checkpoint resume dtype={dtype}")
+    H, O0 = wl.config_lanczos_split()
+    if dtype:
+        O0 = f32(O0)
+    Hd = uph(pk, H)
+    T = pk.Trunc(max_strings=5000)
+    full = pk.lanczos(Hd, pk.PauliOp.from_host(O0, dtype=dtype, ws=ws), 10, T, ws=ws)
+    prev, cur, b = None, pk.PauliOp.from_host(O0, dtype=dtype, ws=ws), 0.0
+    bs = []
+    for k in range(10):
+        if k == 5:  # checkpoint and restore
+            prev.save(str(tmp_path / "prev.npz"))
+            cur.save(str(tmp_path / "cur.npz"))
+            prev = pk.PauliOp.load(str(tmp_path / "prev.npz"))
+            cur = pk.PauliOp.load(str(tmp_path / "cur.npz"))
+            assert cur.dtype == dtype
+        nxt, b, _ = pk.lanczos_step(Hd, prev, cur, b, T, ws=ws)
+        bs.append(b)
+        prev, cur = cur, nxt
+    assert bs == list(full)

@@ -111,3 +111,55 @@ def test_noisy_xxz_full_parameters(pk):
     assert np.allclose(np.array(got_P), np.array(want_P), rtol=1e-12, atol=1e-15)
     del ws, got_O
     torch.cuda.empty_cache()
+
+
+def test_rk4_tfim_trajectory_single_steps_with_budget_binding(pk):
+    """The RK4 workload with the string budget binding: along the oracle's
+    own trajectory (8x8 TFIM, O0 = Z(4,4), dt = 0.02, length <= 16, O0 kept,
+    M = 2^12, which binds from step 2), every step is taken on the GPU from
+    the oracle's previous state and compared element-wise, through step 12."""
+    H, O0 = wl.config_rk4_tfim()
+    M, L, dt = 1 << 12, 16, 0.02
+    ws = pk.Workspace(256 << 20)
+    Hd = pk.PauliOp.from_raw(64, H.x, H.z, H.coef)
+    Od0 = pk.PauliOp.from_host(O0, ws=ws)
+    tg = pk.Trunc(max_len=L, max_strings=M, keep=Od0)
+    th = oracle.Trunc(max_len=L, max_strings=M, keep=O0)
+    cur = O0
+    for k in range(12):
+        say(f"rk4 TFIM trajectory, M = 2^12: step {k + 1}")
+        want = oracle.rk4_step(H, cur, dt, th)
+        got = pk.rk4_step(Hd, pk.PauliOp.from_host(cur, ws=ws), dt, tg, ws=ws).to_host()
+        assert want.n == (M if k >= 1 else want.n)
+        assert_same_operator(got, want, what=f"rk4 step {k + 1}")
+        cur = want
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lanczos_split_trajectory_single_steps_with_budget_binding(pk, prec):
+    """The precision-split workload with the budget binding: along the
+    oracle's trajectory (N = 128 XXZ(0.5) + 0.3 r_i Z_i, O0 = sum X_i/sqrt N,
+    M = 2^12, binding from step 4), each Lanczos step on the GPU from the
+    oracle's O_{n-2}, O_{n-1} and b_{n-1}, FP64 (1e-12) and FP32 + Kahan
+    (keys and stored FP32 values bit-exact), through step 14."""
+    H, O0 = wl.config_lanczos_split()
+    M = 1 << 12
+    ws = pk.Workspace(256 << 20)
+    Hd = pk.PauliOp.from_raw(128, H.x, H.z, H.coef)
+    dt = pk.PAULI_C64K if prec else pk.PAULI_C128
+    th, tg = oracle.Trunc(max_strings=M), pk.Trunc(max_strings=M)
+    prev, cur, b_prev = None, (f32(O0) if prec else O0), 0.0
+    for k in range(14):
+        say(f"precision split trajectory, M = 2^12, prec {prec}: step {k + 1}")
+        want, bw, broke = oracle.lanczos_step(H, prev, cur, b_prev, th, prec)
+        pd = pk.PauliOp.from_host(prev, dtype=dt, ws=ws) if prev is not None else None
+        got, bg, gbroke = pk.lanczos_step(Hd, pd, pk.PauliOp.from_host(cur, dtype=dt, ws=ws),
+                                          b_prev, tg, ws=ws)
+        assert not broke and not gbroke
+        assert abs(bg - bw) <= 1e-12 * bw
+        g = got.to_host()
+        if k >= 3:
+            assert want.n == M
+        assert_same_operator(g, want, rtol=1e-12 if not prec else 0.0,
+                             what=f"lanczos step {k + 1}")
+        prev, cur, b_prev = cur, want, bw

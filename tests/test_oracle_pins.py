@@ -296,6 +296,17 @@ def test_xx_chain_gaussian_lanczos_closed_form():
         assert np.allclose(np.array(b_ts) ** 2, 8.0 * np.arange(1, steps + 1), rtol=1e-12, atol=0)
 
 
+def test_chunked_commutator_equals_commutator():
+    """The full-size helper (chunks of O, summed by linearity) gives the same
+    strings as the plain commutator and coefficients equal to rounding."""
+    H = wl.ising_chain(64)
+    O = wl.random_local_strings(64, 6000, 10, seed=12)
+    a, b = oracle.commutator(H, O).as_dict(), oracle.commutator_chunked(H, O, threads=4,
+                                                                       chunks=7).as_dict()
+    assert set(a) == set(b)
+    assert max(abs(a[k] - b[k]) / max(1.0, abs(a[k])) for k in a) <= 1e-14
+
+
 def test_add_norm_inner_vs_dense():
     n = 5
     A = wl.random_operator(n, 20, seed=11)
@@ -738,3 +749,29 @@ def test_f32k_lanczos_within_split_tolerance():
     b32 = oracle.lanczos(H, O0, steps, prec=oracle.F32K)
     rel = np.abs(np.array(b32) - np.array(b64)) / np.array(b64)
     assert rel.max() < 1e-6
+
+
+def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any report aborts), driven through every routine on random one- and
+    two-word operators by tests/sanitize_oracle.c."""
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc missing")
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path / "sanitize_oracle")
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-ffp-contract=off",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-fno-omit-frame-pointer", "-o", exe,
+                           os.path.join(here, "sanitize_oracle.c"),
+                           os.path.join(here, "..", "oracle", "pauli_oracle.c"), "-lm"])
+    # a preloaded library ahead of the sanitizer runtime is tolerated
+    env = dict(os.environ,
+               ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([exe], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
+    assert "sanitizer driver ok" in r.stdout
