@@ -35,7 +35,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--count", type=int, default=1 << 20, help="strings in O")
     ap.add_argument("--cpu-sample", type=int, default=1 << 17,
-                    help="O strings given to the CPU oracle (0: skip the CPU baseline)")
+                    help="O strings given to the single-threaded CPU oracle timing (0: skip "
+                         "every CPU baseline)")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="host threads of the full-size CPU oracle run (at most the usable CPUs)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--workload", default="commutator",
                     choices=["commutator", "lanczos-split", "rk4-tfim", "lanczos-small", "moments",
@@ -77,6 +80,50 @@ def measured_traffic(kernel: str):
             "total_bytes": round(k["fetch_bytes"] + k["write_bytes"])}
 
 
+def host_info(threads_used: int | None = None) -> dict:
+    """nproc, CPU model and GPU name of the machine running the benchmark."""
+    import torch
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    info = {"nproc": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0)),
+            "cpu_model": model,
+            "gpu": torch.cuda.get_device_name(0) if torch.cuda.is_available() else None}
+    if threads_used is not None:
+        info["threads_used"] = threads_used
+    return info
+
+
+def measured_copy_gbs(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """HBM bandwidth of a plain device-to-device copy of `nbytes` (read + write
+    counted), timed with events: the practical ceiling beside the 8 TB/s spec."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def cpu_threads(args) -> int:
+    return max(1, min(args.cpu_threads, len(os.sched_getaffinity(0))))
+
+
 def calibrate_copy(nbytes: int):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -85,6 +132,17 @@ def calibrate_copy(nbytes: int):
         torch.mul(src, 1.0, out=dst)  # elementwise kernel: reads and writes nbytes
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes, "launches": 5}), flush=True)
+
+
+def step_roofline(tot: dict, wall: float, steps: int) -> dict:
+    """Whole-step HBM roofline fraction: the algorithmic bytes of every engine
+    pass of the timed steps (inputs + 2 records + 2 merged + output, at the
+    record size; pauli_read_totals) over the wall time, against 8 TB/s."""
+    gbs = tot["alg_bytes"] / wall / 1e9
+    return {"bound": "hbm", "alg_bytes_per_step": tot["alg_bytes"] / max(steps, 1),
+            "records_per_step": tot["emitted"] / max(steps, 1),
+            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def run_lanczos_split(args):
@@ -116,6 +174,7 @@ def run_lanczos_split(args):
         prev, cur, b_prev = None, O0, 0.0
         bs, sizes, pairs, emitted = [], [], 0, 0
         torch.cuda.synchronize()
+        pk.read_totals(reset=True)
         t0 = time.perf_counter()
         for _ in range(steps):
             pairs += H.size * cur.size
@@ -128,8 +187,10 @@ def run_lanczos_split(args):
             prev, cur, b_prev = cur, nxt, b
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        tot = pk.read_totals()
         res[name] = {"b": bs, "strings": sizes, "seconds": wall, "ms_per_step": 1e3 * wall / len(bs),
-                     "pairs_per_s": pairs / wall, "emitted_per_s": emitted / wall}
+                     "pairs_per_s": pairs / wall, "emitted_per_s": emitted / wall,
+                     "roofline_step": step_roofline(tot, wall, len(bs))}
     b64, b32, b64r = res["f64"]["b"], res["f32_kahan"]["b"], res["f64_reversed_H"]["b"]
     b64p = res["f64_perturbed_H"]["b"]
     m = min(len(b64), len(b32), len(b64r), len(b64p))
@@ -137,6 +198,34 @@ def run_lanczos_split(args):
     rel_r = [abs(b64r[k] - b64[k]) / abs(b64[k]) for k in range(m)]
     rel_p = [abs(b64p[k] - b64[k]) / abs(b64[k]) for k in range(m)]
     full = [k for k in range(m) if res["f64"]["strings"][k] < M]  # steps before the cut binds
+    one_step = None
+    if args.cpu_sample > 0:
+        # one Lanczos step, oracle and GPU, FP64 and FP32 + Kahan, from the
+        # oracle's own vectors after five steps at M = 2^12 (budget binding)
+        import oracle
+        one_step = {}
+        for name, prec, dt in (("f64", oracle.F64, pk.PAULI_C128),
+                               ("f32_kahan", oracle.F32K, pk.PAULI_C64K)):
+            th = oracle.Trunc(max_strings=1 << 12)
+            o0 = O0_host if prec == oracle.F64 else wl.HostOp(
+                128, O0_host.x, O0_host.z, O0_host.coef.astype(np.complex64).astype(complex))
+            prev, cur, b_prev = None, o0, 0.0
+            for _ in range(5):
+                nxt, b_prev_new, _ = oracle.lanczos_step(H_host, prev, cur, b_prev, th, prec)
+                prev, cur, b_prev = cur, nxt, b_prev_new
+            tc = time.perf_counter()
+            oracle.lanczos_step(H_host, prev, cur, b_prev, th, prec)
+            tcpu = time.perf_counter() - tc
+            Hd = pk.PauliOp.from_raw(128, H_host.x, H_host.z, H_host.coef)
+            pd = pk.PauliOp.from_host(prev, dtype=dt, ws=ws)
+            cd = pk.PauliOp.from_host(cur, dtype=dt, ws=ws)
+            pk.lanczos_step(Hd, pd, cd, b_prev, pk.Trunc(max_strings=1 << 12), ws=ws)
+            torch.cuda.synchronize()
+            tg = time.perf_counter()
+            pk.lanczos_step(Hd, pd, cd, b_prev, pk.Trunc(max_strings=1 << 12), ws=ws)
+            torch.cuda.synchronize()
+            one_step[name] = {"strings": cur.n, "oracle_seconds": tcpu,
+                              "gpu_seconds": time.perf_counter() - tg, "cores": 1}
     print(json.dumps({"workload": "lanczos precision split: N=128 XXZ(0.5) + 0.3 r_i Z_i, "
                                   "O0 = sum X_i/sqrt(N)", "steps": steps, "max_strings": M,
                       "b_rel_err_vs_f64": rel, "max_b_rel_err": max(rel) if rel else None,
@@ -147,6 +236,7 @@ def run_lanczos_split(args):
                       "max_f64_h_perturbation_sensitivity": max(rel_p) if rel_p else None,
                       "max_h_perturbation_sensitivity_untruncated_steps":
                           max([rel_p[k] for k in full], default=None),
+                      "one_step_M4096_from_oracle_state": one_step, "host": host_info(),
                       **res}), flush=True)
 
 
@@ -163,22 +253,50 @@ def run_rk4_tfim(args):
     ws = pk.Workspace(1 << 30)
     O0 = pk.PauliOp.from_host(O0_host, ws=ws)
     trunc = pk.Trunc(max_len=16, max_strings=M, keep=O0)
-    n0 = pk.norm2(O0, ws=ws)
     S, sizes, pairs = [1.0], [O0.size], 0
     cur = O0
     torch.cuda.synchronize()
+    pk.read_totals(reset=True)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         pairs += 4 * H.size * cur.size  # lower bound: the stages grow beyond |O|
         cur = pk.rk4_step(H, cur, 0.02, trunc, ws=ws)
-        S.append(pk.inner(cur, O0, ws=ws).conjugate().real / n0)
+        S.append(pk.correlator(O0, cur, ws=ws).real)
         sizes.append(cur.size)
+        if k % 50 == 49:
+            print(f"rk4 step {k + 1}: {1e3 * (time.perf_counter() - t0) / (k + 1):.1f} ms/step",
+                  file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    print(json.dumps({"workload": "rk4 8x8 TFIM J=1 hx=2, O0 = Z(4,4), dt = 0.02",
-                      "steps": steps, "max_strings": M, "max_len": 16,
-                      "seconds": wall, "ms_per_step": 1e3 * wall / steps, "S": S,
-                      "strings": sizes}), flush=True)
+    tot = pk.read_totals()
+    line = {"workload": "rk4 8x8 TFIM J=1 hx=2, O0 = Z(4,4), dt = 0.02",
+            "steps": steps, "max_strings": M, "max_len": 16,
+            "seconds": wall, "ms_per_step": 1e3 * wall / steps, "S": S,
+            "strings": sizes, "roofline_step": step_roofline(tot, wall, steps),
+            "host": host_info()}
+    if args.cpu_sample > 0:
+        # one RK4 step, oracle and GPU, from the oracle's own state after five
+        # steps at M = 2^12 (budget binding; a full-M step takes minutes on the host)
+        import oracle
+        Ms = 1 << 12
+        th = oracle.Trunc(max_len=16, max_strings=Ms, keep=O0_host)
+        st = O0_host
+        for _ in range(5):
+            st = oracle.rk4_step(H_host, st, 0.02, th)
+        tc = time.perf_counter()
+        oracle.rk4_step(H_host, st, 0.02, th)
+        tcpu = time.perf_counter() - tc
+        sd = pk.PauliOp.from_host(st, ws=ws)
+        tg_trunc = pk.Trunc(max_len=16, max_strings=Ms, keep=O0)
+        pk.rk4_step(H, sd, 0.02, tg_trunc, ws=ws)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        pk.rk4_step(H, sd, 0.02, tg_trunc, ws=ws)
+        torch.cuda.synchronize()
+        line["one_step_M4096_from_oracle_state"] = {
+            "strings": st.n, "oracle_seconds": tcpu, "gpu_seconds": time.perf_counter() - tg,
+            "cores": 1}
+    print(json.dumps(line), flush=True)
 
 
 def run_lanczos_small(args):
@@ -305,21 +423,22 @@ def run_noisy_xxz(args):
                                        for k in range(steps + 1))}
     if args.cpu_sample > 0:
         import oracle
-        # one noisy step, oracle and GPU, from a sample of the evolved state: its
-        # 4096 largest strings (a full-M step would take minutes on one core)
+        # one noisy step, oracle and GPU, from the oracle's own state after
+        # four steps at M = 4096 (a full-M step would take minutes on one core)
         Ms = 4096
-        Os = pk.truncate(O, pk.Trunc(max_strings=Ms), ws=ws)
-        hs = Os.to_host()
+        hs, _, _ = oracle.evolve_noisy(H_host, O0_host, dt, 4, Ms, eps)
         print(f"oracle step from {hs.n} strings", file=sys.stderr, flush=True)
         tc = time.perf_counter()
         oracle.evolve_noisy(H_host, hs, dt, 1, Ms, eps)
         tcpu = time.perf_counter() - tc
+        Os = pk.PauliOp.from_host(hs, ws=ws)
+        pk.evolve_noisy(H, Os, dt, 1, Ms, eps, ws=ws)
         torch.cuda.synchronize()
         tg = time.perf_counter()
         pk.evolve_noisy(H, Os, dt, 1, Ms, eps, ws=ws)
         torch.cuda.synchronize()
         tgpu = time.perf_counter() - tg
-        line["step_from_4096_string_sample"] = {"strings": hs.n, "oracle_seconds": tcpu,
+        line["step_from_oracle_state_M4096"] = {"strings": hs.n, "oracle_seconds": tcpu,
                                                 "gpu_seconds": tgpu, "cores": 1}
     print(json.dumps(line), flush=True)
 
@@ -558,19 +677,38 @@ def main():
                                       "achieved": round(mt_bytes / (mt_ms * 1e-3) / 1e9, 1),
                                       "frac": round(mt_bytes / (mt_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
+    if roofline is not None:
+        copy = measured_copy_gbs()
+        roofline["measured_copy_GBs"] = round(copy, 1)
+        roofline["frac_of_measured_copy"] = round(roofline["achieved"] / copy, 4)
+
     cpu = None
     if args.cpu_sample > 0:
         import oracle
+        # the whole workload on the host cores: O in chunks over the threads
+        # (the C oracle as it stands, one call per chunk), added by linearity,
+        # then the oracle's truncation
+        nt = cpu_threads(args)
+        tc0 = time.perf_counter()
+        C = oracle.commutator_chunked(H_host, O_host, threads=nt, chunks=4 * nt)
+        oracle.truncate(C, oracle.Trunc(max_len=max_len, max_strings=max_strings))
+        tc = time.perf_counter() - tc0
+        del C
+        # single thread on a sample (the paper's one-core setting)
         n = min(args.cpu_sample, O_host.n)
         sub = wl.HostOp(64, O_host.x[:n], O_host.z[:n], O_host.coef[:n])
-        tc0 = time.perf_counter()
-        C = oracle.commutator(H_host, sub)
-        oracle.truncate(C, oracle.Trunc(max_len=max_len, max_strings=n))
-        tc = time.perf_counter() - tc0
-        cpu = {"value": H_host.n * n / tc, "unit": "products/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {n} of the {O_host.n} O strings ({H_host.n * n} pairs), "
-                         f"commutator + truncate (length <= {max_len}, top {n}), "
-                         f"single-threaded C oracle, {tc:.1f} s"}
+        ts0 = time.perf_counter()
+        C1 = oracle.commutator(H_host, sub)
+        oracle.truncate(C1, oracle.Trunc(max_len=max_len, max_strings=n))
+        ts = time.perf_counter() - ts0
+        cpu = {"value": pairs / tc, "unit": "products/s", "cores": nt, "kind": "oracle",
+               "sample": f"the whole workload: all {O_host.n} O strings ({pairs} pairs) in "
+                         f"{4 * nt} chunks over {nt} threads, added by linearity, then "
+                         f"truncate (length <= {max_len}, top {max_strings}); {tc:.1f} s",
+               "single_thread": {"value": H_host.n * n / ts, "cores": 1,
+                                 "sample": f"first {n} O strings ({H_host.n * n} pairs), "
+                                           f"commutator + truncate, {ts:.1f} s"},
+               "host": host_info(nt)}
 
     line = {
         "metric": METRIC, "value": value, "unit": "products/s", "n_gpus": 1,

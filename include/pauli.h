@@ -359,6 +359,23 @@ typedef struct pauli_stats {
 } pauli_stats;
 void pauli_last_stats(pauli_stats *out);
 
+/* Totals over every engine pass of this thread since the last reset (a
+ * Runge-Kutta step makes eight passes, a Lanczos step one or two): strings
+ * read as inputs, records emitted, merged strings, output strings, and the
+ * algorithmic HBM bytes (inputs + 2 emitted + 2 merged + output) times the
+ * record size (16 W + 16 bytes in FP64, 16 W + 8 in FP32) that the method
+ * must move once its products are materialised.  reset != 0 clears them
+ * after reading. */
+typedef struct pauli_totals {
+  int64_t calls;
+  int64_t inputs;
+  int64_t emitted;
+  int64_t unique;
+  int64_t output;
+  double alg_bytes;
+} pauli_totals;
+void pauli_read_totals(pauli_totals *out, int reset);
+
 /* Static description of the error code. */
 const char *pauli_strerror(int status);
 /* Text of the last HIP error seen by this thread (empty if none). */

@@ -793,7 +793,8 @@ void or_inner(const or_op *A, const or_op *B, double *re, double *im) {
 /*   O_n  = trunc(O'_n / b_n)                                                */
 /* Breakdown when b_n <= 1e-13 max(1, b_{n-1}).                              */
 /* prec = OR_F32K: commutator in FP32 with Kahan sums (values then FP64),    */
-/* recombination, norm and division in FP64, result rounded to FP32.        */
+/* recombination, norm, division and truncation decisions in FP64, the kept */
+/* values rounded to FP32.                                                   */
 /* ------------------------------------------------------------------------ */
 static void round_to_f32(or_op *o) {
   int64_t m = 0;
@@ -804,6 +805,19 @@ static void round_to_f32(or_op *o) {
     memmove(&o->z[2 * m], &o->z[2 * k], 2 * sizeof(uint64_t));
     o->re[m] = re;
     o->im[m] = im;
+    m++;
+  }
+  o->n = m;
+}
+
+static void drop_f32_zeros(or_op *o) {
+  int64_t m = 0;
+  for (int64_t k = 0; k < o->n; k++) {
+    if (is_zero((double)(float)o->re[k], (double)(float)o->im[k])) continue;
+    memmove(&o->x[2 * m], &o->x[2 * k], 2 * sizeof(uint64_t));
+    memmove(&o->z[2 * m], &o->z[2 * k], 2 * sizeof(uint64_t));
+    o->re[m] = o->re[k];
+    o->im[m] = o->im[k];
     m++;
   }
   o->n = m;
@@ -872,9 +886,13 @@ static int lanczos_step(int ts, const or_op *H, const or_op *O_prev, const or_op
   rc = or_divide(&A, b, &D);
   or_free(&A);
   if (rc) return rc;
-  if (prec == OR_F32K) round_to_f32(&D);
+  /* FP32 mode: strings whose FP32 value would be an exact zero are dropped;
+   * the cutoff and top-M are decided on the FP64 quotient; the kept values
+   * are then rounded to FP32 */
+  if (prec == OR_F32K) drop_f32_zeros(&D);
   rc = or_truncate(&D, t, O_next);
   or_free(&D);
+  if (rc == OR_OK && prec == OR_F32K) round_to_f32(O_next);
   return rc;
 }
 

@@ -21,6 +21,7 @@ EXPORTS = ["pauli_commutator", "pauli_multiply", "pauli_trace", "pauli_add", "pa
            "pauli_lanczos_step_ts1d",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
            "pauli_correlator", "pauli_workspace_query", "pauli_commutator_noalloc",
+           "pauli_read_totals",
            "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_only", "pauli_profile_read",
            "pauli_last_stats", "pauli_order_keys", "pauli_strings_from_order_keys",
            "pauli_mlp_num_params", "pauli_mlp_sync", "pauli_mlp_forward",
@@ -47,6 +48,12 @@ class PauliStatsC(ctypes.Structure):
     _fields_ = [("emitted", ctypes.c_int64), ("unique", ctypes.c_int64),
                 ("survivors", ctypes.c_int64), ("output", ctypes.c_int64),
                 ("passes", ctypes.c_int32), ("buckets", ctypes.c_int32)]
+
+
+class PauliTotalsC(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int64), ("inputs", ctypes.c_int64),
+                ("emitted", ctypes.c_int64), ("unique", ctypes.c_int64),
+                ("output", ctypes.c_int64), ("alg_bytes", ctypes.c_double)]
 
 
 class PauliError(RuntimeError):
@@ -100,13 +107,15 @@ def load():
     L.pauli_profile_read.restype = ctypes.c_size_t
     L.pauli_last_stats.argtypes = [P(PauliStatsC)]
     L.pauli_last_stats.restype = None
+    L.pauli_read_totals.argtypes = [P(PauliTotalsC), ctypes.c_int]
+    L.pauli_read_totals.restype = None
     L.pauli_order_keys.argtypes = [P(PauliOpC), ctypes.c_void_p, ctypes.c_void_p]
     L.pauli_strings_from_order_keys.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                                 ctypes.c_void_p, ctypes.c_void_p,
                                                 ctypes.c_int64, ctypes.c_void_p]
     for name in EXPORTS:
         if name in ("pauli_strerror", "pauli_last_error", "pauli_profile_read",
-                    "pauli_last_stats"):
+                    "pauli_last_stats", "pauli_read_totals"):
             continue
         if name == "pauli_mlp_num_params":
             L[name].restype = ctypes.c_int64

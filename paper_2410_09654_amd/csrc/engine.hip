@@ -29,6 +29,7 @@ namespace {
 
 thread_local std::string g_last_error;
 thread_local pauli_stats g_stats;
+thread_local pauli_totals g_totals;
 
 // ---------------------------------------------------------------------------
 // Optional kernel timing
@@ -1021,6 +1022,20 @@ int run_call(Arena& ar, pauli_ws* ws, void* stream, Call& c, Ctl* hctl = nullptr
   e.hctl = hctl;
   int rc = dispatch(e, c);
   if (rc == PAULI_EWORKSPACE || ar.short_) return ws_short(ar, ws);
+  if (rc == PAULI_OK || rc == PAULI_BREAKDOWN) {
+    // algorithmic bytes of the pass: inputs read, records written and read,
+    // merged strings written and read, output written, at the record size
+    int64_t inputs = (c.has_comm ? c.O.n : 0);
+    for (int t = 0; t < c.n_terms; t++) inputs += c.T[t].n;
+    const double rb = 16.0 * c.W + (c.f32rec ? 8.0 : 16.0);
+    g_totals.calls++;
+    g_totals.inputs += inputs;
+    g_totals.emitted += g_stats.emitted;
+    g_totals.unique += g_stats.unique;
+    g_totals.output += g_stats.output;
+    g_totals.alg_bytes += rb * (double)(inputs + 2 * g_stats.emitted + 2 * g_stats.unique +
+                                        g_stats.output);
+  }
   return rc;
 }
 
@@ -1304,6 +1319,11 @@ const char* pauli_last_error(void) { return g_last_error.c_str(); }
 
 void pauli_last_stats(pauli_stats* out) {
   if (out) *out = g_stats;
+}
+
+void pauli_read_totals(pauli_totals* out, int reset) {
+  if (out) *out = g_totals;
+  if (reset) memset(&g_totals, 0, sizeof(g_totals));
 }
 
 void pauli_profile_enable(int on) {

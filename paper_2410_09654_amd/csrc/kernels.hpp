@@ -1356,9 +1356,9 @@ __global__ __launch_bounds__(1024) void k_reduce_dd(const double2* part, uint32_
   }
 }
 
-// Lanczos: divide the merged O'_n by b_n (IEEE division), round to FP32 when
-// the result is stored in FP32, then apply the plain-mode filters; dropped
-// strings become exact zeros in place.
+// Lanczos: divide the merged O'_n by b_n (IEEE division), then apply the
+// plain-mode filters on the FP64 quotient (FP32 outputs are rounded when
+// written); dropped strings become exact zeros in place.
 struct ScaleArgs {
   const uint32_t* b_ubase;
   const uint32_t* b_slots;
@@ -1393,8 +1393,11 @@ __global__ __launch_bounds__(256) void k_scale_filter(ScaleArgs a) {
   for (uint32_t i = tid; i < ns; i += 256) {
     double2 v = uc[i];
     v = make_double2(v.x / a.bnorm, v.y / a.bnorm);
-    if (a.round32) v = make_double2(round_to_f32(v.x), round_to_f32(v.y));
-    bool ok = !is_zero(v);
+    // FP32 storage: a string whose stored value would be an exact zero is
+    // dropped; every other decision (cutoff, top-M) is taken on the FP64
+    // quotient, which the output write rounds to FP32
+    bool ok = a.round32 ? !is_zero(make_double2(round_to_f32(v.x), round_to_f32(v.y)))
+                        : !is_zero(v);
     const Key<W> mk = uk[i];
     if (ok && a.max_len > 0 && key_length<W>(unmix_key<W>(mk)) > a.max_len) ok = false;
     if (ok && a.use_eps && !(weight2(v) >= a.eps2)) ok = false;

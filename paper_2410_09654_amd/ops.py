@@ -571,6 +571,13 @@ def workspace_query(op: int, A: PauliOp | None, B: PauliOp | None, C: PauliOp | 
     return int(nb.value), int(cap.value)
 
 
+def read_totals(reset: bool = False) -> dict:
+    """Totals over every engine pass since the last reset (pauli_read_totals)."""
+    t = _lib.PauliTotalsC()
+    _lib.load().pauli_read_totals(ctypes.byref(t), 1 if reset else 0)
+    return {k: getattr(t, k) for k, _ in _lib.PauliTotalsC._fields_}
+
+
 def last_stats() -> dict:
     """Counters of the last engine pass on this thread (see pauli_stats)."""
     st = _lib.PauliStatsC()

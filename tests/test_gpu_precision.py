@@ -137,3 +137,21 @@ def test_kahan_long_runs_bit_exact(pk, ws, n, k, seed):
                         ws=ws).to_host()
     assert exact_fraction(got, f32(want)) == 1.0
     assert got.as_dict()[z1] == complex(0.0, float(np.float32(wv)))
+
+
+def test_lanczos_f32k_cut_on_fp64_quotient_gpu(pk, ws):
+    """The FP32 Lanczos step decides the top-M cut on the FP64 quotient: of
+    two quotients that tie in FP32 it keeps the larger FP64 one, as the
+    oracle does (M = 1)."""
+    import math as _m
+    f = np.float32
+    ca, cb, c3 = float(np.nextafter(f(1.0), f(0))), 1.0, float(f(0.010598019696772099))
+    H = wl.from_terms(4, [(1.0, [("X", 1)])])
+    O = wl.from_terms(4, [(ca, [("Z", 1), ("Z", 2)]), (cb, [("Z", 1), ("Z", 3)]),
+                          (c3, [("Z", 1), ("Z", 4)])])
+    b = _m.sqrt(4 * ca * ca + 4 * cb * cb + 4 * c3 * c3)
+    assert float(f(2 * ca / b)) == float(f(2 * cb / b))
+    want, _, _ = oracle.lanczos_step(H, None, O, 0.0, oracle.Trunc(max_strings=1), oracle.F32K)
+    got, _, _ = pk.lanczos_step(uph(pk, H), None, pk.PauliOp.from_host(O, dtype=C64K, ws=ws),
+                                0.0, pk.Trunc(max_strings=1), ws=ws)
+    assert got.to_host().as_dict() == want.as_dict()

@@ -743,6 +743,32 @@ def test_kahan_fold_hand_derived():
     assert exact == complex(0.0, -1.0 + 2.0**-20)
 
 
+def f32_tie_case():
+    """A Lanczos step whose two largest quotients tie in FP32 but not in FP64:
+    [X_1, c Z_1 Z_j] = -2i c Y_1 Z_j with c = 1 - 2^-24 (j = 2), 1 (j = 3)
+    and a small third string (j = 4) that sets b_1."""
+    f = np.float32
+    ca, cb, c3 = float(np.nextafter(f(1.0), f(0))), 1.0, float(f(0.010598019696772099))
+    n = 4
+    H = wl.from_terms(n, [(1.0, [("X", 1)])])
+    O = wl.from_terms(n, [(ca, [("Z", 1), ("Z", 2)]), (cb, [("Z", 1), ("Z", 3)]),
+                          (c3, [("Z", 1), ("Z", 4)])])
+    b = math.sqrt(4 * ca * ca + 4 * cb * cb + 4 * c3 * c3)
+    return H, O, 2 * ca / b, 2 * cb / b
+
+
+def test_f32k_lanczos_cut_decided_on_fp64_quotient():
+    """FP32 mode keeps the string with the larger FP64 quotient when the two
+    quotients round to the same FP32 value (M = 1): the cut is taken before
+    the values are rounded for storage.  Rounding first would tie them and
+    keep Y_1 Z_2, the smaller key."""
+    H, O, qa, qb = f32_tie_case()
+    assert qa < qb and float(np.float32(qa)) == float(np.float32(qb))
+    got, _, _ = oracle.lanczos_step(H, None, O, 0.0, oracle.Trunc(max_strings=1), oracle.F32K)
+    y1z3 = wl.string_bits(4, [("Y", 1), ("Z", 3)])
+    assert got.as_dict() == {tuple(y1z3[0]) + tuple(y1z3[1]): complex(0.0, -float(np.float32(qb)))}
+
+
 def test_f32k_lanczos_within_split_tolerance():
     H, O0, steps = wl.config_lanczos_small()
     b64 = oracle.lanczos(H, O0, steps, prec=oracle.F64)
