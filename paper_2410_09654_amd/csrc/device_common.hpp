@@ -26,6 +26,14 @@ constexpr int MERGE_CAP = 1984;         // max records of one merge bucket (LDS:
 template <int W>
 constexpr int merge_cap() { return W == 1 ? MERGE_CAP : 1344; }
 constexpr int MERGE_THREADS = 1024;   // 16 waves; two merge blocks per CU (8 waves/SIMD)
+// Small-bucket merge: 512 threads and an LDS footprint of at most 53 KiB
+// (keys, values and source ids per record plus the 8 KiB digit table), so
+// three blocks share a CU; larger buckets go to the full-size merge.
+constexpr int MERGE_SMALL_THREADS = 512;
+template <int W, bool F32>
+constexpr int small_merge_cap() {
+  return ((53 * 1024 - 9 * 1024) / (16 * W + (F32 ? 8 : 16) + 4)) & ~63;
+}
 constexpr int DIGIT_BITS = 11;          // in-bucket counting-sort digit
 constexpr int NDIGITS = 1 << DIGIT_BITS;
 constexpr int EMIT_THREADS = 1024;

@@ -290,6 +290,7 @@ struct Bufs1 {
   uint32_t* histL[2] = {nullptr, nullptr};
   uint32_t *hsum = nullptr, *h0sum = nullptr;
   unsigned long long* psum = nullptr;
+  uint32_t* defer = nullptr;  // buckets left to the full-size merge (per pass)
 };
 template <int W>
 void take_bufs1(Arena& ar, bool comm, int64_t nH, int64_t n_keep, int rows, Bufs1<W>& b) {
@@ -310,6 +311,7 @@ void take_bufs1(Arena& ar, bool comm, int64_t nH, int64_t n_keep, int rows, Bufs
   b.hsum = (uint32_t*)ar.take(SEL_BINS * 4);
   b.h0sum = (uint32_t*)ar.take(SEL0_BINS * 4);
   b.psum = (unsigned long long*)ar.take(PLAN_PARTS * 4 * 8);
+  b.defer = (uint32_t*)ar.take(NBINS_MP * 4);
 }
 
 // scratch taken after the count pass: records (and their partitions),
@@ -613,6 +615,7 @@ int Engine::run(Call& c) {
   ma.hist0 = hist0;
   ma.norm_part = norm_part;
   ma.ctl = dctl;
+  ma.defer = nullptr;
 
   ea.recs = recs;
   ea.rsrc_wide = rsrc_wide;
@@ -724,7 +727,14 @@ int Engine::run(Call& c) {
       ma.u_off = u_off;
       ma.bucket_off = nbk;
       const uint32_t nb_pass = (uint32_t)((1u << nbl) >> g_log);
-      LAUNCH("k_merge", (k_merge<W, F32>), nb_pass, MERGE_THREADS, ma);
+      // buckets up to the small variant's capacity run three to a CU; the
+      // full-size merge takes the rest from the deferral list
+      constexpr int SCAP = small_merge_cap<W, F32>();
+      ma.defer = b1.defer;
+      LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, true>), nb_pass,
+             MERGE_SMALL_THREADS, ma);
+      LAUNCH("k_merge", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), false>),
+             std::min<uint32_t>(nb_pass, 512), MERGE_THREADS, ma);
       nbk += nb_pass;
       u_off += pe;
     }

@@ -56,6 +56,7 @@ struct Ctl {
   unsigned int deep;             // the device select stopped: the host finishes it
   unsigned int sel_d0, sel_d1;   // threshold digits 0 and 1
   unsigned long long part_total; // records in all partitions (several-pass calls)
+  unsigned int ndefer;           // buckets deferred to the full-size merge (this pass)
 };
 
 struct EmitArgs {
@@ -670,6 +671,7 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   if (t == 0) {
     bin_base[NB] = (uint32_t)total;
     ctl->pe_total = total;
+    ctl->ndefer = 0u;
     if (total > 0xFFFFFFFFull) ctl->overflow |= 2u;
     for (int lg = 0; lg < 5; lg++) {
       unsigned int m = 0;
@@ -711,6 +713,7 @@ struct MergeArgs {
   uint32_t* b_unique;
   uint32_t* hist0;
   double2* norm_part;
+  uint32_t* defer;  // buckets above the small variant's capacity (nullptr: none deferred)
   Ctl* ctl;
 };
 
@@ -747,16 +750,15 @@ DEV uint64_t key_window(const Key<W>& m, int shift) {
 // (mixed key, source id) comparison, used when two distinct keys of a group
 // share their 32 sort bits.  On entry mk/sx/sv hold the n records grouped by
 // digit (ascending); on return they are in (key, source id) order.
-template <int W, bool F32>
+template <int W, bool F32, int THREADS, int CAP>
 DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, int shift) {
-  constexpr int CAP = merge_cap<W>();
-  constexpr int PER = (CAP + MERGE_THREADS - 1) / MERGE_THREADS;
+  constexpr int PER = (CAP + THREADS - 1) / THREADS;
   Key<W> k[PER];
   uint32_t x[PER], pos[PER];
   typename std::conditional<F32, float, double>::type vx[PER], vy[PER];
 #pragma unroll
   for (int q = 0; q < PER; q++) {
-    const uint32_t p = threadIdx.x + q * MERGE_THREADS;
+    const uint32_t p = threadIdx.x + q * THREADS;
     pos[q] = p;
     if (p < n) {
       k[q] = mk[p];
@@ -788,7 +790,7 @@ DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, in
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; q++) {
-    const uint32_t p = threadIdx.x + q * MERGE_THREADS;
+    const uint32_t p = threadIdx.x + q * THREADS;
     if (p < n) {
       mk[pos[q]] = k[q];
       sx[pos[q]] = x[q];
@@ -799,13 +801,16 @@ DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, in
   __syncthreads();
 }
 
-template <int W, bool F32>
-__global__ __launch_bounds__(MERGE_THREADS)
-__attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
+// THREADS threads merge one bucket of at most CAP records.  SMALL: the
+// small-bucket variant (512 threads, three blocks per CU by LDS) defers a
+// bucket above its CAP to the list a.defer; the full-size variant then merges
+// the listed buckets (a.defer set) or every bucket of the grid (a.defer null).
+template <int W, bool F32, int THREADS, int CAP, bool SMALL>
+__global__ __launch_bounds__(THREADS)
+__attribute__((amdgpu_waves_per_eu(SMALL ? 6 : 8))) void k_merge(MergeArgs a) {
   using V = RecV<F32>;
-  constexpr int CAP = merge_cap<W>();
-  constexpr int PER = (CAP + MERGE_THREADS - 1) / MERGE_THREADS;
-  constexpr int DPT = NDIGITS / MERGE_THREADS;
+  constexpr int PER = (CAP + THREADS - 1) / THREADS;
+  constexpr int DPT = NDIGITS / THREADS;
   static_assert(SEL0_BINS == 2 * NDIGITS,
                 "digit counts and the |c|^2 histogram (16-bit counters, two per word) share LDS");
   // Sort: a counting sort on the DIGIT_BITS key bits after the bucket bits,
@@ -825,7 +830,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   __shared__ uint32_t s_pk;
   __shared__ uint32_t dh[NDIGITS];
   uint32_t* const h0 = dh;
-  __shared__ uint32_t scan_tmp[MERGE_THREADS / 64 + 1];
+  __shared__ uint32_t scan_tmp[THREADS / 64 + 1];
   __shared__ int s_gk[MAX_GROUPS], s_ak[MAX_GROUPS];
   __shared__ double2 s_al[MAX_GROUPS];
   __shared__ uint32_t sbb[17];
@@ -833,13 +838,17 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   __shared__ uint64_t hmask[NHW];  // bit p: sorted position p starts a run of equal keys
 
   const int tid = threadIdx.x;
-  const uint32_t j = blockIdx.x;
+  auto bucket = [&](const uint32_t j) {
   const uint32_t gb = a.bucket_off + j;
   const uint32_t b0 = a.bin_base[j << a.g_log];
   const uint32_t b1 = a.bin_base[(j + 1) << a.g_log];
   const uint32_t n = b1 - b0;
   const unsigned long long ub = a.u_off + b0;
   if (n > (uint32_t)CAP) {
+    if (SMALL) {  // left to the full-size variant
+      if (tid == 0) a.defer[atomicAdd(&a.ctl->ndefer, 1u)] = j;
+      return;
+    }
     if (tid == 0) {
       atomicOr(&a.ctl->overflow, 1u);
       a.b_ubase[gb] = (uint32_t)ub;
@@ -850,7 +859,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
     }
     return;
   }
-  for (int i = tid; i < NDIGITS; i += MERGE_THREADS) dh[i] = 0u;
+  for (int i = tid; i < NDIGITS; i += THREADS) dh[i] = 0u;
   if (tid < MAX_GROUPS) {
     s_gk[tid] = a.gkind[tid];
     s_ak[tid] = a.alpha_kind[tid];
@@ -887,7 +896,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   auto sort_word = [&](int k) -> uint64_t { return ((uint64_t)swl[k] << 32) | rsx[k]; };
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const uint32_t i = tid + k * MERGE_THREADS;
+    const uint32_t i = tid + k * THREADS;
     dig[k] = 0;
     rnk[k] = 0;
     rsx[k] = 0;
@@ -930,7 +939,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   // sort words in digit-group order
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const uint32_t i = tid + k * MERGE_THREADS;
+    const uint32_t i = tid + k * THREADS;
     if (i < n) swd[dh[dig[k]] + rnk[k]] = sort_word(k);
   }
   __syncthreads();
@@ -939,7 +948,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   uint32_t fpos[PER];
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const uint32_t i = tid + k * MERGE_THREADS;
+    const uint32_t i = tid + k * THREADS;
     fpos[k] = 0;
     if (i < n) {
       const uint32_t s0 = dh[dig[k]];
@@ -966,10 +975,10 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   // keys, sources and values in sorted order; the digit counts become the
   // level-0 |c|^2 histogram (16-bit counters, two per word)
   if (a.mode == M_PLAIN)
-    for (int i = tid; i < NDIGITS; i += MERGE_THREADS) h0[i] = 0u;
+    for (int i = tid; i < NDIGITS; i += THREADS) h0[i] = 0u;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
-    const uint32_t i = tid + k * MERGE_THREADS;
+    const uint32_t i = tid + k * THREADS;
     if (i < n) {
       if constexpr (HOLD_KEY) {
         Key<W> m;
@@ -1081,10 +1090,10 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   Key<W>* uk = reinterpret_cast<Key<W>*>(a.uk) + ub;
   double2* uc = a.uc + ub;
   uint32_t kc = 0, nzu = 0;
-  const uint32_t nround = (n + MERGE_THREADS - 1) / MERGE_THREADS;
+  const uint32_t nround = (n + THREADS - 1) / THREADS;
   const uint32_t nwords = (n + 63) / 64;
   for (uint32_t r = 0; r < nround; r++) {
-    const uint32_t p = r * MERGE_THREADS + tid;
+    const uint32_t p = r * THREADS + tid;
     bool head = false;
     if (p < n) {
       head = p == 0;
@@ -1101,9 +1110,9 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   __syncthreads();
   if (s_collide) {
     // rare: distinct keys with equal sort bits; rank again by full keys
-    merge_full_rank<W, F32>(mk, sx, sv, n, a.digit_shift);
+    merge_full_rank<W, F32, THREADS, CAP>(mk, sx, sv, n, a.digit_shift);
     for (uint32_t r = 0; r < nround; r++) {
-      const uint32_t p = r * MERGE_THREADS + tid;
+      const uint32_t p = r * THREADS + tid;
       const bool head = p < n && (p == 0 || !key_eq<W>(mk[p - 1], mk[p]));
       const uint64_t m = __ballot(head);
       if ((tid & 63) == 0 && (p >> 6) < (uint32_t)NHW) hmask[p >> 6] = m;
@@ -1115,8 +1124,8 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   // folds the runs that start there (a run may reach into the next threads'
   // positions), applies the filters (plain mode), and one block scan places
   // every survivor in sorted order.
-  static_assert(PER * MERGE_THREADS >= CAP, "every position has an owner");
-  const uint32_t per = (n + MERGE_THREADS - 1) / MERGE_THREADS;
+  static_assert(PER * THREADS >= CAP, "every position has an owner");
+  const uint32_t per = (n + THREADS - 1) / THREADS;
   double2 fv[PER];
   uint32_t smask = 0;
 #pragma unroll
@@ -1186,7 +1195,7 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
   if (a.mode == M_PLAIN) {
     // word i of the LDS histogram holds bins 2i (low half) and 2i + 1
     uint32_t* hrep = a.hist0 + (size_t)(j % HREP) * SEL0_BINS;
-    for (int i = tid; i < NDIGITS; i += MERGE_THREADS) {
+    for (int i = tid; i < NDIGITS; i += THREADS) {
       const uint32_t w = h0[i];
       if (w & 0xFFFFu) atomicAdd(&hrep[2 * i], w & 0xFFFFu);
       if (w >> 16) atomicAdd(&hrep[2 * i + 1], w >> 16);
@@ -1198,6 +1207,16 @@ __attribute__((amdgpu_waves_per_eu(8))) void k_merge(MergeArgs a) {
     a.b_surv[gb] = tot_cnt;
     a.b_keep[gb] = tot_kc;
     a.b_unique[gb] = tot_nzu;
+  }
+  };
+  if (SMALL || !a.defer) {
+    bucket(blockIdx.x);
+  } else {
+    const uint32_t nd = *reinterpret_cast<volatile unsigned int*>(&a.ctl->ndefer);
+    for (uint32_t it = blockIdx.x; it < nd; it += gridDim.x) {
+      bucket(a.defer[it]);
+      __syncthreads();  // the next bucket reuses the shared arrays
+    }
   }
 }
 
