@@ -339,6 +339,22 @@ int pauli_mlp_loss_grad(const pauli_mlp *net, const float *x, const float *targe
 /* One Adam step (step index t >= 1) from net->grads; refreshes params_bf16. */
 int pauli_mlp_adam(const pauli_mlp *net, double lr, double beta1, double beta2, double eps,
                    int64_t t, void *stream);
+/* Minibatch training with the fused step kernels: for every epoch e and
+ * minibatch k (rows order[e n + k batch ...], batch rows, the last one of an
+ * epoch shorter when batch does not divide n), one kernel runs the forward
+ * pass, the masked MSE and the backward pass of 32 rows per block with the
+ * activations in LDS and every product on the matrix cores (the BF16
+ * operands and FP32 epilogues of pauli_mlp_loss_grad), a second sums the
+ * blocks' gradient shares in block order and takes the Adam step (step
+ * index t0 + 1, t0 + 2, ...).  x, t, mask: device [n][16]; order: device
+ * int32 [epochs][n], each a permutation of 0..n-1 (not checked); losses:
+ * device double [epochs][ceil(n / batch)] receives every minibatch's loss;
+ * net->grads holds the last minibatch's gradient.  1 <= batch <= 4096.
+ * Synchronous at return. */
+int pauli_mlp_train(const pauli_mlp *net, const float *x, const float *t, const float *mask,
+                    int64_t n, const int32_t *order, int64_t epochs, int32_t batch, double lr,
+                    double beta1, double beta2, double eps, int64_t t0, double *losses,
+                    pauli_ws *ws, void *stream);
 /* C[M][N] (fp32) = A(M x K) B(K x N) with BF16 operands on the matrix cores;
  * A(m,k) = transA ? A[k*lda + m] : A[m*lda + k], B(k,n) = transB ? B[n*ldb + k]
  * : B[k*ldb + n]; M and N multiples of 16. */

@@ -25,7 +25,7 @@ EXPORTS = ["pauli_commutator", "pauli_multiply", "pauli_trace", "pauli_add", "pa
            "pauli_strerror", "pauli_last_error", "pauli_profile_enable", "pauli_profile_only", "pauli_profile_read",
            "pauli_last_stats", "pauli_order_keys", "pauli_strings_from_order_keys",
            "pauli_mlp_num_params", "pauli_mlp_sync", "pauli_mlp_forward",
-           "pauli_mlp_loss_grad", "pauli_mlp_adam", "pauli_gemm_bf16"]
+           "pauli_mlp_loss_grad", "pauli_mlp_adam", "pauli_gemm_bf16", "pauli_mlp_train"]
 
 
 class PauliOpC(ctypes.Structure):

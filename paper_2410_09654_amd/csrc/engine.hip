@@ -2243,6 +2243,53 @@ int pauli_mlp_loss_grad(const pauli_mlp* net, const float* x, const float* t, co
   return PAULI_OK;
 }
 
+int pauli_mlp_train(const pauli_mlp* net, const float* x, const float* t, const float* mask,
+                    int64_t n, const int32_t* order, int64_t epochs, int32_t batch, double lr,
+                    double b1, double b2, double eps, int64_t t0, double* losses, pauli_ws* ws,
+                    void* stream_) {
+  using namespace mlp;
+  hipStream_t stream = (hipStream_t)stream_;
+  TRY(mlp_check(net));
+  if (!ws || !x || !t || !mask || !order || !losses || n <= 0 || epochs < 0 || batch <= 0 ||
+      batch > 4096 || t0 < 0 || !net->grads || !net->adam_m || !net->adam_v)
+    return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  const int nblk_max = (batch + SR - 1) / SR;
+  float* part = (float*)ar.take((size_t)nblk_max * NPARAM * 4);
+  double* lpart = (double*)ar.take((size_t)nblk_max * 16);
+  if (ar.short_) return ws_short(ar, ws);
+  const int64_t spe = (n + batch - 1) / batch;  // minibatches per epoch
+  int64_t step = t0;
+  for (int64_t e = 0; e < epochs; e++) {
+    for (int64_t k = 0; k < spe; k++) {
+      const int64_t s0 = k * batch;
+      const int rows = (int)std::min<int64_t>(batch, n - s0);
+      const int nblk = (rows + SR - 1) / SR;
+      StepArgs sa;
+      sa.params = net->params;
+      sa.pb = net->params_bf16;
+      sa.X = x;
+      sa.T = t;
+      sa.Mk = mask;
+      sa.order = order + e * n + s0;
+      sa.rows = rows;
+      sa.part = part;
+      sa.lpart = lpart;
+      LAUNCH("k_mlp_step", k_mlp_step, nblk, 256, sa);
+      step++;
+      const float c1 = (float)(1.0 - std::pow(b1, (double)step));
+      const float c2 = (float)(1.0 - std::pow(b2, (double)step));
+      LAUNCH("k_mlp_reduce_adam", k_mlp_reduce_adam, (NPARAM + 255) / 256, 256, part, nblk,
+             net->grads, net->params, net->adam_m, net->adam_v, net->params_bf16, (float)lr,
+             (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps, c1, c2,
+             lpart, losses + e * spe + k);
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  g_prof.resolve();
+  return PAULI_OK;
+}
+
 int pauli_mlp_adam(const pauli_mlp* net, double lr, double b1, double b2, double eps, int64_t t,
                    void* stream_) {
   hipStream_t stream = (hipStream_t)stream_;

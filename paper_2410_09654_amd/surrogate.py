@@ -53,8 +53,12 @@ def _setup(L):
                                  ctypes.c_double, ctypes.c_double, ctypes.c_int64, vp]
     L.pauli_gemm_bf16.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
                                   vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    d = ctypes.c_double
+    L.pauli_mlp_train.argtypes = [P(PauliMlpC), vp, vp, vp, ctypes.c_int64, vp, ctypes.c_int64,
+                                  ctypes.c_int32, d, d, d, d, ctypes.c_int64, vp,
+                                  P(_lib.PauliWsC), vp]
     for f in ("pauli_mlp_sync", "pauli_mlp_forward", "pauli_mlp_loss_grad", "pauli_mlp_adam",
-              "pauli_gemm_bf16"):
+              "pauli_gemm_bf16", "pauli_mlp_train"):
         L[f].restype = ctypes.c_int
     L._mlp_ready = True
 
@@ -160,13 +164,48 @@ class BnSurrogate:
         _check(lib().pauli_mlp_adam(ctypes.byref(net), lr, beta1, beta2, eps, self.t,
                                     _stream_handle()), "pauli_mlp_adam")
 
-    def train(self, x, t, mask, epochs=200, batch=512, lr=1e-3, seed=0, log_every=0):
-        """Minibatch Adam; returns the per-epoch mean training loss."""
+    @staticmethod
+    def epoch_orders(n, epochs, seed=0):
+        """The minibatch order of every epoch: seeded permutations of 0..n-1."""
         g = torch.Generator(device="cpu").manual_seed(seed)
+        return torch.stack([torch.randperm(n, generator=g) for _ in range(epochs)])
+
+    def train(self, x, t, mask, epochs=200, batch=512, lr=1e-3, seed=0, log_every=0,
+              beta1=0.9, beta2=0.999, eps=1e-8):
+        """Minibatch Adam with the fused step kernels (pauli_mlp_train: one
+        library call for the whole run); returns the per-epoch mean training
+        loss (minibatch losses weighted by their rows)."""
+        L = lib()
+        n = int(x.shape[0])
+        xs = x.to(self.device, torch.float32).contiguous()
+        ts = t.to(self.device, torch.float32).contiguous()
+        ms = mask.to(self.device, torch.float32).contiguous()
+        order = self.epoch_orders(n, epochs, seed).to(self.device, torch.int32).contiguous()
+        spe = (n + batch - 1) // batch
+        losses = torch.zeros(max(epochs * spe, 1), dtype=torch.float64, device=self.device)
+        net = self.c_struct()
+        self._ws_call(lambda wss: L.pauli_mlp_train(
+            ctypes.byref(net), xs.data_ptr(), ts.data_ptr(), ms.data_ptr(), n, order.data_ptr(),
+            epochs, batch, lr, beta1, beta2, eps, self.t, losses.data_ptr(), ctypes.byref(wss),
+            _stream_handle()), "pauli_mlp_train")
+        self.t += epochs * spe
+        rows = np.array([min(batch, n - k * batch) for k in range(spe)], dtype=np.float64)
+        lv = losses.cpu().numpy()[:epochs * spe].reshape(epochs, spe)
+        hist = [float((lv[e] * rows).sum() / n) for e in range(epochs)]
+        if log_every:
+            for e in range(0, epochs, log_every):
+                print(f"epoch {e} loss {hist[e]:.3e}", flush=True)
+        return hist
+
+    def train_layers(self, x, t, mask, epochs=200, batch=512, lr=1e-3, seed=0, log_every=0):
+        """The same minibatch Adam sequenced from Python, one layer-by-layer
+        loss/gradient call and one Adam call per minibatch (same epoch
+        orders as `train`); returns the per-epoch mean training loss."""
         n = x.shape[0]
+        orders = self.epoch_orders(n, epochs, seed)
         hist = []
         for ep in range(epochs):
-            perm = torch.randperm(n, generator=g)
+            perm = orders[ep]
             tot, cnt = 0.0, 0
             for s in range(0, n, batch):
                 idx = perm[s:s + batch].to(x.device)
