@@ -727,14 +727,25 @@ int Engine::run(Call& c) {
       ma.u_off = u_off;
       ma.bucket_off = nbk;
       const uint32_t nb_pass = (uint32_t)((1u << nbl) >> g_log);
-      // buckets up to the small variant's capacity run three to a CU; the
-      // full-size merge takes the rest from the deferral list
+      // Buckets up to the small variant's capacity run three to a CU: all
+      // of them when the largest bucket fits; when most do, the full-size
+      // merge takes the others from a deferral list; else the full-size merge
+      // takes every bucket.
       constexpr int SCAP = small_merge_cap<W, F32>();
+      const unsigned int big = hctl->maxg[g_log];
       ma.defer = b1.defer;
-      LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, true>), nb_pass,
-             MERGE_SMALL_THREADS, ma);
-      LAUNCH("k_merge", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), false>),
-             std::min<uint32_t>(nb_pass, 512), MERGE_THREADS, ma);
+      if (big <= (unsigned int)SCAP) {
+        LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, MERGE_SMALL>),
+               nb_pass, MERGE_SMALL_THREADS, ma);
+      } else if (pe <= (unsigned long long)nb_pass * (SCAP * 7 / 8)) {
+        LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, MERGE_SMALL>),
+               nb_pass, MERGE_SMALL_THREADS, ma);
+        LAUNCH("k_merge_deferred", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), MERGE_LIST>),
+               std::min<uint32_t>(nb_pass, 512), MERGE_THREADS, ma);
+      } else {
+        LAUNCH("k_merge", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), MERGE_GRID>), nb_pass,
+               MERGE_THREADS, ma);
+      }
       nbk += nb_pass;
       u_off += pe;
     }

@@ -801,13 +801,16 @@ DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, in
   __syncthreads();
 }
 
-// THREADS threads merge one bucket of at most CAP records.  SMALL: the
-// small-bucket variant (512 threads, three blocks per CU by LDS) defers a
-// bucket above its CAP to the list a.defer; the full-size variant then merges
-// the listed buckets (a.defer set) or every bucket of the grid (a.defer null).
-template <int W, bool F32, int THREADS, int CAP, bool SMALL>
+// THREADS threads merge one bucket of at most CAP records.  MODE
+// MERGE_GRID: block j merges bucket j; MERGE_SMALL: the same, but a bucket
+// above CAP goes to the list a.defer instead (the small-bucket variant, 512
+// threads, three blocks per CU by LDS); MERGE_LIST: the blocks merge the
+// listed buckets.
+enum MergeKind : int { MERGE_GRID = 0, MERGE_SMALL = 1, MERGE_LIST = 2 };
+template <int W, bool F32, int THREADS, int CAP, int MODE>
 __global__ __launch_bounds__(THREADS)
-__attribute__((amdgpu_waves_per_eu(SMALL ? 6 : 8))) void k_merge(MergeArgs a) {
+__attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(MergeArgs a) {
+  constexpr bool SMALL = MODE == MERGE_SMALL;
   using V = RecV<F32>;
   constexpr int PER = (CAP + THREADS - 1) / THREADS;
   constexpr int DPT = NDIGITS / THREADS;
@@ -1209,7 +1212,7 @@ __attribute__((amdgpu_waves_per_eu(SMALL ? 6 : 8))) void k_merge(MergeArgs a) {
     a.b_unique[gb] = tot_nzu;
   }
   };
-  if (SMALL || !a.defer) {
+  if constexpr (MODE != MERGE_LIST) {
     bucket(blockIdx.x);
   } else {
     const uint32_t nd = *reinterpret_cast<volatile unsigned int*>(&a.ctl->ndefer);
