@@ -76,8 +76,12 @@ def measured_traffic(kernel: str):
     if t.get("source_sha") != kernel_source_sha() or kernel not in t["kernels"]:
         return None
     k = t["kernels"][kernel]
+    cal = t["copy_calibration"]
     return {"fetch_bytes": round(k["fetch_bytes"]), "write_bytes": round(k["write_bytes"]),
-            "total_bytes": round(k["fetch_bytes"] + k["write_bytes"])}
+            "total_bytes": round(k["fetch_bytes"] + k["write_bytes"]),
+            "fetch_factor": round(cal["fetch_factor"], 4), "write_factor": round(cal["write_factor"], 4),
+            "read_bytes_by_request_size": round(k["read_bytes_by_request_size"]),
+            "write_bytes_by_request_size": round(k["write_bytes_by_request_size"])}
 
 
 def host_info(threads_used: int | None = None) -> dict:
