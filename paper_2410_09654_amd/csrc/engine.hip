@@ -167,6 +167,7 @@ struct Arena {
 struct OpV {
   int W = 1;
   int f32 = 0;
+  int canon = 0;  // written by the engine: canonical order known
   int64_t n = 0;
   int64_t cap = 0;
   const uint64_t* x = nullptr;
@@ -246,6 +247,7 @@ int alpha_kind(double2 a) {
 constexpr int64_t COMM_ROWS_MAX = 1024, TERM_ROWS_MAX = (1 << 17) / EMIT_THREADS;
 static_assert(COMM_ROWS_MAX + TERM_ROWS_MAX <= SC_ROWS_MAX, "k_scan_cols covers every count row");
 constexpr int MAX_PASS_BITS = 12;
+constexpr int DIRECT_MAX_F = 22;  // at most 2^22 buckets in a direct merge
 constexpr int PART_NBL = 12;  // at most 2^12 partitions (MAX_PASS_BITS)
 // blocks binning one partition: 1024 (one per CU, LDS-bound, so four
 // rounds) write shorter per-(block, bin) runs and beat 256 and 512
@@ -331,9 +333,9 @@ struct Bufs2 {
 };
 template <int W, bool F32>
 void take_bufs2(Arena& ar, size_t ptot, bool wide, bool partitioned, uint32_t max_buckets,
-                bool want_select, Bufs2& b) {
+                bool want_select, Bufs2& b, bool records = true) {
   const size_t KB = sizeof(Key<W>), RB = sizeof(Rec<W, F32>);
-  b.recs = ar.take(ptot * RB);
+  b.recs = records ? ar.take(ptot * RB) : nullptr;
   b.rsrc_wide = wide ? (uint32_t*)ar.take(ptot * 4) : nullptr;
   // several passes: every record is emitted once into 2^pass_bits partitions
   // (full order keys, source ids aside); each pass bins one partition
@@ -359,6 +361,7 @@ struct Engine {
   hipStream_t stream;
   Ctl* dctl = nullptr;
   Ctl* hctl = nullptr;
+  bool run_emit = false;  // take the emission path even for canonical terms
 
   int read_ctl() {
     HIP_TRY(hipMemcpyAsync(hctl, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
@@ -393,6 +396,7 @@ int Engine::run(Call& c) {
   const size_t KB = sizeof(Key<W>);
   const size_t RB = sizeof(Rec<W, F32>);
   ar->bottom = 0;
+  const size_t top0 = ar->top;
   memset(&g_stats, 0, sizeof(g_stats));
   // translation-symmetric commutator: H = sum_k T_k(H0), H0 listed over its
   // N translations (entry h N + k), then the plain commutator with every
@@ -480,98 +484,342 @@ int Engine::run(Call& c) {
            keep->capacity, n_keep, keep_mk, &dctl->bad_keep);
   }
 
-  EmitArgs ea;
-  memset(&ea, 0, sizeof(ea));
-  ea.Hk = Hk;
-  ea.Hidx = Hidx;
-  ea.hstart = hstart;
-  ea.hspan = hspan;
-  ea.Hc = comm ? (const double2*)c.H.c : nullptr;
-  ea.nH = comm ? (int)c.H.n : 0;
-  ea.has_comm = comm ? 1 : 0;
-  ea.product = c.product ? 1 : 0;
-  ea.ts_n = c.ts;
-  ea.comm_rows = comm_rows;
-  ea.comm_group = (uint32_t)c.comm_group;
-  if (comm) {
-    ea.Ox = c.O.x;
-    ea.Oz = c.O.z;
-    ea.Ocap = c.O.cap;
-    ea.nO = c.O.n;
-    ea.Oc = c.O.c;
-  }
-  ea.n_terms = c.n_terms;
-  ea.term_rows = term_rows;
-  for (int t = 0; t < c.n_terms; t++) {
-    ea.tx[t] = c.T[t].x;
-    ea.tz[t] = c.T[t].z;
-    ea.tcap[t] = c.T[t].cap;
-    ea.tc[t] = c.T[t].c;
-    ea.tf32[t] = c.T[t].f32;
-    ea.tgroup[t] = (uint32_t)c.tgroup[t];
-    ea.tlist[t] = c.tlist[t];
-  }
-  for (int t = 0; t <= c.n_terms; t++) ea.tstart[t] = tstart[t];
-  ea.counts = counts;
-  ea.bin_base = bin_base;
-  ea.max_len = (c.mode == M_PLAIN && tr) ? tr->max_len : 0;
-
-  // 2^nbl hash bins per pass: NBINS_LOG while the call fits one pass,
-  // NBINS_LOG_MP (twice the records per pass) when it needs several
-  int nbl = NBINS_LOG;
-  auto count_pass = [&](int pass_bits, uint32_t pass_id) -> int {
-    ea.pass_bits = pass_bits;
-    ea.pass_id = pass_id;
-    // the first count pass of a merge sequence also clears the level-0 |c|^2 histogram
-    uint32_t* zero = pass_id == 0 ? hist0 : (uint32_t*)nullptr;
-    const uint32_t nzero = pass_id == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
-    if (nbl == NBINS_LOG) {
-      LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG>), rows, EMIT_THREADS, ea);
-      LAUNCH("k_scan_cols", k_scan_cols, NBINS / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl, NBINS);
-      LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG>, 1, 1024, bin_total, bin_base, dctl, zero,
-             nzero);
-    } else {
-      LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);
-      LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl,
-             NBINS_MP);
-      LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
-             nzero);
-    }
-    return read_ctl();
-  };
-  TRY(count_pass(0, 0));
-  if (hctl->bad_keep) return PAULI_EINVAL;
-  if (hctl->overflow & 2u) {
-    g_last_error = "more than 2^32 records in one pass";
-    return PAULI_EINTERNAL;
-  }
-  const unsigned long long pe_all = hctl->pe_total;
-  // passes over disjoint hash ranges keep every bucket within the merge capacity; the
-  // largest bin does not always halve with each extra pass bit (all records
-  // of one string share a bin), so a pass that still overflows restarts the
-  // loop with one more pass bit
-  // the count pass measured every bin exactly
-  int pass_bits = plan_pass_bits<W>(hctl->maxg[0], &nbl);
-  const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
-  const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
-  const uint32_t max_buckets = (uint32_t)(1u << nbl) << table_bits;
-  // ----- records, U, bucket tables, candidate lists -------------------------
-  // source ids fold into the key bits implied by the bin unless an index
-  // needs more than 11 bits (H above 2047 strings, canonicalisation lists)
-  // (translation-symmetric calls carry (H entry, rotation) as the source id)
-  bool wide = comm && (c.H.n > 2047 || c.ts);
-  for (int t = 0; t < c.n_terms; t++) wide = wide || c.tlist[t];
-  const bool partitioned = nbl == NBINS_LOG_MP;
+  // ----- canonical terms: every bucket merged straight from its term runs ---
+  // A linear combination with no commutator, no list term and one group per
+  // term needs no emission when each term is in canonical order: the strings
+  // of a hash bucket (top F bits of the mixed key) are one contiguous run of
+  // every term.  Terms the engine wrote are canonical; the others are checked
+  // on the device, and when one is out of order the merges leave every bucket
+  // empty and the call is redone by emission (run_emit).
+  unsigned long long pe_all = 0;
   const bool want_select = tr && tr->max_strings > 0;
   Bufs2 b2;
-  take_bufs2<W, F32>(*ar, ptot, wide, partitioned, max_buckets, want_select, b2);
-  if (ar->short_) return PAULI_EWORKSPACE;
-  void* recs = b2.recs;
-  uint32_t* rsrc_wide = b2.rsrc_wide;
-  void* precs = b2.precs;
-  uint32_t* psrc = b2.psrc;
-  uint32_t* pbase = b2.pbase;
-  uint32_t* scounts = b2.scounts;
+  MergeArgs ma;
+  uint32_t nbk = 0;  // buckets written so far
+  int npass = 1;
+  auto merge_common = [&]() {
+    memset(&ma, 0, sizeof(ma));
+    for (int g = 0; g < c.n_groups; g++) {
+      ma.alpha[g] = c.groups[g].alpha;
+      ma.alpha_kind[g] = alpha_kind(c.groups[g].alpha);
+      ma.gkind[g] = c.groups[g].kind;
+    }
+    ma.mode = c.mode;
+    ma.single = (c.n_groups == 1 && c.groups[0].kind != G_SUM_KAHAN32) ? 1 : 0;
+    ma.round32 = c.round32 ? 1 : 0;
+    ma.max_len = tr ? tr->max_len : 0;
+    ma.use_eps = (tr && tr->coef_eps > 0.0) ? 1 : 0;
+    ma.eps2 = tr ? tr->coef_eps * tr->coef_eps : 0.0;
+    ma.keep_mk = keep_mk;
+    ma.n_keep = (int)n_keep;
+    ma.uk = b2.uk;
+    ma.uc = b2.uc;
+    ma.b_ubase = b2.b_ubase;
+    ma.b_slots = b2.b_slots;
+    ma.b_surv = b2.b_surv;
+    ma.b_keep = b2.b_keep;
+    ma.b_unique = b2.b_unique;
+    ma.hist0 = hist0;
+    ma.norm_part = b2.norm_part;
+    ma.ctl = dctl;
+    ma.defer = nullptr;
+  };
+  bool direct = !run_emit && !comm && c.n_terms > 0 && !c.ts && !c.product &&
+                nterm_rec < ((int64_t)1 << 31);
+  for (int t = 0; t < c.n_terms && direct; t++) {
+    direct = !c.tlist[t];
+    for (int u = 0; u < t; u++) direct = direct && c.tgroup[u] != c.tgroup[t];
+  }
+  if (direct) {
+    // 2^F buckets of at most 0.6 of the small merge's capacity on average
+    constexpr int SCAP = small_merge_cap<W, F32>();
+    int F = 0;
+    while (F < DIRECT_MAX_F && (double)nterm_rec > std::ldexp(0.6 * SCAP, F)) F++;
+    const uint32_t nb = 1u << F;
+    uint32_t* tbounds = (uint32_t*)ar->take((size_t)c.n_terms * (nb + 1) * 4);
+    take_bufs2<W, F32>(*ar, (size_t)nterm_rec, false, false, nb, want_select, b2, false);
+    if (ar->short_) return PAULI_EWORKSPACE;
+    TermView tv;
+    memset(&tv, 0, sizeof(tv));
+    tv.n_terms = c.n_terms;
+    tv.F = F;
+    tv.bounds = tbounds;
+    for (int t = 0; t < c.n_terms; t++) {
+      const OpV& T = c.T[t];
+      tv.tx[t] = T.x;
+      tv.tz[t] = T.z;
+      tv.tcap[t] = T.cap;
+      tv.tn[t] = T.n;
+      tv.tc[t] = T.c;
+      tv.tf32[t] = T.f32;
+      tv.tgroup[t] = (uint32_t)c.tgroup[t];
+      if (!T.canon && T.n > 1)
+        LAUNCH("k_check_sorted", (k_check_sorted<W>),
+               (int)std::min<int64_t>((T.n + 255) / 256, 4096), 256, T.x, T.z, T.cap, T.n,
+               &dctl->unsorted);
+    }
+    const int64_t nbounds = (int64_t)c.n_terms * (nb + 1);
+    LAUNCH("k_term_bounds", (k_term_bounds<W>), (nbounds + 255) / 256, 256, tv, tbounds);
+    TRY(zero_u32(hist0, (size_t)HREP * SEL0_BINS));
+    merge_common();
+    ma.tv = tv;
+    ma.nbins_log = F;
+    ma.digit_shift = F;
+    ma.defer = b1.defer;
+    // buckets above the small variant's capacity go to the full-size one
+    LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, MERGE_SMALL, true>), nb,
+           MERGE_SMALL_THREADS, ma);
+    LAUNCH("k_merge_deferred",
+           (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), MERGE_LIST, true>),
+           std::min<uint32_t>(nb, 512), MERGE_THREADS, ma);
+    nbk = nb;
+    pe_all = (unsigned long long)nterm_rec;
+  }
+  if (!direct) {
+    EmitArgs ea;
+    memset(&ea, 0, sizeof(ea));
+    ea.Hk = Hk;
+    ea.Hidx = Hidx;
+    ea.hstart = hstart;
+    ea.hspan = hspan;
+    ea.Hc = comm ? (const double2*)c.H.c : nullptr;
+    ea.nH = comm ? (int)c.H.n : 0;
+    ea.has_comm = comm ? 1 : 0;
+    ea.product = c.product ? 1 : 0;
+    ea.ts_n = c.ts;
+    ea.comm_rows = comm_rows;
+    ea.comm_group = (uint32_t)c.comm_group;
+    if (comm) {
+      ea.Ox = c.O.x;
+      ea.Oz = c.O.z;
+      ea.Ocap = c.O.cap;
+      ea.nO = c.O.n;
+      ea.Oc = c.O.c;
+    }
+    ea.n_terms = c.n_terms;
+    ea.term_rows = term_rows;
+    for (int t = 0; t < c.n_terms; t++) {
+      ea.tx[t] = c.T[t].x;
+      ea.tz[t] = c.T[t].z;
+      ea.tcap[t] = c.T[t].cap;
+      ea.tc[t] = c.T[t].c;
+      ea.tf32[t] = c.T[t].f32;
+      ea.tgroup[t] = (uint32_t)c.tgroup[t];
+      ea.tlist[t] = c.tlist[t];
+    }
+    for (int t = 0; t <= c.n_terms; t++) ea.tstart[t] = tstart[t];
+    ea.counts = counts;
+    ea.bin_base = bin_base;
+    ea.max_len = (c.mode == M_PLAIN && tr) ? tr->max_len : 0;
+
+    // 2^nbl hash bins per pass: NBINS_LOG while the call fits one pass,
+    // NBINS_LOG_MP (twice the records per pass) when it needs several
+    int nbl = NBINS_LOG;
+    auto count_pass = [&](int pass_bits, uint32_t pass_id) -> int {
+      ea.pass_bits = pass_bits;
+      ea.pass_id = pass_id;
+      // the first count pass of a merge sequence also clears the level-0 |c|^2 histogram
+      uint32_t* zero = pass_id == 0 ? hist0 : (uint32_t*)nullptr;
+      const uint32_t nzero = pass_id == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
+      if (nbl == NBINS_LOG) {
+        LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG>), rows, EMIT_THREADS, ea);
+        LAUNCH("k_scan_cols", k_scan_cols, NBINS / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl, NBINS);
+        LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG>, 1, 1024, bin_total, bin_base, dctl, zero,
+               nzero);
+      } else {
+        LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);
+        LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl,
+               NBINS_MP);
+        LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
+               nzero);
+      }
+      return read_ctl();
+    };
+    TRY(count_pass(0, 0));
+    if (hctl->bad_keep) return PAULI_EINVAL;
+    if (hctl->overflow & 2u) {
+      g_last_error = "more than 2^32 records in one pass";
+      return PAULI_EINTERNAL;
+    }
+    pe_all = hctl->pe_total;
+    // passes over disjoint hash ranges keep every bucket within the merge capacity; the
+    // largest bin does not always halve with each extra pass bit (all records
+    // of one string share a bin), so a pass that still overflows restarts the
+    // loop with one more pass bit
+    // the count pass measured every bin exactly
+    int pass_bits = plan_pass_bits<W>(hctl->maxg[0], &nbl);
+    const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
+    const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
+    const uint32_t max_buckets = (uint32_t)(1u << nbl) << table_bits;
+    // ----- records, U, bucket tables, candidate lists -------------------------
+    // source ids fold into the key bits implied by the bin unless an index
+    // needs more than 11 bits (H above 2047 strings, canonicalisation lists)
+    // (translation-symmetric calls carry (H entry, rotation) as the source id)
+    bool wide = comm && (c.H.n > 2047 || c.ts);
+    for (int t = 0; t < c.n_terms; t++) wide = wide || c.tlist[t];
+    const bool partitioned = nbl == NBINS_LOG_MP;
+    take_bufs2<W, F32>(*ar, ptot, wide, partitioned, max_buckets, want_select, b2);
+    if (ar->short_) return PAULI_EWORKSPACE;
+    void* recs = b2.recs;
+    uint32_t* rsrc_wide = b2.rsrc_wide;
+    void* precs = b2.precs;
+    uint32_t* psrc = b2.psrc;
+    uint32_t* pbase = b2.pbase;
+    uint32_t* scounts = b2.scounts;
+    void* uk = b2.uk;
+    double2* uc = b2.uc;
+    uint32_t* b_ubase = b2.b_ubase;
+    uint32_t* b_slots = b2.b_slots;
+    uint32_t* b_surv = b2.b_surv;
+    uint32_t* b_keep = b2.b_keep;
+    uint32_t* b_unique = b2.b_unique;
+    uint32_t* b_abv = b2.b_abv;
+    uint32_t* b_bcnt = b2.b_bcnt;
+    uint32_t* b_obase = b2.b_obase;
+    double2* norm_part = b2.norm_part;
+    uint32_t* const* cand = b2.cand;
+    uint32_t* const* ccnt = b2.ccnt;
+
+    merge_common();
+    ma.bin_base = bin_base;
+    ma.recs = recs;
+    ma.rsrc_wide = rsrc_wide;
+    ma.wide = wide ? 1 : 0;
+
+    ea.recs = recs;
+    ea.rsrc_wide = rsrc_wide;
+    ea.wide = wide ? 1 : 0;
+    nbk = 0;  // buckets written so far
+    npass = 1 << pass_bits;
+    // the first count pass's prefixes (in `counts`) and bin totals (in
+    // bin_total) serve the first partitioning only
+    bool first_counts = pe_all < 0xFFFFFFFFull;
+    for (bool done = false; !done;) {
+      done = true;
+      nbk = 0;
+      unsigned long long u_off = 0;  // U slots reserved by earlier passes
+      npass = 1 << pass_bits;
+      SplitArgs sp;
+      memset(&sp, 0, sizeof(sp));
+      if (pass_bits > 0) {
+        // emit every record once, into the partitions of its top pass_bits bits
+        ea.part = 1;
+        ea.pass_bits = pass_bits;
+        ea.pass_id = 0;
+        ea.recs = precs;
+        ea.psrc = psrc;
+        ea.bin_base = pbase;
+        if (first_counts && pass_bits <= 10) {
+          // partition prefixes summed from the first count pass's bins, kept
+          // above its rows x NBINS entries: no second pass over the pairs
+          uint32_t* pcounts = counts + (size_t)rows * NBINS;
+          LAUNCH("k_part_from_bins", k_part_from_bins, rows + 1, 1024, counts, rows, pass_bits,
+                 1 << PART_NBL, pcounts, bin_total);
+          ea.counts = pcounts;
+        } else {
+          LAUNCH("k_emit_part_count", (k_emit<W, F32, false, PART_NBL>), rows, EMIT_THREADS, ea);
+          LAUNCH("k_scan_cols", k_scan_cols, (1 << PART_NBL) / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl,
+                 1 << PART_NBL);
+        }
+        LAUNCH("k_scan_part", k_scan_part, 1, 1024, bin_total, npass, pbase, (1 << PART_NBL) + 1,
+               dctl);
+        LAUNCH("k_emit_part_scatter", (k_emit<W, F32, true, PART_NBL>), rows, EMIT_THREADS, ea);
+        ea.counts = counts;
+        first_counts = false;  // bin_total now holds partition, then split, totals
+        ea.part = 0;
+        ea.recs = recs;
+        ea.bin_base = bin_base;
+        sp.precs = precs;
+        sp.psrc = psrc;
+        sp.pbase = pbase;
+        sp.pass_bits = pass_bits;
+        sp.wide = wide ? 1 : 0;
+        sp.counts = scounts;
+        sp.bin_base = bin_base;
+        sp.recs = recs;
+        sp.rsrc_wide = rsrc_wide;
+      }
+      for (int p = 0; p < npass; p++) {
+        if (pass_bits > 0) {
+          // bin partition p: histogram, scans (and the host check below)
+          sp.part = (uint32_t)p;
+          uint32_t* zero = p == 0 ? hist0 : (uint32_t*)nullptr;
+          const uint32_t nzero = p == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
+          LAUNCH("k_split_count", (k_split<W, F32, false, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
+          LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, scounts, SPLIT_ROWS, bin_total,
+                 dctl, NBINS_MP);
+          LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
+                 nzero);
+          TRY(read_ctl());
+        } else if (nbl != NBINS_LOG) {
+          // one pass at NBINS_LOG_MP bins: count again at that bin count; this
+          // overwrites the first count pass's NBINS_LOG-bin prefixes and totals
+          TRY(count_pass(pass_bits, (uint32_t)p));
+          first_counts = false;
+        }
+        if (pass_bits > 0 && p == 0 && hctl->part_total != pe_all) {
+          char msg[160];
+          snprintf(msg, sizeof(msg), "partitions hold %llu records, the count pass %llu",
+                   (unsigned long long)hctl->part_total, pe_all);
+          g_last_error = msg;
+          return PAULI_EINTERNAL;
+        }
+        const unsigned long long pe = hctl->pe_total;
+        if (hctl->maxg[0] > (unsigned int)merge_cap<W>()) {
+          if (pass_bits >= table_bits) {
+            char msg[256];
+            snprintf(msg, sizeof(msg),
+                     "hash bucket above merge capacity: pass %d of %d, largest bin %u, "
+                     "records in pass %llu, records in all passes %llu",
+                     p, npass, hctl->maxg[0], (unsigned long long)pe, pe_all);
+            g_last_error = msg;
+            return PAULI_EINTERNAL;
+          }
+          pass_bits++;
+          done = false;
+          break;
+        }
+        int g_log = 4;
+        while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)merge_cap<W>()) g_log--;
+        if (pe == 0) continue;
+        if (pass_bits > 0)
+          LAUNCH("k_split_scatter", (k_split<W, F32, true, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
+        else if (nbl == NBINS_LOG)
+          LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG>), rows, EMIT_THREADS, ea);
+        else
+          LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);
+        ma.g_log = g_log;
+        ma.nbins_log = nbl;
+        ma.digit_shift = pass_bits + nbl - g_log;
+        ma.pass_bits = pass_bits;
+        ma.pass_id = (uint32_t)p;
+        ma.u_off = u_off;
+        ma.bucket_off = nbk;
+        const uint32_t nb_pass = (uint32_t)((1u << nbl) >> g_log);
+        // Buckets up to the small variant's capacity run three to a CU: all
+        // of them when the largest bucket fits; when most do, the full-size
+        // merge takes the others from a deferral list; else the full-size merge
+        // takes every bucket.
+        constexpr int SCAP = small_merge_cap<W, F32>();
+        const unsigned int big = hctl->maxg[g_log];
+        ma.defer = b1.defer;
+        if (big <= (unsigned int)SCAP) {
+          LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, MERGE_SMALL>),
+                 nb_pass, MERGE_SMALL_THREADS, ma);
+        } else if (pe <= (unsigned long long)nb_pass * (SCAP * 7 / 8)) {
+          LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, MERGE_SMALL>),
+                 nb_pass, MERGE_SMALL_THREADS, ma);
+          LAUNCH("k_merge_deferred", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), MERGE_LIST>),
+                 std::min<uint32_t>(nb_pass, 512), MERGE_THREADS, ma);
+        } else {
+          LAUNCH("k_merge", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), MERGE_GRID>), nb_pass,
+                 MERGE_THREADS, ma);
+        }
+        nbk += nb_pass;
+        u_off += pe;
+      }
+    }
+  }
   void* uk = b2.uk;
   double2* uc = b2.uc;
   uint32_t* b_ubase = b2.b_ubase;
@@ -585,171 +833,6 @@ int Engine::run(Call& c) {
   double2* norm_part = b2.norm_part;
   uint32_t* const* cand = b2.cand;
   uint32_t* const* ccnt = b2.ccnt;
-
-  MergeArgs ma;
-  memset(&ma, 0, sizeof(ma));
-  ma.bin_base = bin_base;
-  ma.recs = recs;
-  ma.rsrc_wide = rsrc_wide;
-  ma.wide = wide ? 1 : 0;
-  for (int g = 0; g < c.n_groups; g++) {
-    ma.alpha[g] = c.groups[g].alpha;
-    ma.alpha_kind[g] = alpha_kind(c.groups[g].alpha);
-    ma.gkind[g] = c.groups[g].kind;
-  }
-  ma.mode = c.mode;
-  ma.single = (c.n_groups == 1 && c.groups[0].kind != G_SUM_KAHAN32) ? 1 : 0;
-  ma.round32 = c.round32 ? 1 : 0;
-  ma.max_len = tr ? tr->max_len : 0;
-  ma.use_eps = (tr && tr->coef_eps > 0.0) ? 1 : 0;
-  ma.eps2 = tr ? tr->coef_eps * tr->coef_eps : 0.0;
-  ma.keep_mk = keep_mk;
-  ma.n_keep = (int)n_keep;
-  ma.uk = uk;
-  ma.uc = uc;
-  ma.b_ubase = b_ubase;
-  ma.b_slots = b_slots;
-  ma.b_surv = b_surv;
-  ma.b_keep = b_keep;
-  ma.b_unique = b_unique;
-  ma.hist0 = hist0;
-  ma.norm_part = norm_part;
-  ma.ctl = dctl;
-  ma.defer = nullptr;
-
-  ea.recs = recs;
-  ea.rsrc_wide = rsrc_wide;
-  ea.wide = wide ? 1 : 0;
-  uint32_t nbk = 0;  // buckets written so far
-  int npass = 1 << pass_bits;
-  // the first count pass's prefixes (in `counts`) and bin totals (in
-  // bin_total) serve the first partitioning only
-  bool first_counts = pe_all < 0xFFFFFFFFull;
-  for (bool done = false; !done;) {
-    done = true;
-    nbk = 0;
-    unsigned long long u_off = 0;  // U slots reserved by earlier passes
-    npass = 1 << pass_bits;
-    SplitArgs sp;
-    memset(&sp, 0, sizeof(sp));
-    if (pass_bits > 0) {
-      // emit every record once, into the partitions of its top pass_bits bits
-      ea.part = 1;
-      ea.pass_bits = pass_bits;
-      ea.pass_id = 0;
-      ea.recs = precs;
-      ea.psrc = psrc;
-      ea.bin_base = pbase;
-      if (first_counts && pass_bits <= 10) {
-        // partition prefixes summed from the first count pass's bins, kept
-        // above its rows x NBINS entries: no second pass over the pairs
-        uint32_t* pcounts = counts + (size_t)rows * NBINS;
-        LAUNCH("k_part_from_bins", k_part_from_bins, rows + 1, 1024, counts, rows, pass_bits,
-               1 << PART_NBL, pcounts, bin_total);
-        ea.counts = pcounts;
-      } else {
-        LAUNCH("k_emit_part_count", (k_emit<W, F32, false, PART_NBL>), rows, EMIT_THREADS, ea);
-        LAUNCH("k_scan_cols", k_scan_cols, (1 << PART_NBL) / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl,
-               1 << PART_NBL);
-      }
-      LAUNCH("k_scan_part", k_scan_part, 1, 1024, bin_total, npass, pbase, (1 << PART_NBL) + 1,
-             dctl);
-      LAUNCH("k_emit_part_scatter", (k_emit<W, F32, true, PART_NBL>), rows, EMIT_THREADS, ea);
-      ea.counts = counts;
-      first_counts = false;  // bin_total now holds partition, then split, totals
-      ea.part = 0;
-      ea.recs = recs;
-      ea.bin_base = bin_base;
-      sp.precs = precs;
-      sp.psrc = psrc;
-      sp.pbase = pbase;
-      sp.pass_bits = pass_bits;
-      sp.wide = wide ? 1 : 0;
-      sp.counts = scounts;
-      sp.bin_base = bin_base;
-      sp.recs = recs;
-      sp.rsrc_wide = rsrc_wide;
-    }
-    for (int p = 0; p < npass; p++) {
-      if (pass_bits > 0) {
-        // bin partition p: histogram, scans (and the host check below)
-        sp.part = (uint32_t)p;
-        uint32_t* zero = p == 0 ? hist0 : (uint32_t*)nullptr;
-        const uint32_t nzero = p == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
-        LAUNCH("k_split_count", (k_split<W, F32, false, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
-        LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, scounts, SPLIT_ROWS, bin_total,
-               dctl, NBINS_MP);
-        LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
-               nzero);
-        TRY(read_ctl());
-      } else if (nbl != NBINS_LOG) {
-        // one pass at NBINS_LOG_MP bins: count again at that bin count; this
-        // overwrites the first count pass's NBINS_LOG-bin prefixes and totals
-        TRY(count_pass(pass_bits, (uint32_t)p));
-        first_counts = false;
-      }
-      if (pass_bits > 0 && p == 0 && hctl->part_total != pe_all) {
-        char msg[160];
-        snprintf(msg, sizeof(msg), "partitions hold %llu records, the count pass %llu",
-                 (unsigned long long)hctl->part_total, pe_all);
-        g_last_error = msg;
-        return PAULI_EINTERNAL;
-      }
-      const unsigned long long pe = hctl->pe_total;
-      if (hctl->maxg[0] > (unsigned int)merge_cap<W>()) {
-        if (pass_bits >= table_bits) {
-          char msg[256];
-          snprintf(msg, sizeof(msg),
-                   "hash bucket above merge capacity: pass %d of %d, largest bin %u, "
-                   "records in pass %llu, records in all passes %llu",
-                   p, npass, hctl->maxg[0], (unsigned long long)pe, pe_all);
-          g_last_error = msg;
-          return PAULI_EINTERNAL;
-        }
-        pass_bits++;
-        done = false;
-        break;
-      }
-      int g_log = 4;
-      while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)merge_cap<W>()) g_log--;
-      if (pe == 0) continue;
-      if (pass_bits > 0)
-        LAUNCH("k_split_scatter", (k_split<W, F32, true, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
-      else if (nbl == NBINS_LOG)
-        LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG>), rows, EMIT_THREADS, ea);
-      else
-        LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);
-      ma.g_log = g_log;
-      ma.nbins_log = nbl;
-      ma.digit_shift = pass_bits + nbl - g_log;
-      ma.pass_bits = pass_bits;
-      ma.pass_id = (uint32_t)p;
-      ma.u_off = u_off;
-      ma.bucket_off = nbk;
-      const uint32_t nb_pass = (uint32_t)((1u << nbl) >> g_log);
-      // Buckets up to the small variant's capacity run three to a CU: all
-      // of them when the largest bucket fits; when most do, the full-size
-      // merge takes the others from a deferral list; else the full-size merge
-      // takes every bucket.
-      constexpr int SCAP = small_merge_cap<W, F32>();
-      const unsigned int big = hctl->maxg[g_log];
-      ma.defer = b1.defer;
-      if (big <= (unsigned int)SCAP) {
-        LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, MERGE_SMALL>),
-               nb_pass, MERGE_SMALL_THREADS, ma);
-      } else if (pe <= (unsigned long long)nb_pass * (SCAP * 7 / 8)) {
-        LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, MERGE_SMALL>),
-               nb_pass, MERGE_SMALL_THREADS, ma);
-        LAUNCH("k_merge_deferred", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), MERGE_LIST>),
-               std::min<uint32_t>(nb_pass, 512), MERGE_THREADS, ma);
-      } else {
-        LAUNCH("k_merge", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), MERGE_GRID>), nb_pass,
-               MERGE_THREADS, ma);
-      }
-      nbk += nb_pass;
-      u_off += pe;
-    }
-  }
   g_stats.emitted = (int64_t)pe_all;
   g_stats.passes = npass;
   g_stats.buckets = (int32_t)nbk;
@@ -779,6 +862,12 @@ int Engine::run(Call& c) {
       LAUNCH("k_norm_bucket", k_norm_bucket, nbk, 256, b_ubase, b_slots, uc, norm_part);
     LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, norm_part, nbk, &dctl->norm_hi);
     TRY(read_ctl());
+    if (direct && hctl->unsorted) {
+      ar->top = top0;
+      run_emit = true;
+      return run<W, F32>(c);
+    }
+    if (direct && hctl->bad_keep) return PAULI_EINVAL;
     if (hctl->overflow) {
       g_last_error = "merge bucket overflow";
       return PAULI_EINTERNAL;
@@ -881,6 +970,7 @@ int Engine::run(Call& c) {
     if (ar->short_) return PAULI_EWORKSPACE;
     c.out.arena_op.W = W;
     c.out.arena_op.f32 = c.out.f32;
+    c.out.arena_op.canon = 1;
     c.out.arena_op.n = 0;
     c.out.arena_op.cap = (int64_t)n;
     c.out.arena_op.x = ox;
@@ -899,6 +989,13 @@ int Engine::run(Call& c) {
   }
   LAUNCH("k_write_out", (k_write_out<W>), nchunk, 256, wa, nbk);
   TRY(read_ctl());
+  if (direct && hctl->unsorted) {
+    // a term out of canonical order: the buckets were left empty; redo by emission
+    ar->top = top0;
+    run_emit = true;
+    return run<W, F32>(c);
+  }
+  if (direct && hctl->bad_keep) return PAULI_EINVAL;
   if (hctl->overflow) {
     g_last_error = "merge bucket overflow";
     return PAULI_EINTERNAL;

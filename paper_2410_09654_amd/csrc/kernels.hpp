@@ -57,6 +57,7 @@ struct Ctl {
   unsigned int sel_d0, sel_d1;   // threshold digits 0 and 1
   unsigned long long part_total; // records in all partitions (several-pass calls)
   unsigned int ndefer;           // buckets deferred to the full-size merge (this pass)
+  unsigned int unsorted;         // a term of a direct merge is not in canonical order
 };
 
 struct EmitArgs {
@@ -681,6 +682,75 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   }
 }
 
+// ---------------------------------------------------------------------------
+// Linear combinations of canonical operators, merged without emission.  A
+// term in canonical order (ascending mixed key, distinct strings) holds the
+// strings of hash bucket b (the top F bits of the mixed key) as one
+// contiguous run, so the merge can read each bucket straight from the terms:
+// k_term_bounds finds the runs, k_check_sorted confirms the order of terms
+// the engine did not write itself.
+// ---------------------------------------------------------------------------
+struct TermView {
+  int n_terms;
+  int F;  // 2^F buckets
+  const uint64_t* tx[MAX_TERMS];
+  const uint64_t* tz[MAX_TERMS];
+  int64_t tcap[MAX_TERMS];
+  int64_t tn[MAX_TERMS];
+  const void* tc[MAX_TERMS];
+  int tf32[MAX_TERMS];
+  uint32_t tgroup[MAX_TERMS];
+  const uint32_t* bounds;  // [n_terms][2^F + 1]: strings of term t in buckets below b
+};
+
+template <int W>
+DEV Key<W> load_raw(const uint64_t* x, const uint64_t* z, int64_t cap, int64_t i) {
+  Key<W> raw;
+#pragma unroll
+  for (int w = 0; w < W; w++) {
+    raw.w[w] = x[(size_t)w * cap + i];
+    raw.w[W + w] = z[(size_t)w * cap + i];
+  }
+  return raw;
+}
+
+// *flag |= 1 when the mixed keys of the n strings do not strictly ascend.
+template <int W>
+__global__ __launch_bounds__(256) void k_check_sorted(const uint64_t* x, const uint64_t* z,
+                                                      int64_t cap, int64_t n, unsigned int* flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x + 1; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const Key<W> a = mix_key<W>(load_raw<W>(x, z, cap, i - 1));
+    const Key<W> b = mix_key<W>(load_raw<W>(x, z, cap, i));
+    bad = bad || key_cmp<W>(a, b) >= 0;
+  }
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+// bounds[t][b], b = 0 .. 2^F: the first string of term t whose bucket is at
+// least b (binary search over the canonical order; one thread per entry).
+template <int W>
+__global__ __launch_bounds__(256) void k_term_bounds(TermView v, uint32_t* bounds) {
+  const int64_t nb1 = ((int64_t)1 << v.F) + 1;
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= nb1 * v.n_terms) return;
+  const int t = (int)(id / nb1);
+  const uint64_t b = (uint64_t)(id - (int64_t)t * nb1);
+  int64_t lo = 0, hi = v.tn[t];
+  if (v.F == 0) {
+    lo = b ? hi : 0;
+  } else {
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      const Key<W> m = mix_key<W>(load_raw<W>(v.tx[t], v.tz[t], v.tcap[t], mid));
+      if ((m.w[0] >> (64 - v.F)) < b) lo = mid + 1;
+      else hi = mid;
+    }
+  }
+  bounds[id] = (uint32_t)lo;
+}
+
 struct MergeArgs {
   const uint32_t* bin_base;
   int nbins_log;  // hash bins of the call: 2^nbins_log per pass
@@ -715,6 +785,7 @@ struct MergeArgs {
   double2* norm_part;
   uint32_t* defer;  // buckets above the small variant's capacity (nullptr: none deferred)
   Ctl* ctl;
+  TermView tv;      // direct merges: the canonical terms and their bucket runs
 };
 
 template <int W>
@@ -807,7 +878,9 @@ DEV void merge_full_rank(Key<W>* mk, uint32_t* sx, RecV<F32>* sv, uint32_t n, in
 // threads, three blocks per CU by LDS); MERGE_LIST: the blocks merge the
 // listed buckets.
 enum MergeKind : int { MERGE_GRID = 0, MERGE_SMALL = 1, MERGE_LIST = 2 };
-template <int W, bool F32, int THREADS, int CAP, int MODE>
+// DIRECT: the records of bucket j are the j-th runs of the canonical terms
+// of a.tv (g_log = 0, no pass bits), read in place; source id = term group.
+template <int W, bool F32, int THREADS, int CAP, int MODE, bool DIRECT = false>
 __global__ __launch_bounds__(THREADS)
 __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(MergeArgs a) {
   constexpr bool SMALL = MODE == MERGE_SMALL;
@@ -843,10 +916,65 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
   const int tid = threadIdx.x;
   auto bucket = [&](const uint32_t j) {
   const uint32_t gb = a.bucket_off + j;
-  const uint32_t b0 = a.bin_base[j << a.g_log];
-  const uint32_t b1 = a.bin_base[(j + 1) << a.g_log];
+  uint32_t b0, b1;
+  // direct merges: start of the bucket's run in each term and the run's
+  // first position in the bucket (tpre, ascending over the terms)
+  uint32_t tst[DIRECT ? MAX_TERMS : 1], tpre[DIRECT ? MAX_TERMS : 1];
+  if constexpr (DIRECT) {
+    const uint32_t stride = (1u << a.tv.F) + 1u;
+    b0 = 0u;
+    b1 = 0u;
+#pragma unroll
+    for (int t = 0; t < MAX_TERMS; t++) {
+      tst[t] = 0u;
+      tpre[t] = 0xFFFFFFFFu;
+      if (t < a.tv.n_terms) {
+        const uint32_t s0 = a.tv.bounds[t * stride + j], s1 = a.tv.bounds[t * stride + j + 1];
+        tst[t] = s0;
+        tpre[t] = b1 - b0;
+        b0 += s0;
+        b1 += s1;
+      }
+    }
+    if (a.ctl->unsorted) b1 = b0;  // the call is redone by emission
+  } else {
+    b0 = a.bin_base[j << a.g_log];
+    b1 = a.bin_base[(j + 1) << a.g_log];
+  }
   const uint32_t n = b1 - b0;
   const unsigned long long ub = a.u_off + b0;
+  // direct merges: term, group and index of bucket position i (the last
+  // term whose run starts at or before i; empty runs are passed over)
+  struct TermPos {
+    int t;
+    int64_t e;
+  };
+  auto term_pos = [&](uint32_t i) -> TermPos {
+    TermPos r{0, 0};
+#pragma unroll
+    for (int t = 0; t < (DIRECT ? MAX_TERMS : 1); t++)
+      if (i >= tpre[t]) {
+        r.t = t;
+        r.e = (int64_t)tst[t] + (int64_t)(i - tpre[t]);
+      }
+    return r;
+  };
+  auto term_key = [&](const TermPos& q) -> Key<W> {
+    return mix_key<W>(load_raw<W>(a.tv.tx[q.t], a.tv.tz[q.t], a.tv.tcap[q.t], q.e));
+  };
+  auto term_val = [&](const TermPos& q) -> V {
+    V v;
+    if (a.tv.tf32[q.t]) {
+      const float2 f = reinterpret_cast<const float2*>(a.tv.tc[q.t])[q.e];
+      v.x = f.x;
+      v.y = f.y;
+    } else {
+      const double2 d = reinterpret_cast<const double2*>(a.tv.tc[q.t])[q.e];
+      v.x = d.x;
+      v.y = d.y;
+    }
+    return v;
+  };
   if (n > (uint32_t)CAP) {
     if (SMALL) {  // left to the full-size variant
       if (tid == 0) a.defer[atomicAdd(&a.ctl->ndefer, 1u)] = j;
@@ -869,7 +997,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
     s_al[tid] = a.alpha[tid];
   }
   const int G = 1 << a.g_log;
-  if (tid <= G) sbb[tid] = a.bin_base[(j << a.g_log) + tid];
+  if (!DIRECT && tid <= G) sbb[tid] = a.bin_base[(j << a.g_log) + tid];
   if (tid == 0) {
     s_collide = 0;
     s_pk = 0u;
@@ -906,16 +1034,23 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
     swl[k] = 0;
     if (i < n) {
       const uint32_t pos = b0 + i;
-      const Key<W> rk = recs[pos].k;
-      const uint32_t small = (uint32_t)(rk.w[0] >> (64 - F));
-      const Key<W> m = order_key(pos, rk);
+      Key<W> m;
+      if constexpr (DIRECT) {
+        const TermPos q = term_pos(i);
+        m = term_key(q);
+        rsx[k] = a.tv.tgroup[q.t] << GROUP_SHIFT;
+      } else {
+        const Key<W> rk = recs[pos].k;
+        const uint32_t small = (uint32_t)(rk.w[0] >> (64 - F));
+        m = order_key(pos, rk);
+        rsx[k] = a.wide ? a.rsrc_wide[pos]
+                        : (((small >> ibits) << GROUP_SHIFT) | (small & ((1u << ibits) - 1u)));
+      }
       if constexpr (HOLD_KEY) {
 #pragma unroll
         for (int q = 0; q < 2 * W; q++) rkw[q][k] = m.w[q];
       }
       const uint64_t win = key_window<W>(m, a.digit_shift);
-      rsx[k] = a.wide ? a.rsrc_wide[pos]
-                      : (((small >> ibits) << GROUP_SHIFT) | (small & ((1u << ibits) - 1u)));
       dig[k] = (uint32_t)(win >> 32);
       swl[k] = (uint32_t)win;
       rnk[k] = atomicAdd(&dh[dig[k]], 1u);
@@ -988,7 +1123,12 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
 #pragma unroll
         for (int q = 0; q < 2 * W; q++) m.w[q] = rkw[q][k];
         mk[fpos[k]] = m;
-        sv[fpos[k]] = recs[b0 + i].v;  // second read (cache)
+        if constexpr (DIRECT) sv[fpos[k]] = term_val(term_pos(i));
+        else sv[fpos[k]] = recs[b0 + i].v;  // second read (cache)
+      } else if constexpr (DIRECT) {
+        const TermPos q = term_pos(i);  // second read (cache)
+        mk[fpos[k]] = term_key(q);
+        sv[fpos[k]] = term_val(q);
       } else {
         const Rec<W, F32> r = recs[b0 + i];  // second read (cache)
         mk[fpos[k]] = order_key(b0 + i, r.k);
@@ -1151,7 +1291,11 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
       }
       if (q > n) q = n;
       double2 v;
-      if (fold(p, q, v)) {
+      // direct merges apply the length cap here (emission applies it to
+      // records before they reach a bucket)
+      const bool too_long = DIRECT && a.mode == M_PLAIN && a.max_len > 0 &&
+                            key_length<W>(unmix_key<W>(mk[p])) > a.max_len;
+      if (!too_long && fold(p, q, v)) {
         nzu++;
         bool surv = true;
         if (a.mode != M_LANCZOS) {
