@@ -322,7 +322,7 @@ struct Bufs2 {
   void* recs = nullptr;
   uint32_t* rsrc_wide = nullptr;
   void* precs = nullptr;
-  uint32_t *psrc = nullptr, *pbase = nullptr, *scounts = nullptr;
+  uint32_t *ptop = nullptr, *psrc = nullptr, *pbase = nullptr, *scounts = nullptr;
   void* uk = nullptr;
   double2* uc = nullptr;
   uint32_t *b_ubase = nullptr, *b_slots = nullptr, *b_surv = nullptr, *b_keep = nullptr;
@@ -338,9 +338,11 @@ void take_bufs2(Arena& ar, size_t ptot, bool wide, bool partitioned, uint32_t ma
   b.recs = records ? ar.take(ptot * RB) : nullptr;
   b.rsrc_wide = wide ? (uint32_t*)ar.take(ptot * 4) : nullptr;
   // several passes: every record is emitted once into 2^pass_bits partitions
-  // (full order keys, source ids aside); each pass bins one partition
+  // (the top 32 bits of its order key aside, and its source id when wide);
+  // each pass bins one partition
   b.precs = partitioned ? ar.take(ptot * RB) : nullptr;
-  b.psrc = partitioned ? (uint32_t*)ar.take(ptot * 4) : nullptr;
+  b.ptop = partitioned ? (uint32_t*)ar.take(ptot * 4) : nullptr;
+  b.psrc = partitioned && wide ? (uint32_t*)ar.take(ptot * 4) : nullptr;
   b.pbase = partitioned ? (uint32_t*)ar.take(((1u << PART_NBL) + 1) * 4) : nullptr;
   b.scounts = partitioned ? (uint32_t*)ar.take((size_t)SPLIT_ROWS * NBINS_MP * 4) : nullptr;
   b.uk = ar.take(ptot * KB);
@@ -663,6 +665,7 @@ int Engine::run(Call& c) {
     void* recs = b2.recs;
     uint32_t* rsrc_wide = b2.rsrc_wide;
     void* precs = b2.precs;
+    uint32_t* ptop = b2.ptop;
     uint32_t* psrc = b2.psrc;
     uint32_t* pbase = b2.pbase;
     uint32_t* scounts = b2.scounts;
@@ -707,7 +710,9 @@ int Engine::run(Call& c) {
         ea.pass_bits = pass_bits;
         ea.pass_id = 0;
         ea.recs = precs;
+        ea.ptop = ptop;
         ea.psrc = psrc;
+        ea.part_F = NBINS_LOG_MP + pass_bits;
         ea.bin_base = pbase;
         if (first_counts && pass_bits <= 10) {
           // partition prefixes summed from the first count pass's bins, kept
@@ -730,6 +735,7 @@ int Engine::run(Call& c) {
         ea.recs = recs;
         ea.bin_base = bin_base;
         sp.precs = precs;
+        sp.ptop = ptop;
         sp.psrc = psrc;
         sp.pbase = pbase;
         sp.pass_bits = pass_bits;

@@ -97,9 +97,13 @@ struct EmitArgs {
   // length cap depends on the key alone, so it can act before the merge
   int max_len;
   // partition mode: the bin is the top pass_bits bits of the order key
-  // (2^pass_bits partitions), records keep their full order key and the
-  // source ids go to psrc
+  // (2^pass_bits partitions); records are written as the binning of a pass
+  // will store them (source id in the top part_F bits of the key), the top
+  // 32 bits of the order key go to ptop, and the source ids to psrc when they
+  // are kept aside (wide)
   int part;
+  int part_F;
+  uint32_t* ptop;
   uint32_t* psrc;
   // binning
   int pass_bits;
@@ -166,11 +170,15 @@ __attribute__((amdgpu_waves_per_eu(W == 1 && NBL <= 14 ? 8 : 4))) void k_emit(Em
       const uint32_t pid = (uint32_t)(mk.w[0] >> (64 - a.pass_bits));
       const uint32_t pos = atomicAdd(&hist[pid], 1u);
       if (SCATTER) {
+        const int PF = a.part_F;
+        a.ptop[pos] = (uint32_t)(mk.w[0] >> 32);
+        const uint64_t small = a.wide ? 0ull : (((uint64_t)group << (PF - 3)) | index);
+        mk.w[0] = (small << (64 - PF)) | (mk.w[0] & (~0ull >> PF));
         Rec<W, F32> r;
         r.k = mk;
         r.v = val;
         recs[pos] = r;
-        a.psrc[pos] = (group << GROUP_SHIFT) | index;
+        if (a.wide) a.psrc[pos] = (group << GROUP_SHIFT) | index;
       }
       return;
     }
@@ -401,13 +409,15 @@ __attribute__((amdgpu_waves_per_eu(W == 1 && NBL <= 14 ? 8 : 4))) void k_emit(Em
 }
 
 // One partition of a several-pass call, binned for the merge: block r of the
-// grid takes the r-th contiguous share of partition `part` (records with
-// full order keys from the partition-mode emission), histograms the NBL key
-// bits after the pass bits (COUNT: into row r of the counts matrix) or writes
-// each record at its bin cursor with the source id folded into the key bits
-// the bin and pass imply (SCATTER), exactly as the emission's scatter does.
+// grid takes the r-th contiguous share of partition `part` (records as the
+// merge reads them, from the partition-mode emission, and the top 32 bits of
+// each order key in ptop), histograms the NBL key bits after the pass bits
+// (COUNT: from ptop alone, into row r of the counts matrix) or copies each
+// record to its bin cursor (SCATTER), with its source id when it is kept
+// aside (wide).
 struct SplitArgs {
   const void* precs;
+  const uint32_t* ptop;
   const uint32_t* psrc;
   const uint32_t* pbase;  // partition starts [2^pass_bits + 1]
   uint32_t part;
@@ -439,34 +449,31 @@ __global__ __launch_bounds__(1024) void k_split(SplitArgs a) {
   static_assert(sizeof(Rec<W, F32>) % 8 == 0, "records are whole 64-bit words");
   const uint64_t* in = reinterpret_cast<const uint64_t*>(a.precs);
   uint64_t* out = reinterpret_cast<uint64_t*>(a.recs);
-  const int F = NBL + a.pass_bits;
   // SB records per thread and step, all loaded before any is binned, so that
-  // each wave keeps SB loads in flight
-  constexpr int SB = 4;
+  // each wave keeps SB loads in flight (COUNT: 4 bytes per record)
+  constexpr int SB = SCATTER ? 4 : 8;
   for (uint32_t i0 = r0 + tid; i0 < r1; i0 += SB * 1024) {
-    uint64_t rw[SB][RW];
-    uint32_t src[SB];
+    uint64_t rw[SCATTER ? SB : 1][RW];
+    uint32_t top[SB], src[SB];
 #pragma unroll
     for (int u = 0; u < SB; u++) {
       const uint32_t i = i0 + u * 1024;
       if (i < r1) {
+        top[u] = a.ptop[i];
+        if constexpr (SCATTER) {
 #pragma unroll
-        for (int q = 0; q < RW; q++) rw[u][q] = in[(size_t)i * RW + q];
-        if (SCATTER) src[u] = a.psrc[i];
+          for (int q = 0; q < RW; q++) rw[u][q] = in[(size_t)i * RW + q];
+          if (a.wide) src[u] = a.psrc[i];
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < SB; u++) {
       const uint32_t i = i0 + u * 1024;
       if (i >= r1) break;
-      const uint32_t bin = (uint32_t)((rw[u][0] << a.pass_bits) >> (64 - NBL));
+      const uint32_t bin = (top[u] << a.pass_bits) >> (32 - NBL);
       const uint32_t pos = atomicAdd(&hist[bin], 1u);
-      if (SCATTER) {
-        const uint64_t small =
-            a.wide ? 0ull
-                   : (((uint64_t)(src[u] >> GROUP_SHIFT) << (F - 3)) |
-                      (src[u] & ((1u << GROUP_SHIFT) - 1u)));
-        rw[u][0] = (small << (64 - F)) | (rw[u][0] & (~0ull >> F));
+      if constexpr (SCATTER) {
 #pragma unroll
         for (int q = 0; q < RW; q++) out[(size_t)pos * RW + q] = rw[u][q];
         if (a.wide) a.rsrc_wide[pos] = src[u];
