@@ -997,6 +997,38 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
     }
     return;
   }
+  const Rec<W, F32>* recs = reinterpret_cast<const Rec<W, F32>*>(a.recs);
+  const int F = a.nbins_log + a.pass_bits;
+  const uint32_t ibits = (uint32_t)(F - 3);
+  // Per record the digit, its rank among the digit's records, the source id
+  // and the 32 sort bits stay in registers, and at W = 1 the order key; the
+  // value (and a wider key) is read a second time, from cache, for the
+  // sorted write, which keeps the kernel spill-free at 8 waves per SIMD.
+  constexpr bool HOLD_KEY = W == 1;
+  uint32_t dig[PER], rnk[PER], rsx[PER], swl[PER];
+  uint64_t rkw[HOLD_KEY ? 2 * W : 1][PER];
+  // one-word keys: the record loads are issued before the shared-memory
+  // set-up, so that their latency overlaps it
+  if constexpr (HOLD_KEY) {
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const uint32_t i = tid + k * THREADS;
+      rsx[k] = 0;
+      if (i < n) {
+        Key<W> m;
+        if constexpr (DIRECT) {
+          const TermPos q = term_pos(i);
+          m = term_key(q);
+          rsx[k] = a.tv.tgroup[q.t] << GROUP_SHIFT;
+        } else {
+          m = recs[b0 + i].k;
+          if (a.wide) rsx[k] = a.rsrc_wide[b0 + i];
+        }
+#pragma unroll
+        for (int q = 0; q < 2 * W; q++) rkw[q][k] = m.w[q];
+      }
+    }
+  }
   for (int i = tid; i < NDIGITS; i += THREADS) dh[i] = 0u;
   if (tid < MAX_GROUPS) {
     s_gk[tid] = a.gkind[tid];
@@ -1011,16 +1043,6 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
   }
   __syncthreads();
 
-  const Rec<W, F32>* recs = reinterpret_cast<const Rec<W, F32>*>(a.recs);
-  const int F = a.nbins_log + a.pass_bits;
-  const uint32_t ibits = (uint32_t)(F - 3);
-  // Per record the digit, its rank among the digit's records, the source id
-  // and the 32 sort bits stay in registers, and at W = 1 the order key; the
-  // value (and a wider key) is read a second time, from cache, for the
-  // sorted write, which keeps the kernel spill-free at 8 waves per SIMD.
-  constexpr bool HOLD_KEY = W == 1;
-  uint32_t dig[PER], rnk[PER], rsx[PER], swl[PER];
-  uint64_t rkw[HOLD_KEY ? 2 * W : 1][PER];
   // the record's order key: the bin bits that the source id displaced restored
   auto order_key = [&](uint32_t pos, const Key<W>& rk) -> Key<W> {
     int kb = 0;
@@ -1037,25 +1059,31 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
     const uint32_t i = tid + k * THREADS;
     dig[k] = 0;
     rnk[k] = 0;
-    rsx[k] = 0;
     swl[k] = 0;
+    if (!HOLD_KEY) rsx[k] = 0;
     if (i < n) {
       const uint32_t pos = b0 + i;
       Key<W> m;
-      if constexpr (DIRECT) {
+      if constexpr (HOLD_KEY) {
+#pragma unroll
+        for (int q = 0; q < 2 * W; q++) m.w[q] = rkw[q][k];
+      } else if constexpr (DIRECT) {
         const TermPos q = term_pos(i);
         m = term_key(q);
         rsx[k] = a.tv.tgroup[q.t] << GROUP_SHIFT;
       } else {
-        const Key<W> rk = recs[pos].k;
-        const uint32_t small = (uint32_t)(rk.w[0] >> (64 - F));
-        m = order_key(pos, rk);
-        rsx[k] = a.wide ? a.rsrc_wide[pos]
-                        : (((small >> ibits) << GROUP_SHIFT) | (small & ((1u << ibits) - 1u)));
+        m = recs[pos].k;
+        if (a.wide) rsx[k] = a.rsrc_wide[pos];
       }
-      if constexpr (HOLD_KEY) {
+      if constexpr (!DIRECT) {
+        // the source id from the key's top bits, then the order key
+        const uint32_t small = (uint32_t)(m.w[0] >> (64 - F));
+        if (!a.wide) rsx[k] = ((small >> ibits) << GROUP_SHIFT) | (small & ((1u << ibits) - 1u));
+        m = order_key(pos, m);
+        if constexpr (HOLD_KEY) {
 #pragma unroll
-        for (int q = 0; q < 2 * W; q++) rkw[q][k] = m.w[q];
+          for (int q = 0; q < 2 * W; q++) rkw[q][k] = m.w[q];
+        }
       }
       const uint64_t win = key_window<W>(m, a.digit_shift);
       dig[k] = (uint32_t)(win >> 32);
