@@ -1270,6 +1270,12 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
   uint32_t kc = 0, nzu = 0;
   const uint32_t nround = (n + THREADS - 1) / THREADS;
   const uint32_t nwords = (n + 63) / 64;
+  // the window (digit and sort bits) as masks of the first two key words:
+  // two keys share it when their XOR has none of the masked bits
+  constexpr int WB = DIGIT_BITS + 32;
+  const int wsh = a.digit_shift;
+  const uint64_t wm0 = wsh + WB <= 64 ? (((1ull << WB) - 1ull) << (64 - wsh - WB)) : (~0ull >> wsh);
+  const uint64_t wm1 = wsh + WB <= 64 ? 0ull : ~(~0ull >> (wsh + WB - 64));
   for (uint32_t r = 0; r < nround; r++) {
     const uint32_t p = r * THREADS + tid;
     bool head = false;
@@ -1278,7 +1284,7 @@ __attribute__((amdgpu_waves_per_eu(MODE == MERGE_SMALL ? 6 : 8))) void k_merge(M
       if (p > 0) {
         const Key<W> k0 = mk[p - 1], k1 = mk[p];
         head = !key_eq<W>(k0, k1);
-        if (head && key_window<W>(k0, a.digit_shift) == key_window<W>(k1, a.digit_shift))
+        if (head && ((k0.w[0] ^ k1.w[0]) & wm0) == 0 && ((k0.w[1] ^ k1.w[1]) & wm1) == 0)
           s_collide = 1;
       }
     }
