@@ -533,10 +533,10 @@ int Engine::run(Call& c) {
     for (int u = 0; u < t; u++) direct = direct && c.tgroup[u] != c.tgroup[t];
   }
   if (direct) {
-    // 2^F buckets of at most 0.6 of the small merge's capacity on average
+    // 2^F buckets of at most 0.85 of the small merge's capacity on average
     constexpr int SCAP = small_merge_cap<W, F32>();
     int F = 0;
-    while (F < DIRECT_MAX_F && (double)nterm_rec > std::ldexp(0.6 * SCAP, F)) F++;
+    while (F < DIRECT_MAX_F && (double)nterm_rec > std::ldexp(0.85 * SCAP, F)) F++;
     const uint32_t nb = 1u << F;
     uint32_t* tbounds = (uint32_t*)ar->take((size_t)c.n_terms * (nb + 1) * 4);
     take_bufs2<W, F32>(*ar, (size_t)nterm_rec, false, false, nb, want_select, b2, false);
