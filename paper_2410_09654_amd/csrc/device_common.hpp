@@ -17,6 +17,7 @@ namespace pauli {
 
 constexpr int NBINS_LOG = 14;
 constexpr int NBINS = 1 << NBINS_LOG;   // hash bins of a call that fits one pass
+constexpr int NBINS_LOG_SMALL = 10;     // hash bins of a call of at most 2^18 records
 constexpr int NBINS_LOG_MP = 15;        // hash bins per pass of a call that needs
 constexpr int NBINS_MP = 1 << NBINS_LOG_MP;  // several (twice the records per pass)
 constexpr int MERGE_CAP = 1984;         // max records of one merge bucket (LDS: two

@@ -615,15 +615,29 @@ int Engine::run(Call& c) {
     ea.max_len = (c.mode == M_PLAIN && tr) ? tr->max_len : 0;
 
     // 2^nbl hash bins per pass: NBINS_LOG while the call fits one pass,
-    // NBINS_LOG_MP (twice the records per pass) when it needs several
+    // NBINS_LOG_MP (twice the records per pass) when it needs several, and
+    // NBINS_LOG_SMALL for calls of at most 2^18 records even if every pair
+    // emits one (the per-call bin tables then cost a sixteenth)
     int nbl = NBINS_LOG;
+    {
+      const unsigned long long bound =
+          (comm ? (unsigned long long)c.H.n * (unsigned long long)c.O.n : 0ull) +
+          (unsigned long long)nterm_rec;
+      if (bound <= (1ull << (NBINS_LOG_SMALL + 8))) nbl = NBINS_LOG_SMALL;
+    }
     auto count_pass = [&](int pass_bits, uint32_t pass_id) -> int {
       ea.pass_bits = pass_bits;
       ea.pass_id = pass_id;
       // the first count pass of a merge sequence also clears the level-0 |c|^2 histogram
       uint32_t* zero = pass_id == 0 ? hist0 : (uint32_t*)nullptr;
       const uint32_t nzero = pass_id == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
-      if (nbl == NBINS_LOG) {
+      if (nbl == NBINS_LOG_SMALL) {
+        constexpr int NBS = 1 << NBINS_LOG_SMALL;
+        LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG_SMALL>), rows, EMIT_THREADS, ea);
+        LAUNCH("k_scan_cols", k_scan_cols, NBS / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl, NBS);
+        LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_SMALL>, 1, scan_bins_threads<NBINS_LOG_SMALL>(),
+               bin_total, bin_base, dctl, zero, nzero);
+      } else if (nbl == NBINS_LOG) {
         LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG>), rows, EMIT_THREADS, ea);
         LAUNCH("k_scan_cols", k_scan_cols, NBINS / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl, NBINS);
         LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG>, 1, 1024, bin_total, bin_base, dctl, zero,
@@ -638,6 +652,11 @@ int Engine::run(Call& c) {
       return read_ctl();
     };
     TRY(count_pass(0, 0));
+    if (nbl == NBINS_LOG_SMALL && hctl->maxg[0] > (unsigned int)merge_cap<W>()) {
+      // a small call whose records crowd one bin: count again over 2^14 bins
+      nbl = NBINS_LOG;
+      TRY(count_pass(0, 0));
+    }
     if (hctl->bad_keep) return PAULI_EINVAL;
     if (hctl->overflow & 2u) {
       g_last_error = "more than 2^32 records in one pass";
@@ -649,7 +668,7 @@ int Engine::run(Call& c) {
     // of one string share a bin), so a pass that still overflows restarts the
     // loop with one more pass bit
     // the count pass measured every bin exactly
-    int pass_bits = plan_pass_bits<W>(hctl->maxg[0], &nbl);
+    int pass_bits = nbl == NBINS_LOG_SMALL ? 0 : plan_pass_bits<W>(hctl->maxg[0], &nbl);
     const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
     const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
     const uint32_t max_buckets = (uint32_t)(1u << nbl) << table_bits;
@@ -657,7 +676,9 @@ int Engine::run(Call& c) {
     // source ids fold into the key bits implied by the bin unless an index
     // needs more than 11 bits (H above 2047 strings, canonicalisation lists)
     // (translation-symmetric calls carry (H entry, rotation) as the source id)
-    bool wide = comm && (c.H.n > 2047 || c.ts);
+    // (7 bits over 2^10 bins)
+    const int64_t max_h = nbl == NBINS_LOG_SMALL ? (1 << (NBINS_LOG_SMALL - 3)) - 1 : 2047;
+    bool wide = comm && (c.H.n > max_h || c.ts);
     for (int t = 0; t < c.n_terms; t++) wide = wide || c.tlist[t];
     const bool partitioned = nbl == NBINS_LOG_MP;
     take_bufs2<W, F32>(*ar, ptot, wide, partitioned, max_buckets, want_select, b2);
@@ -757,7 +778,7 @@ int Engine::run(Call& c) {
           LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
                  nzero);
           TRY(read_ctl());
-        } else if (nbl != NBINS_LOG) {
+        } else if (nbl == NBINS_LOG_MP) {
           // one pass at NBINS_LOG_MP bins: count again at that bin count; this
           // overwrites the first count pass's NBINS_LOG-bin prefixes and totals
           TRY(count_pass(pass_bits, (uint32_t)p));
@@ -790,6 +811,8 @@ int Engine::run(Call& c) {
         if (pe == 0) continue;
         if (pass_bits > 0)
           LAUNCH("k_split_scatter", (k_split<W, F32, true, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
+        else if (nbl == NBINS_LOG_SMALL)
+          LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG_SMALL>), rows, EMIT_THREADS, ea);
         else if (nbl == NBINS_LOG)
           LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG>), rows, EMIT_THREADS, ea);
         else
@@ -1215,7 +1238,9 @@ void dry_call(Arena& ar, const DryCall& d, unsigned long long* pe_out) {
   const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
   const uint32_t max_buckets = (uint32_t)(1u << nbl) << table_bits;
   Bufs2 b2;
-  take_bufs2<W, F32>(ar, (size_t)std::max<unsigned long long>(pe, 1), d.wide || (comm && (nH > 2047 || d.ts)),
+  // source ids aside as the engine decides (7-bit H indices over 2^10 bins)
+  const int64_t max_h = pe <= (1ull << (NBINS_LOG_SMALL + 8)) ? (1 << (NBINS_LOG_SMALL - 3)) - 1 : 2047;
+  take_bufs2<W, F32>(ar, (size_t)std::max<unsigned long long>(pe, 1), d.wide || (comm && (nH > max_h || d.ts)),
                      nbl == NBINS_LOG_MP, max_buckets, d.select, b2);
   if (d.out_arena >= 0) {
     const size_t n = (size_t)std::max<int64_t>(d.out_arena, 1);

@@ -589,23 +589,27 @@ __global__ __launch_bounds__(SC_COLS * SC_NSEG) void k_scan_cols(uint32_t* count
   }
 }
 
-// Exclusive scan of the bin totals (one block of 1024 threads; thread t owns
-// the NB/1024 consecutive bins from t NB/1024, read and written as 16-byte
-// vectors) and the largest total over aligned groups of 1, 2, 4, 8, 16 bins.
-// Also clears `zero` (nzero words) when given: the level-0 |c|^2 histogram of the
-// merges that follow this count pass.
+// Exclusive scan of the bin totals (one block of scan_bins_threads<NBL>()
+// threads; thread t owns the BPT >= 16 consecutive bins from t BPT, read and
+// written as 16-byte vectors) and the largest total over aligned groups of
+// 1, 2, 4, 8, 16 bins.  Also clears `zero` (nzero words) when given: the
+// level-0 |c|^2 histogram of the merges that follow this count pass.
+template <int NBL>
+constexpr int scan_bins_threads() { return (1 << NBL) / 16 < 1024 ? (1 << NBL) / 16 : 1024; }
 template <int NBL>
 __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, uint32_t* bin_base,
                                                     Ctl* ctl, uint32_t* zero, uint32_t nzero) {
   constexpr int NB = 1 << NBL;
-  constexpr int BPT = NB / 1024;
-  static_assert(BPT >= 16 && BPT * 1024 == NB && BPT % 4 == 0,
-                "k_scan_bins covers the bins with 1024 threads");
+  constexpr int TH = scan_bins_threads<NBL>();
+  constexpr int NWV = TH / 64;
+  constexpr int BPT = NB / TH;
+  static_assert(BPT >= 16 && BPT * TH == NB && BPT % 4 == 0 && NWV >= 1 && NWV <= 16,
+                "k_scan_bins covers the bins with TH threads");
   __shared__ unsigned long long tmp[1024 / 64 + 1];
   __shared__ unsigned int gmax[16][5];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   // nzero is a multiple of 4 and `zero` 16-byte aligned (histogram replicas)
-  for (uint32_t i = t; i < nzero / 4; i += 1024)
+  for (uint32_t i = t; i < nzero / 4; i += TH)
     reinterpret_cast<uint4*>(zero)[i] = make_uint4(0u, 0u, 0u, 0u);
   uint32_t v[BPT];
   const uint4* src = reinterpret_cast<const uint4*>(bin_total) + (size_t)t * (BPT / 4);
@@ -653,14 +657,14 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   }
   if (lane == 63) tmp[wv] = x;
   __syncthreads();
-  unsigned long long w = lane < 16 ? tmp[lane] : 0ull;
+  unsigned long long w = lane < NWV ? tmp[lane] : 0ull;
 #pragma unroll
   for (int d = 1; d < 16; d <<= 1) {
     unsigned long long y = __shfl_up(w, d, 64);
     if (lane >= d) w += y;
   }
   const unsigned long long before = wv > 0 ? __shfl(w, wv - 1, 64) : 0ull;
-  const unsigned long long total = __shfl(w, 15, 64);
+  const unsigned long long total = __shfl(w, NWV - 1, 64);
   unsigned long long pre = before + x - s;
   uint4* dst = reinterpret_cast<uint4*>(bin_base) + (size_t)t * (BPT / 4);
 #pragma unroll
@@ -683,7 +687,7 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
     if (total > 0xFFFFFFFFull) ctl->overflow |= 2u;
     for (int lg = 0; lg < 5; lg++) {
       unsigned int m = 0;
-      for (int q = 0; q < 16; q++) m = gmax[q][lg] > m ? gmax[q][lg] : m;
+      for (int q = 0; q < NWV; q++) m = gmax[q][lg] > m ? gmax[q][lg] : m;
       ctl->maxg[lg] = m;
     }
   }
