@@ -492,7 +492,8 @@ int Engine::run(Call& c) {
   // of a hash bucket (top F bits of the mixed key) are one contiguous run of
   // every term.  Terms the engine wrote are canonical; the others are checked
   // on the device, and when one is out of order the merges leave every bucket
-  // empty and the call is redone by emission (run_emit).
+  // empty and the call is redone by emission (run_emit), as it is when strings
+  // crowd one bucket beyond the merge's capacity.
   unsigned long long pe_all = 0;
   const bool want_select = tr && tr->max_strings > 0;
   Bufs2 b2;
@@ -891,7 +892,7 @@ int Engine::run(Call& c) {
       LAUNCH("k_norm_bucket", k_norm_bucket, nbk, 256, b_ubase, b_slots, uc, norm_part);
     LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, norm_part, nbk, &dctl->norm_hi);
     TRY(read_ctl());
-    if (direct && hctl->unsorted) {
+    if (direct && (hctl->unsorted || hctl->overflow)) {
       ar->top = top0;
       run_emit = true;
       return run<W, F32>(c);
@@ -1018,8 +1019,10 @@ int Engine::run(Call& c) {
   }
   LAUNCH("k_write_out", (k_write_out<W>), nchunk, 256, wa, nbk);
   TRY(read_ctl());
-  if (direct && hctl->unsorted) {
-    // a term out of canonical order: the buckets were left empty; redo by emission
+  if (direct && (hctl->unsorted || hctl->overflow)) {
+    // a term out of canonical order (the buckets were left empty), or strings
+    // crowded into one bucket beyond the merge's capacity: redo by emission,
+    // whose hash-range passes split them
     ar->top = top0;
     run_emit = true;
     return run<W, F32>(c);
