@@ -1962,7 +1962,13 @@ int pauli_rk4_step(const pauli_op* H, const pauli_op* O, double dt, const pauli_
   const int W = words_of(O->n_qubits);
   const double h2 = dt / 2.0, c1 = dt / 6.0, c2 = dt / 3.0;
   const OpV Ov = view(O);
-  // k = i [H, S], untruncated, kept at the top of the workspace
+  // k = i [H, S], kept at the top of the workspace.  Every use of k below
+  // (the stage inputs and the final sum) is truncated with t's length cap
+  // first, and the cap acts on each string alone, so strings of k above it
+  // are not emitted at all: every result equals the one from the full k.
+  pauli_trunc tl;
+  memset(&tl, 0, sizeof(tl));
+  if (t) tl.max_len = t->max_len;
   auto comm_i = [&](const OpV& S, OpV* k) -> int {
     Call c;
     c.W = W;
@@ -1972,6 +1978,7 @@ int pauli_rk4_step(const pauli_op* H, const pauli_op* O, double dt, const pauli_
     c.n_groups = 1;
     c.groups[0].kind = G_SUM;
     c.groups[0].alpha = make_double2(0.0, 1.0);
+    c.trunc = tl.max_len > 0 ? &tl : nullptr;
     c.out.to_arena = true;
     int rc = run_call(ar, ws, stream, c);
     *k = c.out.arena_op;
