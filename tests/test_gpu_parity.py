@@ -51,8 +51,11 @@ def say(*a):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,nh,no,seed", [(10, 20, 3000, 1), (64, 191, 2500, 2),
                                           (100, 40, 1500, 3), (128, 30, 700, 4),
-                                          (1, 1, 1, 5)])
+                                          (1, 1, 1, 5), (64, 191, 1300, 6),
+                                          (128, 300, 800, 7)])
 def test_commutator_random(pk, ws, n, nh, no, seed):
+    """Random operators; the last two cases are small calls (at most 2^18
+    pairs) over 2^10 hash bins with H indices above 127 kept aside."""
     say(f"commutator n={n} nh={nh} no={no} seed={seed}")
     H = wl.random_operator(n, nh, seed=seed, density=min(1.0, 3.0 / n + 0.05))
     O = wl.random_operator(n, no, seed=seed + 100, density=min(1.0, 6.0 / n + 0.05))
