@@ -124,6 +124,8 @@ def test_workspace_query_is_sufficient(pk):
     Oh = wl.random_local_strings(n, 20000, 10, seed=7)
     O = pk.PauliOp.from_host(Oh)
     O2 = pk.PauliOp.from_host(wl.random_local_strings(n, 5000, 10, seed=8))
+    O3 = pk.PauliOp.from_host(wl.random_local_strings(n, 1200, 10, seed=10))
+    assert H.size * O3.size <= 1 << 18 and H.size > 127
     T = pk.Trunc(max_len=12, max_strings=30000)
     Q = pk
     cases = [
@@ -139,6 +141,9 @@ def test_workspace_query_is_sufficient(pk):
         (Q.PAULI_Q_RK4, H, O2, None, pk.Trunc(max_strings=20000),
          lambda w: pk.rk4_step(H, O2, 0.02, pk.Trunc(max_strings=20000), ws=w)),
         (Q.PAULI_Q_REDUCTION, O, O2, None, None, lambda w: pk.inner(O, O2, ws=w)),
+        # small calls (at most 2^18 pairs) over 2^10 bins, H indices kept aside
+        (Q.PAULI_Q_COMMUTATOR, H, O3, None, None, lambda w: pk.commutator(H, O3, ws=w)),
+        (Q.PAULI_Q_MULTIPLY, H, O3, None, None, lambda w: pk.multiply(H, O3, ws=w)),
     ]
     for op, A, B, C, t, fn in cases:
         nbytes, cap = pk.workspace_query(op, A, B, C, t)
