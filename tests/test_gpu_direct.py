@@ -155,3 +155,31 @@ def test_crowded_hash_range_falls_back_to_emission(pk, ws):
     want = oracle.canonicalize(L)
     got = pk.canonicalize(pk.PauliOp.from_raw(n, L.x, L.z, L.coef), ws=ws)
     assert_same_operator(got.to_host(), want, what="canonicalize crowded list")
+
+
+@pytest.mark.parametrize("n,count,dtype", [(64, 1, 0), (64, 7, 0), (64, 900, 0), (64, 1500, 1),
+                                           (128, 3000, 0), (64, 70_000, 1), (128, 200_000, 0)])
+def test_direct_sizes_match_emission(pk, ws, n, count, dtype):
+    """From one string to 2^F buckets of every size class (F = 0 through 9):
+    a three-term sum with truncation, canonical terms (direct) against the
+    same terms out of order (emission), bit for bit."""
+    say(f"direct sizes n={n} count={count} dtype={dtype}")
+    A = random_words_op(n, count, seed=count + n)
+    B = random_words_op(n, count, seed=count + n + 1, share=A, nshare=count // 2)
+    if dtype:
+        for X in (A, B):
+            X.coef = X.coef.astype(np.complex64).astype(np.complex128)
+    Ad = pk.PauliOp.from_host(A, dtype=dtype, ws=ws)
+    Bd = pk.PauliOp.from_host(B, dtype=dtype, ws=ws)
+    T = pk.Trunc(n * 3 // 4, 0.1, max(1, count // 3))
+    got = pk.add(Ad, 0.5 + 0.25j, Bd, -1.0, T, ws=ws)
+    alt = pk.add(shuffled(pk, A, 1, dtype), 0.5 + 0.25j, shuffled(pk, B, 2, dtype), -1.0, T,
+                 ws=ws)
+    assert got.size == alt.size
+    for a, b in ((got.x, alt.x), (got.z, alt.z)):
+        assert np.array_equal(a[:, :got.size].cpu().numpy(), b[:, :alt.size].cpu().numpy())
+    assert np.array_equal(got.coef[:got.size].cpu().numpy(), alt.coef[:alt.size].cpu().numpy())
+    if dtype == 0:
+        want = oracle.truncate(oracle.add(A, 0.5 + 0.25j, B, -1.0),
+                               oracle.Trunc(n * 3 // 4, 0.1, max(1, count // 3)))
+        assert_same_operator(got.to_host(), want, what="direct sizes")
