@@ -197,6 +197,13 @@ int pauli_canonicalize(const pauli_op *in, pauli_op *out, pauli_ws *ws, void *st
  * Asynchronous on `stream`. */
 int pauli_add_noise(pauli_op *A, double lambda, void *stream);
 
+/* A <- A^dagger in place.  Every Pauli string is Hermitian, so the adjoint
+ * of sum_k c_k P_k is sum_k conj(c_k) P_k: the imaginary part of every
+ * coefficient changes sign; strings, order and size are unchanged (the
+ * Heisenberg section's dagger, as in Tr(O(t) O0^dagger)).  Asynchronous on
+ * `stream`. */
+int pauli_dagger(pauli_op *A, void *stream);
+
 /* out[2q] + i out[2q+1] (host, 2 Q->size doubles) = the coefficient in A of the
  * string q of Q, 0 when A lacks it.  A must be canonical (distinct strings in
  * canonical order, as every call of this library leaves it); Q's strings are

@@ -2046,6 +2046,15 @@ int pauli_add_noise(pauli_op* A, double lambda, void* stream_) {
   return PAULI_OK;
 }
 
+int pauli_dagger(pauli_op* A, void* stream_) {
+  if (check_op(A, false)) return PAULI_EINVAL;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (A->size == 0) return PAULI_OK;
+  const int blocks = (int)std::min<int64_t>((A->size + 255) / 256, 8192);
+  LAUNCH("k_conj", k_conj, blocks, 256, A->coef, A->size, A->dtype == PAULI_C64K ? 1 : 0);
+  return PAULI_OK;
+}
+
 int pauli_coefficients(const pauli_op* A, const pauli_op* Q, double* out, pauli_ws* ws,
                        void* stream_) {
   if (!ws || check_op(A, false) || check_op(Q, false) || (Q->size && !out)) return PAULI_EINVAL;

@@ -2163,6 +2163,19 @@ __global__ __launch_bounds__(256) void k_add_noise(const uint64_t* x, const uint
   }
 }
 
+// Adjoint in place: the imaginary part of every coefficient changes sign.
+__global__ __launch_bounds__(256) void k_conj(void* coef, int64_t n, int f32) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    if (f32) {
+      float2* c = reinterpret_cast<float2*>(coef) + i;
+      c->y = -c->y;
+    } else {
+      double2* c = reinterpret_cast<double2*>(coef) + i;
+      c->y = -c->y;
+    }
+  }
+}
+
 // Coefficients in A (canonical: ascending order keys `ak`) of the strings of
 // Q: out[q] = A's coefficient of Q's string q, or 0 when A lacks it.
 template <int W>

@@ -325,6 +325,17 @@ def add_noise(A: PauliOp, lam: float) -> PauliOp:
     return A
 
 
+def dagger(A: PauliOp) -> PauliOp:
+    """A <- A^dagger in place (conjugated coefficients: every string is
+    Hermitian); returns A."""
+    L = _lib.load()
+    As = A.c_struct()
+    st = L.pauli_dagger(ctypes.byref(As), _stream_handle())
+    if st != PAULI_OK:
+        raise PauliError(st, "pauli_dagger", _lib.last_error())
+    return A
+
+
 def coefficients(A: PauliOp, Q: PauliOp, ws: Workspace | None = None) -> np.ndarray:
     """complex128 [Q.size]: A's coefficient of each string of Q (0 if absent)."""
     L = _lib.load()

@@ -126,3 +126,29 @@ def test_coefficients_lookup_fp32_operand(pk, ws):
     want = np.array([d.get(k, 0j) for k in Q.keys()])
     assert np.array_equal(got, want)
     assert np.array_equal(want, A.coef[::7].astype(np.complex64).astype(np.complex128))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_dagger_conjugates_in_place(pk, ws, dtype):
+    """pauli_dagger: the same strings in the same order, every coefficient
+    conjugated (bit for bit); Tr(B A^dagger)/2^N from the product's identity
+    coefficient equals <A, B>."""
+    say(f"dagger dtype={dtype}")
+    n = 20
+    A = wl.random_operator(n, 3000, seed=41, density=0.2)
+    B = wl.HostOp(n, A.x[:1500], A.z[:1500], A.coef[1000:2500] * (0.3 - 0.7j))
+    if dtype:
+        A.coef = A.coef.astype(np.complex64).astype(np.complex128)
+    Ad = up(pk, A, ws, dtype=dtype)
+    before = Ad.to_host()
+    pk.dagger(Ad)
+    after = Ad.to_host()
+    assert np.array_equal(after.x, before.x) and np.array_equal(after.z, before.z)
+    assert np.array_equal(after.coef, np.conj(before.coef))
+    if dtype == 0:
+        Bd = up(pk, B, ws)
+        prod = pk.multiply(Bd, Ad, ws=ws)  # Tr(B A^dagger) = Tr(A^dagger B)
+        tr = pk.trace(prod, ws=ws)
+        pk.dagger(Ad)  # back to A
+        ip = pk.inner(Ad, Bd, ws=ws)
+        assert abs(tr - ip) <= 1e-12 * max(1.0, abs(ip))

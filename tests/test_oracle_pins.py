@@ -801,3 +801,20 @@ def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     assert r.returncode == 0, r.stderr[-3000:]
     assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
     assert "sanitizer driver ok" in r.stdout
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_adjoint_is_conjugated_coefficients(seed):
+    """Every string of the encoding is Hermitian, so the adjoint of an
+    operator is the same strings with conjugated coefficients (what
+    pauli_dagger computes): dense(A)^H equals dense of the conjugated
+    operator, and Tr(A^H B)/2^N equals the oracle's inner product."""
+    n = 3
+    A = wl.random_operator(n, 12, seed=seed + 300, density=0.7)
+    B = wl.random_operator(n, 10, seed=seed + 310, density=0.7)
+    conjA = wl.HostOp(n, A.x, A.z, np.conj(A.coef))
+    dA = dense(A)
+    assert np.allclose(dA.conj().T, dense(conjA), atol=1e-14)
+    got = oracle.inner(A, B)
+    want = np.trace(dA.conj().T @ dense(B)) / 2 ** n
+    assert abs(got - want) < 1e-13
