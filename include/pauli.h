@@ -183,6 +183,13 @@ int pauli_add(const pauli_op *A, double alpha_re, double alpha_im, const pauli_o
 int pauli_truncate(const pauli_op *in, const pauli_trunc *t, pauli_op *out, pauli_ws *ws,
                    void *stream);
 
+/* out = in / b for a finite real b != 0: every coefficient's parts divided
+ * by b (IEEE division in FP64; FP32 outputs rounded once), exact zeros
+ * (underflow) dropped, canonical order (the Krylov section's O'_n / b_n as a
+ * call of its own).  `in` needs unique strings; PAULI_EINVAL for b = 0 or not
+ * finite; PAULI_ECAPACITY as for pauli_add. */
+int pauli_divide(const pauli_op *in, double b, pauli_op *out, pauli_ws *ws, void *stream);
+
 /* out = canonical form of in: duplicate strings summed in input order, exact
  * zeros dropped, library order.  Duplicates allowed; up to 2^28 strings. */
 int pauli_canonicalize(const pauli_op *in, pauli_op *out, pauli_ws *ws, void *stream);

@@ -11,7 +11,8 @@ from ._lib import (PAULI_C128, PAULI_C64K, PAULI_Q_ADD, PAULI_Q_CANONICALIZE,
                    PAULI_Q_MULTIPLY, PAULI_Q_REDUCTION, PAULI_Q_RK4, PAULI_Q_TRUNCATE,
                    PAULI_REORTH_LOCAL, PauliError)
 from .ops import (PauliOp, Trunc, Workspace, add, add_noise, canonicalize, canonicalize_ts1d,
-                  coefficients, commutator, commutator_ts1d, correlator, dagger, inner, lanczos_step,
+                  coefficients, commutator, commutator_ts1d, correlator, dagger, divide, inner,
+                  lanczos_step,
                   last_stats, read_totals, workspace_query,
                   multiply, norm2, norm2_ts1d, order_keys, profile_enable, profile_read,
                   rk4_step, strings_from_order_keys, trace, truncate)
@@ -21,7 +22,7 @@ __all__ = ["PAULI_C128", "PAULI_C64K", "PauliError", "PauliOp", "Trunc", "Worksp
            "canonicalize", "commutator", "inner", "lanczos_step", "norm2", "rk4_step",
            "truncate", "lanczos", "evolve", "profile_enable", "profile_read", "last_stats",
            "order_keys", "strings_from_order_keys", "multiply", "trace", "moments",
-           "add_noise", "dagger", "coefficients", "evolve_noisy", "commutator_ts1d",
+           "add_noise", "dagger", "divide", "coefficients", "evolve_noisy", "commutator_ts1d",
            "canonicalize_ts1d", "norm2_ts1d", "lanczos_ts1d", "correlator",
            "workspace_query", "read_totals", "PAULI_REORTH_LOCAL", "PAULI_Q_COMMUTATOR", "PAULI_Q_MULTIPLY",
            "PAULI_Q_ADD", "PAULI_Q_TRUNCATE", "PAULI_Q_CANONICALIZE", "PAULI_Q_LANCZOS",

@@ -16,7 +16,7 @@ PAULI_REORTH_LOCAL = 1
  PAULI_Q_CANONICALIZE_TS1D, PAULI_Q_LANCZOS_TS1D, PAULI_Q_REDUCTION) = range(12)
 
 EXPORTS = ["pauli_commutator", "pauli_multiply", "pauli_trace", "pauli_add", "pauli_truncate",
-           "pauli_canonicalize", "pauli_add_noise", "pauli_dagger", "pauli_coefficients",
+           "pauli_canonicalize", "pauli_divide", "pauli_add_noise", "pauli_dagger", "pauli_coefficients",
            "pauli_commutator_ts1d", "pauli_canonicalize_ts1d", "pauli_norm2_ts1d",
            "pauli_lanczos_step_ts1d",
            "pauli_rk4_step", "pauli_lanczos_step", "pauli_norm2", "pauli_inner",
@@ -83,6 +83,7 @@ def load():
     L.pauli_trace.argtypes = [op, P(d), ws, vp]
     L.pauli_add_noise.argtypes = [op, d, vp]
     L.pauli_dagger.argtypes = [op, vp]
+    L.pauli_divide.argtypes = [op, d, op, ws, vp]
     L.pauli_commutator_ts1d.argtypes = [op, op, tr, op, ws, vp]
     L.pauli_canonicalize_ts1d.argtypes = [op, op, ws, vp]
     L.pauli_norm2_ts1d.argtypes = [op, P(d), ws, vp]

@@ -199,6 +199,7 @@ int check_op(const pauli_op* o, bool output) {
 struct GroupSpec {
   int kind = G_TERM;
   double2 alpha = make_double2(1.0, 0.0);
+  bool divide = false;  // the group's values are divided by alpha.x instead
 };
 
 struct OutSpec {
@@ -504,7 +505,7 @@ int Engine::run(Call& c) {
     memset(&ma, 0, sizeof(ma));
     for (int g = 0; g < c.n_groups; g++) {
       ma.alpha[g] = c.groups[g].alpha;
-      ma.alpha_kind[g] = alpha_kind(c.groups[g].alpha);
+      ma.alpha_kind[g] = c.groups[g].divide ? A_DIV : alpha_kind(c.groups[g].alpha);
       ma.gkind[g] = c.groups[g].kind;
     }
     ma.mode = c.mode;
@@ -1734,6 +1735,24 @@ int pauli_truncate(const pauli_op* in, const pauli_trunc* t, pauli_op* out, paul
   c.T[0] = view(in);
   c.n_groups = 1;
   c.trunc = t;
+  c.out.user = out;
+  c.out.f32 = out->dtype == PAULI_C64K;
+  c.round32 = c.out.f32;
+  return run_call(ar, ws, stream, c);
+}
+
+int pauli_divide(const pauli_op* in, double b, pauli_op* out, pauli_ws* ws, void* stream) {
+  if (!ws || check_op(in, false) || check_op(out, true)) return PAULI_EINVAL;
+  if (out->n_qubits != in->n_qubits || !(std::isfinite(b) && b != 0.0)) return PAULI_EINVAL;
+  Arena ar = make_arena(ws);
+  Call c;
+  c.W = words_of(in->n_qubits);
+  c.f32rec = in->dtype == PAULI_C64K;
+  c.n_terms = 1;
+  c.T[0] = view(in);
+  c.n_groups = 1;
+  c.groups[0].alpha = make_double2(b, 0.0);
+  c.groups[0].divide = true;
   c.out.user = out;
   c.out.f32 = out->dtype == PAULI_C64K;
   c.round32 = c.out.f32;

@@ -28,7 +28,7 @@
 namespace pauli {
 
 enum GroupKind : int { G_TERM = 0, G_SUM = 1, G_SUM_KAHAN32 = 2 };
-enum AlphaKind : int { A_GENERAL = 0, A_ONE = 1, A_I = 2 };
+enum AlphaKind : int { A_GENERAL = 0, A_ONE = 1, A_I = 2, A_DIV = 3 };  // A_DIV: v / alpha.x
 enum MergeMode : int { M_PLAIN = 0, M_LANCZOS = 1 };
 constexpr int MAX_GROUPS = 8;
 constexpr int MAX_TERMS = 6;
@@ -815,6 +815,7 @@ DEV bool keep_lookup(const Key<W>* keep, int n, const Key<W>& mk) {
 DEV double2 apply_alpha(int kind, double2 alpha, double2 v) {
   if (kind == A_ONE) return v;
   if (kind == A_I) return make_double2(-v.y, v.x);
+  if (kind == A_DIV) return make_double2(v.x / alpha.x, v.y / alpha.x);
   return cmul(alpha, v);
 }
 

@@ -395,6 +395,26 @@ def truncate(O: PauliOp, trunc: Trunc, out: PauliOp | None = None,
     return out
 
 
+def divide(O: PauliOp, b: float, out: PauliOp | None = None,
+           ws: Workspace | None = None) -> PauliOp:
+    """O / b for a finite real b != 0 (IEEE division of each part, exact zeros
+    dropped), canonical."""
+    L = _lib.load()
+    ws = ws or default_workspace(O.device)
+    if out is None:
+        out = _out_like(O.n_qubits, O.size, O.dtype, O.device)
+    Os = O.c_struct()
+
+    def fn(wss):
+        outs = out.c_struct()
+        st = L.pauli_divide(ctypes.byref(Os), float(b), ctypes.byref(outs), ctypes.byref(wss),
+                            _stream_handle())
+        return st, outs
+
+    _call("pauli_divide", fn, ws, out)
+    return out
+
+
 def canonicalize(O: PauliOp, out: PauliOp | None = None, ws: Workspace | None = None) -> PauliOp:
     L = _lib.load()
     ws = ws or default_workspace(O.device)

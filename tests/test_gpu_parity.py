@@ -461,3 +461,32 @@ def test_multi_pass_restart_after_wide_count(pk):
     assert np.array_equal(h.coef[go], rc[ro])
     del O, got, ws
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_divide(pk, ws, dtype):
+    """O / b: bit for bit the oracle's IEEE division (FP32 operands divided in
+    FP64 and rounded once); a coefficient that underflows is dropped; b = 0
+    is refused.  Canonical input (direct merge) and shuffled input."""
+    say(f"divide dtype={dtype}")
+    n = 64
+    O = wl.random_operator(n, 5000, seed=61, density=0.1)
+    O.coef[7] = 3e-310 + 1e-310j  # divided by b, both parts underflow to zero
+    if dtype:
+        O.coef = O.coef.astype(np.complex64).astype(np.complex128)
+        O.coef[7] = 1e-40 + 0j  # an FP32 subnormal
+    b = 7.25e15 if dtype == 0 else 3.5e30
+    want = oracle.divide(O, b)
+    got = pk.divide(up(pk, O, ws, dtype=dtype), b, ws=ws).to_host()
+    if dtype:
+        want = wl.HostOp(n, want.x, want.z,
+                         want.coef.real.astype(np.float32) + 1j * want.coef.imag.astype(np.float32))
+        keep = (want.coef.real != 0) | (want.coef.imag != 0)
+        want = wl.HostOp(n, want.x[keep], want.z[keep], want.coef[keep])
+    assert got.n == want.n < O.n
+    assert_same_operator(got, want, rtol=0.0, what="divide")
+    p = np.random.default_rng(3).permutation(O.n)
+    raw = pk.PauliOp.from_raw(n, O.x[p], O.z[p], O.coef[p], dtype=dtype)
+    assert_same_operator(pk.divide(raw, b, ws=ws).to_host(), want, rtol=0.0, what="divide raw")
+    with pytest.raises(pk.PauliError):
+        pk.divide(raw, 0.0, ws=ws)
