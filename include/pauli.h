@@ -187,7 +187,8 @@ int pauli_truncate(const pauli_op *in, const pauli_trunc *t, pauli_op *out, paul
  * by b (IEEE division in FP64; FP32 outputs rounded once), exact zeros
  * (underflow) dropped, canonical order (the Krylov section's O'_n / b_n as a
  * call of its own).  `in` needs unique strings; PAULI_EINVAL for b = 0 or not
- * finite; PAULI_ECAPACITY as for pauli_add. */
+ * finite; PAULI_ECAPACITY as for pauli_add; its workspace is that of
+ * PAULI_Q_TRUNCATE with no truncation. */
 int pauli_divide(const pauli_op *in, double b, pauli_op *out, pauli_ws *ws, void *stream);
 
 /* out = canonical form of in: duplicate strings summed in input order, exact
