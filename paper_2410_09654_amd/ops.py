@@ -85,6 +85,50 @@ class PauliOp:
         raw = cls.from_raw(host.n_qubits, host.x, host.z, host.coef, dtype, device)
         return canonicalize(raw, ws=ws)
 
+    @classmethod
+    def from_terms(cls, n_qubits: int, terms, dtype: int = PAULI_C128, device="cuda",
+                   ws=None) -> "PauliOp":
+        """Operator from terms (coef, "XZ", [i, j]): letters X, Y, Z (I or 1 for the
+        identity) on the given 1-based sites; strings that repeat are summed in
+        the order given.  Canonical on return."""
+        W = _words(n_qubits)
+        terms = list(terms)
+        x = np.zeros((len(terms), W), np.uint64)
+        z = np.zeros((len(terms), W), np.uint64)
+        coef = np.zeros(len(terms), np.complex128)
+        bits = {"X": (1, 0), "Y": (1, 1), "Z": (0, 1), "I": (0, 0), "1": (0, 0)}
+        for k, (c, letters, sites) in enumerate(terms):
+            if len(letters) != len(sites):
+                raise ValueError(f"term {k}: {len(letters)} letters for {len(sites)} sites")
+            coef[k] = c
+            for ch, site in zip(letters, sites):
+                if not 1 <= int(site) <= n_qubits or ch not in bits:
+                    raise ValueError(f"term {k}: bad factor {ch}{site}")
+                w, b = divmod(int(site) - 1, 64)
+                bx, bz = bits[ch]
+                if (x[k, w] >> np.uint64(b)) & np.uint64(1) or (z[k, w] >> np.uint64(b)) & np.uint64(1):
+                    raise ValueError(f"term {k}: site {site} given twice")
+                x[k, w] |= np.uint64(bx) << np.uint64(b)
+                z[k, w] |= np.uint64(bz) << np.uint64(b)
+        raw = cls.from_raw(n_qubits, x, z, coef, dtype, device)
+        return canonicalize(raw, ws=ws)
+
+    def to_strings(self):
+        """The operator as lines "(re + im im) XYZ1...": site 1 leftmost, 1 for the
+        identity, in storage order."""
+        x, z, c = self.to_numpy()
+        letters = {(0, 0): "1", (1, 0): "X", (1, 1): "Y", (0, 1): "Z"}
+        lines = []
+        for k in range(len(c)):
+            text = "".join(
+                letters[(int(x[k, j // 64] >> np.uint64(j % 64)) & 1,
+                         int(z[k, j // 64] >> np.uint64(j % 64)) & 1)]
+                for j in range(self.n_qubits))
+            sign = "-" if np.signbit(c[k].imag) else "+"
+            # a zero real part prints as 0, whatever its sign bit
+            lines.append(f"({c[k].real + 0.0:.10g} {sign} {abs(c[k].imag):.10g}im) {text}")
+        return lines
+
     def to_numpy(self):
         n = self.size
         x = self.x[:, :n].cpu().numpy().view(np.uint64).T.copy()

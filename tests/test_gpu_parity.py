@@ -490,3 +490,21 @@ def test_divide(pk, ws, dtype):
     assert_same_operator(pk.divide(raw, b, ws=ws).to_host(), want, rtol=0.0, what="divide raw")
     with pytest.raises(pk.PauliError):
         pk.divide(raw, 0.0, ws=ws)
+
+
+def test_from_terms_and_to_strings(pk, ws):
+    """The paper-style constructor and printer: terms on 1-based sites, repeats
+    summed in order, printed with site 1 leftmost and 1 for the identity."""
+    say("from_terms / to_strings")
+    O = pk.PauliOp.from_terms(10, [(1.0, "X", [1])], ws=ws)
+    assert O.to_strings() == ["(1 + 0im) X111111111"]
+    A = pk.PauliOp.from_terms(5, [(0.5, "ZZ", [1, 2]), (2.0, "Y", [5]), (0.25, "ZZ", [1, 2]),
+                                  (complex(0.0, -1.0), "XIZ", [2, 3, 4])], ws=ws)
+    got = dict((line.split()[-1], line) for line in A.to_strings())
+    assert got == {"ZZ111": "(0.75 + 0im) ZZ111", "1111Y": "(2 + 0im) 1111Y",
+                   "1X1Z1": "(0 - 1im) 1X1Z1"}
+    H = wl.from_terms(5, [(0.75, [("Z", 1), ("Z", 2)]), (2.0, [("Y", 5)]),
+                          (complex(0.0, -1.0), [("X", 2), ("Z", 4)])])
+    assert_same_operator(A.to_host(), oracle.canonicalize(H), rtol=0.0, what="from_terms")
+    with pytest.raises(ValueError):
+        pk.PauliOp.from_terms(5, [(1.0, "XX", [1, 1])])
