@@ -387,6 +387,12 @@ typedef struct pauli_stats {
   int64_t output;    /* strings written to the output */
   int32_t passes;    /* hash-range passes */
   int32_t buckets;   /* merge buckets */
+  int32_t host_syncs; /* times the host waited for the stream (control-block
+                         reads): one for a call planned from its sizes (at most
+                         2^18 possible records, workspace for that bound), more
+                         when the count must be read first or the top-M select
+                         needs the host */
+  int32_t reserved;
 } pauli_stats;
 void pauli_last_stats(pauli_stats *out);
 

@@ -47,7 +47,8 @@ class PauliWsC(ctypes.Structure):
 class PauliStatsC(ctypes.Structure):
     _fields_ = [("emitted", ctypes.c_int64), ("unique", ctypes.c_int64),
                 ("survivors", ctypes.c_int64), ("output", ctypes.c_int64),
-                ("passes", ctypes.c_int32), ("buckets", ctypes.c_int32)]
+                ("passes", ctypes.c_int32), ("buckets", ctypes.c_int32),
+                ("host_syncs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PauliTotalsC(ctypes.Structure):

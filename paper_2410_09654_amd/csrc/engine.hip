@@ -365,8 +365,10 @@ struct Engine {
   Ctl* dctl = nullptr;
   Ctl* hctl = nullptr;
   bool run_emit = false;  // take the emission path even for canonical terms
+  bool run_counted = false;  // read the count before planning, even for small calls
 
   int read_ctl() {
+    g_stats.host_syncs++;
     HIP_TRY(hipMemcpyAsync(hctl, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     g_prof.resolve();
@@ -380,6 +382,7 @@ struct Engine {
   }
   int set_u64(unsigned long long* dst, unsigned long long v) {
     // small host->device update of the control block (not used under capture)
+    g_stats.host_syncs++;
     HIP_TRY(hipMemcpyAsync(dst, &v, sizeof(v), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     return PAULI_OK;
@@ -496,6 +499,7 @@ int Engine::run(Call& c) {
   // empty and the call is redone by emission (run_emit), as it is when strings
   // crowd one bucket beyond the merge's capacity.
   unsigned long long pe_all = 0;
+  bool planned = false;  // one pass planned from the sizes alone (no count read)
   const bool want_select = tr && tr->max_strings > 0;
   Bufs2 b2;
   MergeArgs ma;
@@ -621,13 +625,11 @@ int Engine::run(Call& c) {
     // NBINS_LOG_SMALL for calls of at most 2^18 records even if every pair
     // emits one (the per-call bin tables then cost a sixteenth)
     int nbl = NBINS_LOG;
-    {
-      const unsigned long long bound =
-          (comm ? (unsigned long long)c.H.n * (unsigned long long)c.O.n : 0ull) +
-          (unsigned long long)nterm_rec;
-      if (bound <= (1ull << (NBINS_LOG_SMALL + 8))) nbl = NBINS_LOG_SMALL;
-    }
-    auto count_pass = [&](int pass_bits, uint32_t pass_id) -> int {
+    const unsigned long long rec_bound =
+        (comm ? (unsigned long long)c.H.n * (unsigned long long)c.O.n : 0ull) +
+        (unsigned long long)nterm_rec;
+    if (rec_bound <= (1ull << (NBINS_LOG_SMALL + 8))) nbl = NBINS_LOG_SMALL;
+    auto count_pass = [&](int pass_bits, uint32_t pass_id, bool read = true) -> int {
       ea.pass_bits = pass_bits;
       ea.pass_id = pass_id;
       // the first count pass of a merge sequence also clears the level-0 |c|^2 histogram
@@ -637,7 +639,7 @@ int Engine::run(Call& c) {
         constexpr int NBS = 1 << NBINS_LOG_SMALL;
         LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG_SMALL>), rows, EMIT_THREADS, ea);
         LAUNCH("k_scan_cols", k_scan_cols, NBS / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl, NBS);
-        LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_SMALL>, 1, scan_bins_threads<NBINS_LOG_SMALL>(),
+        LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_SMALL>, 1, 1024,
                bin_total, bin_base, dctl, zero, nzero);
       } else if (nbl == NBINS_LOG) {
         LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG>), rows, EMIT_THREADS, ea);
@@ -651,20 +653,53 @@ int Engine::run(Call& c) {
         LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
                nzero);
       }
-      return read_ctl();
+      return read ? read_ctl() : PAULI_OK;
     };
-    TRY(count_pass(0, 0));
-    if (nbl == NBINS_LOG_SMALL && hctl->maxg[0] > (unsigned int)merge_cap<W>()) {
+    // source ids fold into the key bits implied by the bin unless an index
+    // needs more than 11 bits (H above 2047 strings, canonicalisation lists)
+    // (translation-symmetric calls carry (H entry, rotation) as the source id)
+    // (7 bits over 2^10 bins)
+    auto wide_for = [&](int bins_log) {
+      const int64_t max_h = bins_log == NBINS_LOG_SMALL ? (1 << (NBINS_LOG_SMALL - 3)) - 1 : 2047;
+      bool w = comm && (c.H.n > max_h || c.ts);
+      for (int t = 0; t < c.n_terms; t++) w = w || c.tlist[t];
+      return w;
+    };
+    // A call of at most 2^18 possible records runs one pass over 2^10 bins
+    // planned from its sizes alone (records laid out at that bound, a fixed
+    // bucket width), so the host reads nothing before the output size; the
+    // count's bins are checked then, and a call whose strings crowd a bucket
+    // is redone with the count read first.
+    if (nbl == NBINS_LOG_SMALL && !run_counted) {
+      TRY(count_pass(0, 0, false));
+      const size_t mark_bottom = ar->bottom, mark_need = ar->need;
+      take_bufs2<W, F32>(*ar, (size_t)std::max<unsigned long long>(rec_bound, 1),
+                         wide_for(NBINS_LOG_SMALL), false, (1u << NBINS_LOG_SMALL) << 2,
+                         want_select, b2);
+      if (ar->short_) {
+        // the workspace holds the exact layout only: read the count
+        ar->bottom = mark_bottom;
+        ar->need = mark_need;
+        ar->short_ = false;
+        run_counted = true;
+        TRY(read_ctl());
+      } else {
+        planned = true;
+      }
+    } else {
+      TRY(count_pass(0, 0));
+    }
+    if (!planned && nbl == NBINS_LOG_SMALL && hctl->maxg[0] > (unsigned int)merge_cap<W>()) {
       // a small call whose records crowd one bin: count again over 2^14 bins
       nbl = NBINS_LOG;
       TRY(count_pass(0, 0));
     }
-    if (hctl->bad_keep) return PAULI_EINVAL;
-    if (hctl->overflow & 2u) {
+    if (!planned && hctl->bad_keep) return PAULI_EINVAL;
+    if (!planned && (hctl->overflow & 2u)) {
       g_last_error = "more than 2^32 records in one pass";
       return PAULI_EINTERNAL;
     }
-    pe_all = hctl->pe_total;
+    pe_all = planned ? rec_bound : hctl->pe_total;
     // passes over disjoint hash ranges keep every bucket within the merge capacity; the
     // largest bin does not always halve with each extra pass bit (all records
     // of one string share a bin), so a pass that still overflows restarts the
@@ -675,16 +710,12 @@ int Engine::run(Call& c) {
     const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
     const uint32_t max_buckets = (uint32_t)(1u << nbl) << table_bits;
     // ----- records, U, bucket tables, candidate lists -------------------------
-    // source ids fold into the key bits implied by the bin unless an index
-    // needs more than 11 bits (H above 2047 strings, canonicalisation lists)
-    // (translation-symmetric calls carry (H entry, rotation) as the source id)
-    // (7 bits over 2^10 bins)
-    const int64_t max_h = nbl == NBINS_LOG_SMALL ? (1 << (NBINS_LOG_SMALL - 3)) - 1 : 2047;
-    bool wide = comm && (c.H.n > max_h || c.ts);
-    for (int t = 0; t < c.n_terms; t++) wide = wide || c.tlist[t];
+    const bool wide = wide_for(nbl);
     const bool partitioned = nbl == NBINS_LOG_MP;
-    take_bufs2<W, F32>(*ar, ptot, wide, partitioned, max_buckets, want_select, b2);
-    if (ar->short_) return PAULI_EWORKSPACE;
+    if (!planned) {
+      take_bufs2<W, F32>(*ar, ptot, wide, partitioned, max_buckets, want_select, b2);
+      if (ar->short_) return PAULI_EWORKSPACE;
+    }
     void* recs = b2.recs;
     uint32_t* rsrc_wide = b2.rsrc_wide;
     void* precs = b2.precs;
@@ -786,6 +817,33 @@ int Engine::run(Call& c) {
           TRY(count_pass(pass_bits, (uint32_t)p));
           first_counts = false;
         }
+        if (planned) {
+          // buckets of 2^g bins whose mean stays within 0.85 of the small
+          // merge's capacity even if every possible record is emitted; the
+          // merges and the deferral list take whatever arrives, and a bucket
+          // above the full-size merge's capacity sends the call round again
+          constexpr int SCAP = small_merge_cap<W, F32>();
+          int g_log = 4;
+          while (g_log > 0 &&
+                 (double)pe_all > std::ldexp(0.85 * SCAP, NBINS_LOG_SMALL - g_log))
+            g_log--;
+          LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG_SMALL>), rows, EMIT_THREADS, ea);
+          ma.g_log = g_log;
+          ma.nbins_log = nbl;
+          ma.digit_shift = nbl - g_log;
+          ma.pass_bits = 0;
+          ma.pass_id = 0;
+          ma.u_off = 0;
+          ma.bucket_off = 0;
+          const uint32_t nb_pass = (uint32_t)((1u << nbl) >> g_log);
+          ma.defer = b1.defer;
+          LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, MERGE_SMALL>),
+                 nb_pass, MERGE_SMALL_THREADS, ma);
+          LAUNCH("k_merge_deferred", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), MERGE_LIST>),
+                 std::min<uint32_t>(nb_pass, 512), MERGE_THREADS, ma);
+          nbk = nb_pass;
+          continue;
+        }
         if (pass_bits > 0 && p == 0 && hctl->part_total != pe_all) {
           char msg[160];
           snprintf(msg, sizeof(msg), "partitions hold %llu records, the count pass %llu",
@@ -885,6 +943,7 @@ int Engine::run(Call& c) {
   }
 
   // ----- Lanczos: b_n from the untruncated sum, then divide and filter -------
+  const double lanczos_floor_b = 1e-13 * (c.b_prev > 1.0 ? c.b_prev : 1.0);
   if (c.mode == M_LANCZOS) {
     if (c.ts)
       LAUNCH("k_norm_bucket_ts", (k_norm_bucket_ts<W>), nbk, 256, b_ubase, b_slots, uk, uc,
@@ -892,24 +951,9 @@ int Engine::run(Call& c) {
     else
       LAUNCH("k_norm_bucket", k_norm_bucket, nbk, 256, b_ubase, b_slots, uc, norm_part);
     LAUNCH("k_reduce_dd", k_reduce_dd, 1, 1024, norm_part, nbk, &dctl->norm_hi);
-    TRY(read_ctl());
-    if (direct && (hctl->unsorted || hctl->overflow)) {
-      ar->top = top0;
-      run_emit = true;
-      return run<W, F32>(c);
-    }
-    if (direct && hctl->bad_keep) return PAULI_EINVAL;
-    if (hctl->overflow) {
-      g_last_error = "merge bucket overflow";
-      return PAULI_EINTERNAL;
-    }
-    const double b = std::sqrt(hctl->norm_hi);
-    if (c.b_out) *c.b_out = b;
-    const double floor_b = 1e-13 * (c.b_prev > 1.0 ? c.b_prev : 1.0);
-    if (!(b > floor_b)) {
-      write_empty();
-      return PAULI_BREAKDOWN;
-    }
+    // b_n and the breakdown test are taken on the device (no read here); a
+    // breakdown leaves nothing to keep, and the host reports it with the
+    // output size
     ScaleArgs sa;
     memset(&sa, 0, sizeof(sa));
     sa.b_ubase = b_ubase;
@@ -918,7 +962,8 @@ int Engine::run(Call& c) {
     sa.b_keep = b_keep;
     sa.uk = uk;
     sa.uc = uc;
-    sa.bnorm = b;
+    sa.norm2 = &dctl->norm_hi;
+    sa.floor_b = lanczos_floor_b;
     sa.round32 = c.out.f32;
     sa.max_len = ma.max_len;
     sa.use_eps = ma.use_eps;
@@ -1028,10 +1073,29 @@ int Engine::run(Call& c) {
     run_emit = true;
     return run<W, F32>(c);
   }
+  if (planned && (hctl->overflow || hctl->maxg[0] > (unsigned int)merge_cap<W>())) {
+    // strings crowded into one bucket of the planned pass: redo with the
+    // count read first, whose plan splits them
+    ar->top = top0;
+    run_counted = true;
+    return run<W, F32>(c);
+  }
+  if (planned) {
+    if (hctl->bad_keep) return PAULI_EINVAL;
+    g_stats.emitted = (int64_t)hctl->pe_total;
+  }
   if (direct && hctl->bad_keep) return PAULI_EINVAL;
   if (hctl->overflow) {
     g_last_error = "merge bucket overflow";
     return PAULI_EINTERNAL;
+  }
+  if (c.mode == M_LANCZOS) {
+    const double b = std::sqrt(hctl->norm_hi);
+    if (c.b_out) *c.b_out = b;
+    if (!(b > lanczos_floor_b)) {
+      write_empty();
+      return PAULI_BREAKDOWN;
+    }
   }
   g_stats.unique = (int64_t)hctl->u_unique;
   g_stats.survivors = (int64_t)hctl->surv_total;
@@ -1153,6 +1217,7 @@ int Engine::run(Call& c) {
   if ((unsigned long long)wa.ocap >= nout && nout) {
     wa.sel_mode = sel_mode;
     LAUNCH("k_write", (k_write<W>), nbk, 256, wa);
+    g_stats.host_syncs++;
     HIP_TRY(hipStreamSynchronize(stream));
     g_prof.resolve();
   }

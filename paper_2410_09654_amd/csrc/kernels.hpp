@@ -589,11 +589,12 @@ __global__ __launch_bounds__(SC_COLS * SC_NSEG) void k_scan_cols(uint32_t* count
   }
 }
 
-// Exclusive scan of the bin totals (one block of scan_bins_threads<NBL>()
-// threads; thread t owns the BPT >= 16 consecutive bins from t BPT, read and
-// written as 16-byte vectors) and the largest total over aligned groups of
-// 1, 2, 4, 8, 16 bins.  Also clears `zero` (nzero words) when given: the
-// level-0 |c|^2 histogram of the merges that follow this count pass.
+// Exclusive scan of the bin totals (one block of 1024 threads, of which the
+// first scan_bins_threads<NBL>() hold the bins: thread t owns the BPT >= 16
+// consecutive bins from t BPT, read and written as 16-byte vectors) and the
+// largest total over aligned groups of 1, 2, 4, 8, 16 bins.  Also clears
+// `zero` (nzero words) when given, with every thread: the level-0 |c|^2
+// histogram of the merges that follow this count pass.
 template <int NBL>
 constexpr int scan_bins_threads() { return (1 << NBL) / 16 < 1024 ? (1 << NBL) / 16 : 1024; }
 template <int NBL>
@@ -608,14 +609,17 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   __shared__ unsigned long long tmp[1024 / 64 + 1];
   __shared__ unsigned int gmax[16][5];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  // nzero is a multiple of 4 and `zero` 16-byte aligned (histogram replicas)
-  for (uint32_t i = t; i < nzero / 4; i += TH)
+  // every thread of the block clears (nzero is a multiple of 4 and `zero`
+  // 16-byte aligned: histogram replicas); the first TH threads, whole waves,
+  // hold the bins, the others take part with empty bins
+  for (uint32_t i = t; i < nzero / 4; i += blockDim.x)
     reinterpret_cast<uint4*>(zero)[i] = make_uint4(0u, 0u, 0u, 0u);
+  const bool act = t < TH;
   uint32_t v[BPT];
   const uint4* src = reinterpret_cast<const uint4*>(bin_total) + (size_t)t * (BPT / 4);
 #pragma unroll
   for (int q = 0; q < BPT / 4; q++) {
-    const uint4 c = src[q];
+    const uint4 c = act ? src[q] : make_uint4(0u, 0u, 0u, 0u);
     v[4 * q] = c.x;
     v[4 * q + 1] = c.y;
     v[4 * q + 2] = c.z;
@@ -668,7 +672,7 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
   unsigned long long pre = before + x - s;
   uint4* dst = reinterpret_cast<uint4*>(bin_base) + (size_t)t * (BPT / 4);
 #pragma unroll
-  for (int q = 0; q < BPT / 4; q++) {
+  for (int q = 0; q < (act ? BPT / 4 : 0); q++) {
     uint4 o;
     o.x = (uint32_t)pre;
     pre += v[4 * q];
@@ -1578,7 +1582,8 @@ struct ScaleArgs {
   uint32_t* b_keep;
   void* uk;
   double2* uc;
-  double bnorm;
+  const double* norm2;  // ||O'_n||^2, written by the norm reduction
+  double floor_b;       // b_n at or below this is a breakdown: nothing survives
   int round32;
   int max_len;
   int use_eps;
@@ -1601,15 +1606,19 @@ __global__ __launch_bounds__(256) void k_scale_filter(ScaleArgs a) {
   const Key<W>* uk = reinterpret_cast<const Key<W>*>(a.uk) + ub;
   double2* uc = a.uc + ub;
   const Key<W>* keep = reinterpret_cast<const Key<W>*>(a.keep_mk);
+  // b_n = sqrt(||O'_n||^2), correctly rounded as on the host, which reads the
+  // same norm with the output size and reports the breakdown
+  const double bn = sqrt(*a.norm2);
+  const bool brk = !(bn > a.floor_b);
   uint32_t surv = 0, kc = 0;
   for (uint32_t i = tid; i < ns; i += 256) {
     double2 v = uc[i];
-    v = make_double2(v.x / a.bnorm, v.y / a.bnorm);
+    v = make_double2(v.x / bn, v.y / bn);
     // FP32 storage: a string whose stored value would be an exact zero is
     // dropped; every other decision (cutoff, top-M) is taken on the FP64
     // quotient, which the output write rounds to FP32
-    bool ok = a.round32 ? !is_zero(make_double2(round_to_f32(v.x), round_to_f32(v.y)))
-                        : !is_zero(v);
+    bool ok = !brk && (a.round32 ? !is_zero(make_double2(round_to_f32(v.x), round_to_f32(v.y)))
+                                 : !is_zero(v));
     const Key<W> mk = uk[i];
     if (ok && a.max_len > 0 && key_length<W>(unmix_key<W>(mk)) > a.max_len) ok = false;
     if (ok && a.use_eps && !(weight2(v) >= a.eps2)) ok = false;

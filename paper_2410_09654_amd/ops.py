@@ -40,10 +40,11 @@ class PauliOp:
         self.dtype = int(dtype)
         self.capacity = max(int(capacity), 1)
         W = _words(n_qubits)
-        self.x = torch.zeros((W, self.capacity), dtype=torch.int64, device=device)
-        self.z = torch.zeros((W, self.capacity), dtype=torch.int64, device=device)
+        # rows at and above `size` are never read: no fill kernels
+        self.x = torch.empty((W, self.capacity), dtype=torch.int64, device=device)
+        self.z = torch.empty((W, self.capacity), dtype=torch.int64, device=device)
         ft = torch.float64 if self.dtype == PAULI_C128 else torch.float32
-        self.coef = torch.zeros((self.capacity, 2), dtype=ft, device=device)
+        self.coef = torch.empty((self.capacity, 2), dtype=ft, device=device)
         self.size = 0
 
     @property

@@ -155,6 +155,52 @@ def test_workspace_query_is_sufficient(pk):
     assert _fits(pk, nbytes, lambda w: pk.commutator_ts1d(H0, Ots, ws=w))
 
 
+def test_small_call_planned_from_sizes(pk, ws):
+    """Calls of at most 2^18 possible records are planned from their sizes:
+    the host waits for the stream once per call (commutator, Lanczos step with
+    its b_n and breakdown test on the device).  A workspace that holds the
+    exact layout but not the layout at that bound makes the call read its
+    count first (two waits), with the same result bit for bit."""
+    import ctypes
+
+    import torch
+
+    from paper_2410_09654_amd import _lib, ops as pops
+    n = 64
+    H = uph(pk, wl.ising_chain(n))
+    O = pk.PauliOp.from_host(wl.random_local_strings(n, 1200, 10, seed=10))
+    assert H.size * O.size <= 1 << 18
+    want = pk.commutator(H, O, ws=ws)
+    assert pk.last_stats()["host_syncs"] == 1
+    O2 = pk.PauliOp.from_host(wl.random_local_strings(n, 900, 10, seed=11))
+    pk.lanczos_step(H, O2, O, 0.7, pk.Trunc(max_len=12, max_strings=5000), ws=ws)
+    assert pk.last_stats()["host_syncs"] == 1
+    # the workspace each failed call asks for, until the call runs
+    L = _lib.load()
+    nbytes, st = 1 << 20, None
+    for _ in range(8):
+        buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        wss = _lib.PauliWsC(buf.data_ptr(), nbytes, 0)
+        out = pk.PauliOp(n, H.size * O.size)
+        hs, os_, outs = H.c_struct(), O.c_struct(), out.c_struct()
+        st = L.pauli_commutator(ctypes.byref(hs), ctypes.byref(os_), None, ctypes.byref(outs),
+                                ctypes.byref(wss), pops._stream_handle())
+        torch.cuda.synchronize()
+        if st != _lib.PAULI_EWORKSPACE:
+            break
+        nbytes = int(wss.required)
+    assert st == _lib.PAULI_OK
+    assert pk.last_stats()["host_syncs"] == 2
+    nbound, _ = pk.workspace_query(pk.PAULI_Q_COMMUTATOR, H, O)
+    say(f"exact workspace {nbytes / 2**20:.1f} MiB, at the bound {nbound / 2**20:.1f} MiB")
+    assert nbytes < nbound
+    out.size = int(outs.size)
+    assert out.size == want.size
+    m = out.size
+    assert torch.equal(out.x[:, :m], want.x[:, :m]) and torch.equal(out.z[:, :m], want.z[:, :m])
+    assert torch.equal(out.coef[:m], want.coef[:m])
+
+
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_checkpoint_resume_is_exact(pk, ws, tmp_path, dtype):
     """Saving the Krylov vectors to .npz and resuming the recursion from them

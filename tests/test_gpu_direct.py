@@ -147,6 +147,8 @@ def test_crowded_hash_range_falls_back_to_emission(pk, ws):
         got = pk.truncate(pk.PauliOp.from_host(O, ws=ws), pk.Trunc(max_strings=M), ws=ws)
         assert_same_operator(got.to_host(), want, rtol=0.0, what=f"canonical M={M}")
         got = pk.truncate(shuffled(pk, O, M), pk.Trunc(max_strings=M), ws=ws)
+        # planned from its sizes, then redone with the count read first
+        assert pk.last_stats()["host_syncs"] >= 2
         assert_same_operator(got.to_host(), want, rtol=0.0, what=f"shuffled M={M}")
     # a list with repeats of the crowded strings, summed in input order
     rep = rng.integers(0, k, size=1500)
