@@ -839,8 +839,9 @@ int Engine::run(Call& c) {
           ma.defer = b1.defer;
           LAUNCH("k_merge_small", (k_merge<W, F32, MERGE_SMALL_THREADS, SCAP, MERGE_SMALL>),
                  nb_pass, MERGE_SMALL_THREADS, ma);
+          // deferrals are rare here: a few blocks loop over the list
           LAUNCH("k_merge_deferred", (k_merge<W, F32, MERGE_THREADS, merge_cap<W>(), MERGE_LIST>),
-                 std::min<uint32_t>(nb_pass, 512), MERGE_THREADS, ma);
+                 std::min<uint32_t>(nb_pass, 16), MERGE_THREADS, ma);
           nbk = nb_pass;
           continue;
         }
