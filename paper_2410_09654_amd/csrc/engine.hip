@@ -706,6 +706,15 @@ int Engine::run(Call& c) {
     // loop with one more pass bit
     // the count pass measured every bin exactly
     int pass_bits = nbl == NBINS_LOG_SMALL ? 0 : plan_pass_bits<W>(hctl->maxg[0], &nbl);
+    // Several passes bin each partition over 2^14 instead of 2^15 bins when
+    // the 2^14 bins are expected to stay within 0.8 of the merge's capacity
+    // (the merge then takes single bins where it would take pairs of 2^15
+    // bins): half the destinations and count rows for the pass binning, and
+    // its 64 KB bin table lets two blocks share a CU.
+    int pnbl = nbl;  // bins per pass of the merge (and of the pass binning)
+    if (!planned && nbl == NBINS_LOG_MP && pass_bits > 0 &&
+        (double)hctl->maxg[0] <= std::ldexp(0.8 * merge_cap<W>(), pass_bits))
+      pnbl = NBINS_LOG;
     const int table_bits = std::min(pass_bits + 2, MAX_PASS_BITS);
     const size_t ptot = (size_t)std::max<unsigned long long>(pe_all, 1);
     const uint32_t max_buckets = (uint32_t)(1u << nbl) << table_bits;
@@ -766,7 +775,7 @@ int Engine::run(Call& c) {
         ea.recs = precs;
         ea.ptop = ptop;
         ea.psrc = psrc;
-        ea.part_F = NBINS_LOG_MP + pass_bits;
+        ea.part_F = pnbl + pass_bits;
         ea.bin_base = pbase;
         if (first_counts && pass_bits <= 10) {
           // partition prefixes summed from the first count pass's bins, kept
@@ -805,11 +814,19 @@ int Engine::run(Call& c) {
           sp.part = (uint32_t)p;
           uint32_t* zero = p == 0 ? hist0 : (uint32_t*)nullptr;
           const uint32_t nzero = p == 0 ? (uint32_t)(HREP * SEL0_BINS) : 0u;
-          LAUNCH("k_split_count", (k_split<W, F32, false, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
-          LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, scounts, SPLIT_ROWS, bin_total,
-                 dctl, NBINS_MP);
-          LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl, zero,
-                 nzero);
+          if (pnbl == NBINS_LOG) {
+            LAUNCH("k_split_count", (k_split<W, F32, false, NBINS_LOG>), SPLIT_ROWS, 1024, sp);
+            LAUNCH("k_scan_cols", k_scan_cols, NBINS / SC_COLS, SC_COLS * SC_NSEG, scounts,
+                   SPLIT_ROWS, bin_total, dctl, NBINS);
+            LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG>, 1, 1024, bin_total, bin_base, dctl, zero,
+                   nzero);
+          } else {
+            LAUNCH("k_split_count", (k_split<W, F32, false, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
+            LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, scounts,
+                   SPLIT_ROWS, bin_total, dctl, NBINS_MP);
+            LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_MP>, 1, 1024, bin_total, bin_base, dctl,
+                   zero, nzero);
+          }
           TRY(read_ctl());
         } else if (nbl == NBINS_LOG_MP) {
           // one pass at NBINS_LOG_MP bins: count again at that bin count; this
@@ -870,7 +887,9 @@ int Engine::run(Call& c) {
         int g_log = 4;
         while (g_log > 0 && hctl->maxg[g_log] > (unsigned int)merge_cap<W>()) g_log--;
         if (pe == 0) continue;
-        if (pass_bits > 0)
+        if (pass_bits > 0 && pnbl == NBINS_LOG)
+          LAUNCH("k_split_scatter", (k_split<W, F32, true, NBINS_LOG>), SPLIT_ROWS, 1024, sp);
+        else if (pass_bits > 0)
           LAUNCH("k_split_scatter", (k_split<W, F32, true, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
         else if (nbl == NBINS_LOG_SMALL)
           LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG_SMALL>), rows, EMIT_THREADS, ea);
@@ -879,13 +898,13 @@ int Engine::run(Call& c) {
         else
           LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);
         ma.g_log = g_log;
-        ma.nbins_log = nbl;
-        ma.digit_shift = pass_bits + nbl - g_log;
+        ma.nbins_log = pnbl;
+        ma.digit_shift = pass_bits + pnbl - g_log;
         ma.pass_bits = pass_bits;
         ma.pass_id = (uint32_t)p;
         ma.u_off = u_off;
         ma.bucket_off = nbk;
-        const uint32_t nb_pass = (uint32_t)((1u << nbl) >> g_log);
+        const uint32_t nb_pass = (uint32_t)((1u << pnbl) >> g_log);
         // Buckets up to the small variant's capacity run three to a CU: all
         // of them when the largest bucket fits; when most do, the full-size
         // merge takes the others from a deferral list; else the full-size merge
