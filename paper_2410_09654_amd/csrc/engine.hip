@@ -638,9 +638,14 @@ int Engine::run(Call& c) {
       if (nbl == NBINS_LOG_SMALL) {
         constexpr int NBS = 1 << NBINS_LOG_SMALL;
         LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG_SMALL>), rows, EMIT_THREADS, ea);
-        LAUNCH("k_scan_cols", k_scan_cols, NBS / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl, NBS);
-        LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_SMALL>, 1, 1024,
-               bin_total, bin_base, dctl, zero, nzero);
+        if (rows <= SMALL_SCAN_ROWS) {
+          LAUNCH("k_scan_small", k_scan_small, 1, 1024, counts, rows, bin_base, dctl, zero, nzero);
+        } else {
+          LAUNCH("k_scan_cols", k_scan_cols, NBS / SC_COLS, SC_COLS * SC_NSEG, counts, rows,
+                 bin_total, dctl, NBS);
+          LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG_SMALL>, 1, 1024, bin_total, bin_base, dctl,
+                 zero, nzero);
+        }
       } else if (nbl == NBINS_LOG) {
         LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG>), rows, EMIT_THREADS, ea);
         LAUNCH("k_scan_cols", k_scan_cols, NBINS / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl, NBINS);

@@ -606,6 +606,56 @@ __global__ __launch_bounds__(SC_COLS * SC_NSEG) void k_scan_cols(uint32_t* count
   }
 }
 
+// Both scans of a count pass over 2^10 bins with at most SMALL_SCAN_ROWS
+// emission rows, in one block: thread t turns column t of the count matrix
+// into row prefixes (as k_scan_cols), then the block scans the 1024 bin
+// totals into bin bases, takes the largest totals over aligned groups of
+// 1, 2, 4, 8, 16 bins and clears `zero` (as k_scan_bins).  Such calls hold at
+// most 2^18 records, so no total overflows 32 bits.
+constexpr int SMALL_SCAN_ROWS = 32;
+__global__ __launch_bounds__(1024) void k_scan_small(uint32_t* counts, int rows,
+                                                     uint32_t* bin_base, Ctl* ctl, uint32_t* zero,
+                                                     uint32_t nzero) {
+  constexpr int NB = 1 << NBINS_LOG_SMALL;
+  static_assert(NB == 1024, "one thread per bin");
+  __shared__ uint32_t scan_tmp[1024 / 64 + 1];
+  __shared__ uint32_t tot[NB];
+  __shared__ unsigned int gmax[5];
+  const int t = threadIdx.x;
+  for (uint32_t i = t; i < nzero / 4; i += 1024)
+    reinterpret_cast<uint4*>(zero)[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (t < 5) gmax[t] = 0u;
+  uint32_t c[SMALL_SCAN_ROWS];
+#pragma unroll
+  for (int r = 0; r < SMALL_SCAN_ROWS; r++) c[r] = r < rows ? counts[(size_t)r * NB + t] : 0u;
+  uint32_t run = 0;
+#pragma unroll
+  for (int r = 0; r < SMALL_SCAN_ROWS; r++) {
+    if (r < rows) counts[(size_t)r * NB + t] = run;
+    run += c[r];
+  }
+  tot[t] = run;
+  uint32_t total;
+  const uint32_t pre = block_exclusive_scan(run, scan_tmp, &total);  // barriers: tot, gmax set
+  bin_base[t] = pre;
+  if (t == 0) bin_base[NB] = total;
+#pragma unroll
+  for (int lg = 0; lg < 5; lg++) {
+    const int g = 1 << lg;
+    if ((t & (g - 1)) == 0) {
+      uint32_t m = 0;
+      for (int q = 0; q < g; q++) m += tot[t + q];
+      atomicMax(&gmax[lg], m);
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    ctl->pe_total = total;
+    ctl->ndefer = 0u;
+    for (int lg = 0; lg < 5; lg++) ctl->maxg[lg] = gmax[lg];
+  }
+}
+
 // Exclusive scan of the bin totals (one block of 1024 threads, of which the
 // first scan_bins_threads<NBL>() hold the bins: thread t owns the BPT >= 16
 // consecutive bins from t BPT, read and written as 16-byte vectors) and the
