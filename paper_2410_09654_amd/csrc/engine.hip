@@ -120,6 +120,9 @@ inline int words_of(int n_qubits) { return (n_qubits + 63) / 64; }
 
 // pinned host copy of the control block (one per thread)
 thread_local Ctl* t_hctl = nullptr;
+thread_local hipEvent_t t_ctl_event = nullptr, t_scan_event = nullptr;
+thread_local hipStream_t t_side_stream = nullptr;  // on device t_side_dev
+thread_local int t_side_dev = -1;
 int host_ctl(Ctl** out) {
   if (!t_hctl) HIP_TRY(hipHostMalloc((void**)&t_hctl, sizeof(Ctl), hipHostMallocDefault));
   *out = t_hctl;
@@ -364,6 +367,11 @@ struct Engine {
   hipStream_t stream;
   Ctl* dctl = nullptr;
   Ctl* hctl = nullptr;
+  // the count's copy to the host beside the scatter (pinned control block only):
+  // recorded after the scan on the call's stream, then on a side stream
+  // after the copy
+  hipEvent_t ctl_event = nullptr, scan_event = nullptr;
+  hipStream_t side_stream = nullptr;
   bool run_emit = false;  // take the emission path even for canonical terms
   bool run_counted = false;  // read the count before planning, even for small calls
 
@@ -500,6 +508,7 @@ int Engine::run(Call& c) {
   // crowd one bucket beyond the merge's capacity.
   unsigned long long pe_all = 0;
   bool planned = false;  // one pass planned from the sizes alone (no count read)
+  bool scattered = false;  // one pass over 2^14 bins scattered before the count was read
   const bool want_select = tr && tr->max_strings > 0;
   Bufs2 b2;
   MergeArgs ma;
@@ -629,7 +638,8 @@ int Engine::run(Call& c) {
         (comm ? (unsigned long long)c.H.n * (unsigned long long)c.O.n : 0ull) +
         (unsigned long long)nterm_rec;
     if (rec_bound <= (1ull << (NBINS_LOG_SMALL + 8))) nbl = NBINS_LOG_SMALL;
-    auto count_pass = [&](int pass_bits, uint32_t pass_id, bool read = true) -> int {
+    auto count_pass = [&](int pass_bits, uint32_t pass_id, bool read = true,
+                          unsigned long long spec_cap = 0ull) -> int {
       ea.pass_bits = pass_bits;
       ea.pass_id = pass_id;
       // the first count pass of a merge sequence also clears the level-0 |c|^2 histogram
@@ -650,7 +660,7 @@ int Engine::run(Call& c) {
         LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG>), rows, EMIT_THREADS, ea);
         LAUNCH("k_scan_cols", k_scan_cols, NBINS / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl, NBINS);
         LAUNCH("k_scan_bins", k_scan_bins<NBINS_LOG>, 1, 1024, bin_total, bin_base, dctl, zero,
-               nzero);
+               nzero, spec_cap, (unsigned int)merge_cap<W>());
       } else {
         LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG_MP>), rows, EMIT_THREADS, ea);
         LAUNCH("k_scan_cols", k_scan_cols, NBINS_MP / SC_COLS, SC_COLS * SC_NSEG, counts, rows, bin_total, dctl,
@@ -691,6 +701,56 @@ int Engine::run(Call& c) {
       } else {
         planned = true;
       }
+    } else if (nbl == NBINS_LOG && ctl_event &&
+               rec_bound <= 7ull * (1ull << NBINS_LOG) * (unsigned long long)merge_cap<W>()) {
+      // A call that may fit one pass over 2^14 bins (at most seven passes'
+      // worth of possible records) is laid out for as many records as the
+      // workspace holds beside the rest of that pass; the count's control
+      // block goes to the host behind an event and the scatter is launched
+      // at once, so the GPU does not wait for the host's plan.  The bin scan
+      // makes the scatter stand down when the records do not fit the layout
+      // or a bin exceeds the merge capacity; the host then plans from the
+      // count it has read, as below.
+      const bool w14 = wide_for(NBINS_LOG);
+      const uint32_t mb = (1u << NBINS_LOG) << 2;
+      const size_t per = RB + KB + sizeof(double2) + (w14 ? 4 : 0) + (want_select ? 12 : 0) +
+                         (c.out.to_arena ? (size_t)(16 * W + 16) : 0);
+      const size_t fixed = (size_t)mb * (9 * 4 + sizeof(double2) + (want_select ? 12 : 0)) +
+                           ((size_t)64 << 10);
+      const size_t used = align256(ar->bottom) + ar->top;
+      const size_t avail = ar->cap > used + fixed ? ar->cap - used - fixed : 0;
+      const unsigned long long cap_rec =
+          std::min<unsigned long long>(rec_bound, (unsigned long long)(avail / per));
+      const size_t mark_bottom = ar->bottom, mark_need = ar->need;
+      if (cap_rec >= (1ull << 16))
+        take_bufs2<W, F32>(*ar, (size_t)cap_rec, w14, false, mb, want_select, b2);
+      if (cap_rec < (1ull << 16) || ar->short_) {
+        ar->bottom = mark_bottom;
+        ar->need = mark_need;
+        ar->short_ = false;
+        TRY(count_pass(0, 0));
+      } else {
+        TRY(count_pass(0, 0, false, cap_rec));
+        // the copy runs on a side stream once the scan is done, beside the scatter
+        HIP_TRY(hipEventRecord(scan_event, stream));
+        HIP_TRY(hipStreamWaitEvent(side_stream, scan_event, 0));
+        HIP_TRY(hipMemcpyAsync(hctl, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, side_stream));
+        HIP_TRY(hipEventRecord(ctl_event, side_stream));
+        ea.recs = b2.recs;
+        ea.rsrc_wide = b2.rsrc_wide;
+        ea.wide = w14 ? 1 : 0;
+        ea.skip = &dctl->spec_fail;
+        LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG>), rows, EMIT_THREADS, ea);
+        ea.skip = nullptr;
+        g_stats.host_syncs++;
+        HIP_TRY(hipEventSynchronize(ctl_event));
+        if (!hctl->spec_fail) {
+          scattered = true;  // the pass stands: layout and records are in place
+        } else {
+          ar->bottom = mark_bottom;
+          ar->need = mark_need;
+        }
+      }
     } else {
       TRY(count_pass(0, 0));
     }
@@ -726,7 +786,7 @@ int Engine::run(Call& c) {
     // ----- records, U, bucket tables, candidate lists -------------------------
     const bool wide = wide_for(nbl);
     const bool partitioned = nbl == NBINS_LOG_MP;
-    if (!planned) {
+    if (!planned && !scattered) {
       take_bufs2<W, F32>(*ar, ptot, wide, partitioned, max_buckets, want_select, b2);
       if (ar->short_) return PAULI_EWORKSPACE;
     }
@@ -896,6 +956,8 @@ int Engine::run(Call& c) {
           LAUNCH("k_split_scatter", (k_split<W, F32, true, NBINS_LOG>), SPLIT_ROWS, 1024, sp);
         else if (pass_bits > 0)
           LAUNCH("k_split_scatter", (k_split<W, F32, true, NBINS_LOG_MP>), SPLIT_ROWS, 1024, sp);
+        else if (scattered)
+          ;  // launched before the count was read
         else if (nbl == NBINS_LOG_SMALL)
           LAUNCH("k_emit_scatter", (k_emit<W, F32, true, NBINS_LOG_SMALL>), rows, EMIT_THREADS, ea);
         else if (nbl == NBINS_LOG)
@@ -1261,6 +1323,22 @@ int run_call(Arena& ar, pauli_ws* ws, void* stream, Call& c, Ctl* hctl = nullptr
   e.ar = &ar;
   e.stream = (hipStream_t)stream;
   e.hctl = hctl;
+  // the overlapped count read needs the pinned control block, two events and
+  // a side stream (created once per thread, default priority); callers that
+  // bring their own block get none of them
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (!hctl && (!t_side_stream || t_side_dev == dev)) {
+    if (!t_side_stream) {
+      HIP_TRY(hipEventCreateWithFlags(&t_ctl_event, hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&t_scan_event, hipEventDisableTiming));
+      HIP_TRY(hipStreamCreateWithFlags(&t_side_stream, hipStreamNonBlocking));
+      t_side_dev = dev;
+    }
+    e.ctl_event = t_ctl_event;
+    e.scan_event = t_scan_event;
+    e.side_stream = t_side_stream;
+  }
   int rc = dispatch(e, c);
   if (rc == PAULI_EWORKSPACE || ar.short_) return ws_short(ar, ws);
   if (rc == PAULI_OK || rc == PAULI_BREAKDOWN) {

@@ -58,6 +58,7 @@ struct Ctl {
   unsigned long long part_total; // records in all partitions (several-pass calls)
   unsigned int ndefer;           // buckets deferred to the full-size merge (this pass)
   unsigned int unsorted;         // a term of a direct merge is not in canonical order
+  unsigned int spec_fail;        // a scatter launched before the count was read stands down
 };
 
 struct EmitArgs {
@@ -113,6 +114,7 @@ struct EmitArgs {
   void* recs;          // Rec<W, F32>[records]
   uint32_t* rsrc_wide; // source ids when they do not fit the folded bits
   int wide;
+  const unsigned int* skip;  // scatter: nothing to do when *skip != 0 (nullable)
 };
 
 template <bool F32>
@@ -176,6 +178,7 @@ __attribute__((amdgpu_waves_per_eu(W == 1 && NBL <= 14 ? 8 : 4))) void k_emit(Em
   const int lane = tid & 63, wv = tid >> 6;
   const int row = blockIdx.x;
   const uint32_t lrow = layout_row(blockIdx.x, gridDim.x);
+  if (SCATTER && a.skip && *a.skip) return;
   if (SCATTER) {
     const uint32_t* crow = a.counts + (size_t)lrow * NB;
     for (int i = tid; i < NB; i += EMIT_THREADS) hist[i] = a.bin_base[i] + crow[i];
@@ -666,7 +669,9 @@ template <int NBL>
 constexpr int scan_bins_threads() { return (1 << NBL) / 16 < 1024 ? (1 << NBL) / 16 : 1024; }
 template <int NBL>
 __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, uint32_t* bin_base,
-                                                    Ctl* ctl, uint32_t* zero, uint32_t nzero) {
+                                                    Ctl* ctl, uint32_t* zero, uint32_t nzero,
+                                                    unsigned long long spec_cap = 0ull,
+                                                    unsigned int merge_cap = 0u) {
   constexpr int NB = 1 << NBL;
   constexpr int TH = scan_bins_threads<NBL>();
   constexpr int NWV = TH / 64;
@@ -761,6 +766,9 @@ __global__ __launch_bounds__(1024) void k_scan_bins(const uint32_t* bin_total, u
       for (int q = 0; q < NWV; q++) m = gmax[q][lg] > m ? gmax[q][lg] : m;
       ctl->maxg[lg] = m;
     }
+    // a scatter already launched for a single pass laid out for spec_cap
+    // records stands down unless the records fit and every bin fits a bucket
+    if (spec_cap) ctl->spec_fail = (total > spec_cap || ctl->maxg[0] > merge_cap) ? 1u : 0u;
   }
 }
 

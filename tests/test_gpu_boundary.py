@@ -201,6 +201,30 @@ def test_small_call_planned_from_sizes(pk, ws):
     assert torch.equal(out.coef[:m], want.coef[:m])
 
 
+def test_keep_set_out_of_order_is_refused(pk, ws):
+    """A keep set that is not in canonical order is refused with PAULI_EINVAL:
+    by a small call planned from its sizes (checked with the output size), a
+    call that reads its count first, a direct truncation and a Lanczos step;
+    the same strings in canonical order are accepted."""
+    from paper_2410_09654_amd import _lib
+    n = 64
+    H = uph(pk, wl.ising_chain(n))
+    good = pk.PauliOp.from_host(wl.random_local_strings(n, 3, 4, seed=1), ws=ws)
+    assert good.size == 3
+    gx, gz, gc = good.to_numpy()  # the library's canonical order, then reversed
+    bad = pk.PauliOp.from_raw(n, gx[::-1], gz[::-1], gc[::-1])
+    for count in (500, 20000):
+        say(f"keep out of order, |O| = {count}")
+        O = pk.PauliOp.from_host(wl.random_local_strings(n, count, 10, seed=count), ws=ws)
+        calls = [lambda T: pk.commutator(H, O, T, ws=ws), lambda T: pk.truncate(O, T, ws=ws),
+                 lambda T: pk.lanczos_step(H, None, O, 0.0, T, ws=ws)]
+        for fn in calls:
+            with pytest.raises(pk.PauliError) as e:
+                fn(pk.Trunc(max_strings=100, keep=bad))
+            assert e.value.status == _lib.PAULI_EINVAL
+            fn(pk.Trunc(max_strings=100, keep=good))
+
+
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_checkpoint_resume_is_exact(pk, ws, tmp_path, dtype):
     """Saving the Krylov vectors to .npz and resuming the recursion from them
