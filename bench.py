@@ -627,7 +627,9 @@ def main():
     H_host, O_host = wl.config_commutator_bench(args.count)
     max_len, max_strings = 12, args.count
     H = pk.PauliOp.from_raw(64, H_host.x, H_host.z, H_host.coef)
-    ws = pk.Workspace(1 << 30)
+    # room for the records of one pass from the first call on (a smaller
+    # workspace makes the first call grow it and lay the pass out again)
+    ws = pk.Workspace(4 << 30)
     O = pk.PauliOp.from_host(O_host, ws=ws)
     trunc = pk.Trunc(max_len=max_len, max_strings=max_strings)
     out = pk.PauliOp(64, max_strings + 16)
