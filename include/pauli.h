@@ -14,8 +14,11 @@
  *     keeps no pointer to caller memory after a call returns.  State kept
  *     between calls: a pinned host control block (under 1 KiB) per calling thread
  *     (allocated with hipHostMalloc on the thread's first call, kept until the
- *     process ends), the per-thread diagnostics below and the optional
- *     kernel-timing log (pauli_profile_*).
+ *     process ends), two events and a side stream of default priority per
+ *     calling thread (created on its first call, on the device then current;
+ *     the control block is copied to the host on the side stream while the
+ *     call's own stream goes on), the per-thread diagnostics below and the
+ *     optional kernel-timing log (pauli_profile_*).
  *   - x and z are word-major: word w of string k is x[w * capacity + k].
  *     coef holds `capacity` interleaved (re, im) pairs: double for
  *     PAULI_C128, float for PAULI_C64K.
