@@ -117,37 +117,44 @@ def test_rk4_final_sum_of_five_terms(pk, ws):
     assert_same_operator(got.to_host(), want, what="rk4 step")
 
 
-def test_crowded_hash_range_falls_back_to_emission(pk, ws):
-    """3000 strings whose order keys share their top 10 bits on a background
-    of 20000 ordinary ones: the direct merge's bucket overflows and the call is
-    redone by emission, where the 2^10-bin count of a small call overflows too
-    and is redone over 2^14 bins.  Truncation (canonical and shuffled input)
-    and canonicalisation of a list with repeats, against the oracle."""
+@pytest.mark.parametrize("prefix_bits,background", [(10, 20_000), (14, 300_000)])
+def test_crowded_hash_range_falls_back_to_emission(pk, ws, prefix_bits, background):
+    """3000 strings whose order keys share their top bits on a background of
+    ordinary ones: the direct merge's bucket overflows and the call is redone
+    by emission.  With 10 shared bits and 20000 others (a small call planned
+    from its sizes) the 2^10-bin count overflows too and the call is redone
+    with the count read first, over 2^14 bins; with 14 shared bits and 300000
+    others the scatter launched beside the count read stands down (a 2^14 bin
+    above the merge capacity) and the host plans passes over 2^15 bins.
+    Truncation (canonical and shuffled input) and canonicalisation of a list
+    with repeats, against the oracle."""
     import torch
-    say("crowded hash range")
+    say(f"crowded hash range: {prefix_bits} shared bits, {background} others")
     n, k = 64, 3000
     rng = np.random.default_rng(99)
     w = rng.integers(0, 2**63, size=(k, 2), dtype=np.uint64) * np.uint64(2) + \
         rng.integers(0, 2, size=(k, 2), dtype=np.uint64)
-    w[:, 0] = (np.uint64(0x2A7) << np.uint64(54)) | (w[:, 0] >> np.uint64(10))
+    prefix = {10: 0x2A7, 14: 0x29C3}[prefix_bits]
+    w[:, 0] = (np.uint64(prefix) << np.uint64(64 - prefix_bits)) | \
+        (w[:, 0] >> np.uint64(prefix_bits))
     keys = torch.from_numpy(w.view(np.int64)).cuda()
     cx, cz = pk.strings_from_order_keys(n, keys)
     cx = cx.cpu().numpy().view(np.uint64).T.copy()
     cz = cz.cpu().numpy().view(np.uint64).T.copy()
-    bg = random_words_op(n, 20_000, seed=5)
+    bg = random_words_op(n, background, seed=5)
     x = np.concatenate([cx, bg.x])
     z = np.concatenate([cz, bg.z])
     _, first = np.unique(np.concatenate([x, z], 1), axis=0, return_index=True)
     first = np.sort(first)
     c = rng.standard_normal(len(x)) + 1j * rng.standard_normal(len(x))
     O = wl.HostOp(n, x[first], z[first], c[first])
-    assert O.n > 22_000
+    assert O.n > background + 2000
     for M in (0, 5000):
         want = oracle.truncate(O, oracle.Trunc(max_strings=M))
         got = pk.truncate(pk.PauliOp.from_host(O, ws=ws), pk.Trunc(max_strings=M), ws=ws)
         assert_same_operator(got.to_host(), want, rtol=0.0, what=f"canonical M={M}")
         got = pk.truncate(shuffled(pk, O, M), pk.Trunc(max_strings=M), ws=ws)
-        # planned from its sizes, then redone with the count read first
+        # the count was read before the records that went to a bucket
         assert pk.last_stats()["host_syncs"] >= 2
         assert_same_operator(got.to_host(), want, rtol=0.0, what=f"shuffled M={M}")
     # a list with repeats of the crowded strings, summed in input order
