@@ -649,7 +649,8 @@ int Engine::run(Call& c) {
         constexpr int NBS = 1 << NBINS_LOG_SMALL;
         LAUNCH("k_emit_count", (k_emit<W, F32, false, NBINS_LOG_SMALL>), rows, EMIT_THREADS, ea);
         if (rows <= SMALL_SCAN_ROWS) {
-          LAUNCH("k_scan_small", k_scan_small, 1, 1024, counts, rows, bin_base, dctl, zero, nzero);
+          LAUNCH("k_scan_small", k_scan_small, HREP, 1024, counts, rows, bin_base, dctl, zero,
+                 nzero);
         } else {
           LAUNCH("k_scan_cols", k_scan_cols, NBS / SC_COLS, SC_COLS * SC_NSEG, counts, rows,
                  bin_total, dctl, NBS);

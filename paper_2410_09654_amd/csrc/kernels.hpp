@@ -610,11 +610,12 @@ __global__ __launch_bounds__(SC_COLS * SC_NSEG) void k_scan_cols(uint32_t* count
 }
 
 // Both scans of a count pass over 2^10 bins with at most SMALL_SCAN_ROWS
-// emission rows, in one block: thread t turns column t of the count matrix
+// emission rows, in block 0: thread t turns column t of the count matrix
 // into row prefixes (as k_scan_cols), then the block scans the 1024 bin
-// totals into bin bases, takes the largest totals over aligned groups of
-// 1, 2, 4, 8, 16 bins and clears `zero` (as k_scan_bins).  Such calls hold at
-// most 2^18 records, so no total overflows 32 bits.
+// totals into bin bases and takes the largest totals over aligned groups of
+// 1, 2, 4, 8, 16 bins (as k_scan_bins).  All blocks of the grid clear a share
+// of `zero`.  Such calls hold at most 2^18 records, so no total overflows 32
+// bits.
 constexpr int SMALL_SCAN_ROWS = 32;
 __global__ __launch_bounds__(1024) void k_scan_small(uint32_t* counts, int rows,
                                                      uint32_t* bin_base, Ctl* ctl, uint32_t* zero,
@@ -625,8 +626,14 @@ __global__ __launch_bounds__(1024) void k_scan_small(uint32_t* counts, int rows,
   __shared__ uint32_t tot[NB];
   __shared__ unsigned int gmax[5];
   const int t = threadIdx.x;
-  for (uint32_t i = t; i < nzero / 4; i += 1024)
-    reinterpret_cast<uint4*>(zero)[i] = make_uint4(0u, 0u, 0u, 0u);
+  // every block clears its share of `zero`; block 0 also scans
+  {
+    const uint32_t nv = nzero / 4, per = (nv + gridDim.x - 1) / gridDim.x;
+    const uint32_t z0 = blockIdx.x * per, z1 = min(nv, z0 + per);
+    for (uint32_t i = z0 + t; i < z1; i += 1024)
+      reinterpret_cast<uint4*>(zero)[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  if (blockIdx.x != 0) return;
   if (t < 5) gmax[t] = 0u;
   uint32_t c[SMALL_SCAN_ROWS];
 #pragma unroll
