@@ -454,7 +454,9 @@ __global__ __launch_bounds__(1024) void k_split(SplitArgs a) {
   constexpr int NB = 1 << NBL;
   __shared__ uint32_t hist[NB];
   const int tid = threadIdx.x;
-  const uint32_t* crow = a.counts + (size_t)blockIdx.x * NB;
+  // count-matrix row of this block: rows grouped by XCD, as in the emission
+  const uint32_t lrow = layout_row(blockIdx.x, gridDim.x);
+  const uint32_t* crow = a.counts + (size_t)lrow * NB;
   if (SCATTER)
     for (int i = tid; i < NB; i += 1024) hist[i] = a.bin_base[i] + crow[i];
   else
@@ -502,7 +504,7 @@ __global__ __launch_bounds__(1024) void k_split(SplitArgs a) {
   }
   if (!SCATTER) {
     __syncthreads();
-    uint32_t* w = a.counts + (size_t)blockIdx.x * NB;
+    uint32_t* w = a.counts + (size_t)lrow * NB;
     for (int i = tid; i < NB; i += 1024) w[i] = hist[i];
   }
 }
